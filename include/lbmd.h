@@ -1,0 +1,177 @@
+/*
+ * lbmd.h -- C ABI of the MI355X fluctuating lattice-Boltzmann / MD
+ * dissipative-coupling library (Tretyakov & Duenweg, arXiv:1610.02733).
+ *
+ * Units are lattice units: lattice spacing a = 1, LB time step tau_LB = 1,
+ * MD time step tau_MD = 1/n_sub (Sec. 3: the time-scale contrast
+ * m = tau_LB/tau_MD must be an integer).
+ *
+ * Memory and ownership.  Every device buffer is allocated by the caller
+ * (for instance as a torch tensor) and only borrowed by the library: the
+ * workspace of lbmd_workspace_bytes() bytes that lb_create() carves into the
+ * two population buffers, the momentum-transfer field and particle scratch,
+ * and the particle arrays handed to lbmd_bind_particles().  The library never
+ * allocates or frees device memory.  Buffers must stay alive until
+ * lb_destroy().  All floating-point device arrays use the context precision
+ * (float for precision 32, double for precision 64).
+ *
+ * Streams.  A context is bound to one HIP stream.  Every call is an
+ * asynchronous enqueue on it, except lb_moments() with a host totals pointer
+ * and the host-side parameter checks.  Calls on one context must not overlap
+ * from several host threads.
+ *
+ * Errors.  Every call returns LBMD_OK or a negative code.  LBMD_EHIP is
+ * sticky: after a HIP failure the context refuses further work.
+ * lbmd_strerror() gives a message.
+ */
+#ifndef LBMD_H
+#define LBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbmd lbmd; /* opaque context */
+
+enum {
+  LBMD_OK = 0,
+  LBMD_EINVAL = -1,     /* bad parameter or argument                          */
+  LBMD_ESTATE = -2,     /* call out of order (e.g. lb_step after != n MD steps)*/
+  LBMD_EHIP = -3,       /* HIP runtime failure (sticky)                       */
+  LBMD_ENOSPACE = -4,   /* workspace smaller than lbmd_workspace_bytes()      */
+  LBMD_ENONFINITE = -5  /* a particle coordinate or velocity became NaN/Inf  */
+};
+
+/* Layout of the totals returned by lb_moments(). */
+enum {
+  LBMD_TOT_MASS = 0,     /* sum_r rho(r)                                      */
+  LBMD_TOT_PFLUID = 1,   /* [3] sum_r j(r) + sum_r J(r)                       */
+  LBMD_TOT_PSEEN = 4,    /* [3] momentum the coupling sees: variant 1 sum j,
+                            variant 2 sum j + sum J                           */
+  LBMD_TOT_PPART = 7,    /* [3] sum_p m v_p                                   */
+  LBMD_TOT_KEPART = 10,  /* sum_p m |v_p|^2 / 2                               */
+  LBMD_TOT_U2FLUID = 11, /* mean over sites of |j/rho|^2                      */
+  LBMD_TOT_TLB = 12,     /* LB steps done                                     */
+  LBMD_TOT_TMD = 13,     /* MD steps done                                     */
+  LBMD_NTOTALS = 14
+};
+
+/*
+ * Parameters: the paper's statement of the problem (Sec. 2-3): lattice size,
+ * n = tau_LB/tau_MD, viscosity, friction (the paper's zeta, Eq. 4), kT and
+ * the coupling variant (1 = variant A, 2 = variant B).
+ */
+typedef struct {
+  int32_t nx, ny, nz;     /* sites per axis, periodic, each >= 2               */
+  int32_t n_sub;          /* n = tau_LB / tau_MD, integer >= 1 (Sec. 3)        */
+  int32_t variant;        /* 1: fluid velocity frozen over the LB interval;
+                             2: the sites around each particle see its momentum
+                             transfer at the next MD step (Sec. 3)             */
+  int32_t precision;      /* 32: float populations stored as deviations from
+                             w_i rho0; 64: double (also deviations)            */
+  int32_t n_particles;    /* N >= 0                                            */
+  int32_t force_model;    /* 0 none; 1 constant force f_ext on every particle;
+                             2 harmonic bonds within chains + WCA (all pairs)  */
+  int32_t chain_len;      /* beads per chain for force_model 2 (N % chain_len
+                             == 0; bead b is bonded to b+1 inside a chain)     */
+  uint32_t replica;       /* replica id entering the noise counter             */
+  uint64_t seed;          /* Philox key                                        */
+  double rho0;            /* mean fluid mass density, > 0                      */
+  double nu;              /* kinematic shear viscosity, > 0                     */
+  double nu_bulk;         /* bulk viscosity; < 0 means "same rate as shear"    */
+  double gamma_ghost;     /* relaxation factor of the kinetic modes, |g| < 1   */
+  double kT;              /* >= 0; 0 switches all noise off                    */
+  double friction;        /* gamma (the paper's zeta), >= 0                    */
+  double particle_mass;   /* > 0 when N > 0                                    */
+  double body_force[3];   /* uniform force density on the fluid                */
+  double f_ext[3];        /* force_model 1                                     */
+  double k_bond, r0_bond; /* force_model 2: U = k/2 (r - r0)^2                 */
+  double wca_eps, wca_sigma; /* force_model 2: WCA cut at 2^(1/6) sigma        */
+} lbmd_params;
+
+/* Device bytes lb_create() needs for these parameters (0 if invalid). */
+size_t lbmd_workspace_bytes(const lbmd_params *p);
+
+/*
+ * Create a context.  d_ws: caller-owned device buffer of ws_bytes bytes,
+ * 256-byte aligned.  hip_stream: a hipStream_t (NULL = default stream).
+ * Initial fluid: at rest, f_i = w_i rho0 (Sec. 2 populations); no momentum
+ * transfer pending; step counters zero.  Returns LBMD_EINVAL for invalid
+ * parameters, LBMD_ENOSPACE for a short workspace.
+ */
+int lb_create(const lbmd_params *p, void *d_ws, size_t ws_bytes, void *hip_stream,
+              lbmd **out);
+
+/* Destroy the context (host memory only; caller buffers are untouched). */
+int lb_destroy(lbmd *c);
+
+/*
+ * Bind the caller's particle arrays (device, SoA [3][N]: x, then y, then z
+ * rows).  d_x: positions in [0, L) per axis; d_v: velocities; d_img: int32
+ * periodic image counters (unwrapped position = x + L * img).  The library
+ * updates them in place at every md_couple_substep().  Computes the
+ * conservative forces at the bound positions.
+ */
+int lbmd_bind_particles(lbmd *c, void *d_x, void *d_v, int32_t *d_img);
+
+/*
+ * One MD step of the coupled system (Sec. 3, Eq. 4-8): for every particle,
+ * from start-of-step values, interpolate the fluid velocity at its position
+ * over the 8 sites of its cube (Eq. 5), form F = -gamma (v - u) + F_rand
+ * (Eq. 4), dP = tau_MD F (Eq. 6), transfer -delta_k dP to the 8 sites
+ * (Eq. 7-8) and advance the particle by velocity Verlet.  In variant 2 the
+ * transfer is seen by the velocity interpolation of the next MD step; in
+ * variant 1 only by the next lb_step().  At most n_sub calls per LB interval
+ * (LBMD_ESTATE otherwise).
+ */
+int md_couple_substep(lbmd *c);
+
+/*
+ * One LB step (Eq. 3): MRT collision with the force density J/tau_LB of the
+ * accumulated momentum transfer (Guo forcing) plus body_force, thermal noise
+ * on the 15 non-conserved modes, then streaming.  Requires exactly n_sub
+ * md_couple_substep() calls since the previous lb_step() when N > 0
+ * (LBMD_ESTATE otherwise).
+ */
+int lb_step(lbmd *c);
+
+/*
+ * Moments of the current (post-stream) state (Eq. 1-2).  d_rho: nullable
+ * device [nsites] density; d_u: nullable device [3][nsites] velocity j/rho;
+ * both in the context precision.  h_totals: nullable host double[LBMD_NTOTALS]
+ * (FP64 reductions, see the LBMD_TOT_* layout); when given, the call
+ * synchronizes the stream and returns LBMD_ENONFINITE if any particle became
+ * non-finite since creation.
+ */
+int lb_moments(lbmd *c, void *d_rho, void *d_u, double *h_totals);
+
+/*
+ * Populations of the current post-stream state as deviations
+ * df_i(r) = f_i(r) - w_i rho0, device [19][nsites] in the context precision,
+ * site index r = x + nx*(y + ny*z), velocity order: 0, +x, -x, +y, -y, +z,
+ * -z, (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1),
+ * (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  Get copies out, set
+ * replaces the state (pending momentum transfer is kept).
+ */
+int lbmd_get_populations(lbmd *c, void *d_dst);
+int lbmd_set_populations(lbmd *c, const void *d_src);
+
+/* Pending momentum transfer J (sum of Eq. 8 over this LB interval), device
+ * [3][nsites] in the context precision. */
+int lbmd_get_transfer(lbmd *c, void *d_dst);
+
+/* Step counters: LB steps, MD steps, MD steps since the last LB step. */
+int lbmd_get_counters(lbmd *c, int64_t *t_lb, int64_t *t_md, int32_t *subs);
+int lbmd_set_counters(lbmd *c, int64_t t_lb, int64_t t_md, int32_t subs);
+
+/* Message for a status code. */
+const char *lbmd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMD_H */

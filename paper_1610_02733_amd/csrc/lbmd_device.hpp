@@ -1,0 +1,303 @@
+// Device-side building blocks of the fluctuating D3Q19 LB / MD coupling:
+// counter-based noise, the moment-space collision on population deviations
+// and the lattice index helpers.  Host-callable too (no device intrinsics in
+// the arithmetic), so the same code can be checked on the CPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmd_dev {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64-bit products; the two key words advance by the Weyl increments
+// between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__host__ __device__ __forceinline__ Words4 philox10(Words4 c, uint32_t ka, uint32_t kb) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t prodA = (uint64_t)0xD2511F53u * (uint64_t)c.w0;
+    const uint64_t prodB = (uint64_t)0xCD9E8D57u * (uint64_t)c.w2;
+    Words4 n;
+    n.w0 = (uint32_t)(prodB >> 32) ^ c.w1 ^ ka;
+    n.w1 = (uint32_t)prodB;
+    n.w2 = (uint32_t)(prodA >> 32) ^ c.w3 ^ kb;
+    n.w3 = (uint32_t)prodA;
+    c = n;
+    ka += 0x9E3779B9u;
+    kb += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Noise-stream counter: (index, step low word, purpose<<28 | replica<<8 |
+// call, step high word); key = the two words of the 64-bit seed.
+enum : uint32_t { kPurposeFluid = 1u, kPurposeParticle = 2u };
+
+__host__ __device__ __forceinline__ uint32_t noise_tag(uint32_t purpose, uint32_t replica,
+                                                       uint32_t call) {
+  return (purpose << 28) | ((replica & 0xFFFFFu) << 8) | (call & 0xFFu);
+}
+
+// ---------------------------------------------------------------------------
+// Real-type helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec4 {
+  T x, y, z, w;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ T tsqrt(T a);
+template <>
+__host__ __device__ __forceinline__ float tsqrt<float>(float a) { return sqrtf(a); }
+template <>
+__host__ __device__ __forceinline__ double tsqrt<double>(double a) { return sqrt(a); }
+
+// ---------------------------------------------------------------------------
+// Collision constants (per context, passed by value to the kernels).
+// Relaxation factors g_s (shear), g_b (bulk), g_g (kinetic modes); h = (1+g)/2
+// multiplies the Guo stress source; ns[k-4] = sqrt(b_k (1 - g_k^2)) *
+// sqrt(12) / 2^16 turns a centred 16-bit integer into phi_k r_k / sqrt(mu rho).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CollideConsts {
+  T rho0;
+  T gs, gb, gg;
+  T hs, hb;
+  T mu;  // 3 kT
+  T ns[15];
+  T g[3];  // uniform body-force density
+  int noise;
+};
+
+// Collision of one site, in place on the 19 population deviations
+// d_i = f_i - w_i rho0 (post-stream, pre-collision in; post-collision out).
+// F: force density acting over the LB step (pending transfer + body force).
+// hw: the eight Philox words of this site and step (used when k.noise).
+//
+// Mode basis: weighted-orthogonal D3Q19 polynomials 1, c, (c^2-1),
+// (3cx^2-c^2), (cy^2-cz^2), cxcy, cycz, cxcz, (3c^2-5)c, (cy^2-cz^2)cx,
+// (cz^2-cx^2)cy, (cx^2-cy^2)cz, 3c^4-6c^2+1, (2c^2-3)(3cx^2-c^2),
+// (2c^2-3)(cy^2-cz^2), evaluated here through sums (s) and differences (a) of
+// opposite populations.  Equilibrium stress moments are the images of
+// rho c_s^2 I + rho u u with u = (j + F/2)/rho; the kinetic modes have zero
+// equilibrium; the Guo source adds (1+g)/2 times the image of u F + F u.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_deviation(T d[19], T Fx, T Fy, T Fz,
+                                                           const uint32_t hw[8],
+                                                           const CollideConsts<T>& k) {
+  const T s12 = d[1] + d[2], a12 = d[1] - d[2];
+  const T s34 = d[3] + d[4], a34 = d[3] - d[4];
+  const T s56 = d[5] + d[6], a56 = d[5] - d[6];
+  const T s78 = d[7] + d[8], a78 = d[7] - d[8];
+  const T s9a = d[9] + d[10], a9a = d[9] - d[10];
+  const T sbc = d[11] + d[12], abc = d[11] - d[12];
+  const T sde = d[13] + d[14], ade = d[13] - d[14];
+  const T sfg = d[15] + d[16], afg = d[15] - d[16];
+  const T shi = d[17] + d[18], ahi = d[17] - d[18];
+  const T sxy = s78 + s9a, sxz = sbc + sde, syz = sfg + shi;
+  const T sdiag = sxy + sxz + syz;
+  const T saxis = s12 + s34 + s56;
+
+  const T drho = d[0] + saxis + sdiag;
+  const T jx = a12 + a78 + a9a + abc + ade;
+  const T jy = a34 + a78 - a9a + afg + ahi;
+  const T jz = a56 + abc - ade + afg - ahi;
+  const T rho = k.rho0 + drho;
+  const T irho = T(1) / rho;
+  const T ux = (jx + T(0.5) * Fx) * irho;
+  const T uy = (jy + T(0.5) * Fy) * irho;
+  const T uz = (jz + T(0.5) * Fz) * irho;
+
+  // stress modes
+  const T m4 = sdiag - d[0];
+  const T m5 = T(2) * s12 - s34 - s56 + sxy + sxz - T(2) * syz;
+  const T m6 = s34 - s56 + sxy - sxz;
+  const T m7 = s78 - s9a;
+  const T m8 = sfg - shi;
+  const T m9 = sbc - sde;
+  // kinetic modes
+  const T m10 = a78 + a9a + abc + ade - T(2) * a12;
+  const T m11 = a78 - a9a + afg + ahi - T(2) * a34;
+  const T m12 = abc - ade + afg - ahi - T(2) * a56;
+  const T m13 = a78 + a9a - abc - ade;
+  const T m14 = a9a - a78 + afg + ahi;
+  const T m15 = abc - ade - afg + ahi;
+  const T m16 = d[0] - T(2) * saxis + sdiag;
+  const T m17 = s34 + s56 - T(2) * s12 + sxy + sxz - T(2) * syz;
+  const T m18 = s56 - s34 + sxy - sxz;
+
+  // equilibrium stress moments and Guo source
+  const T xx = ux * ux, yy = uy * uy, zz = uz * uz;
+  const T e4 = rho * (xx + yy + zz);
+  const T e5 = rho * (T(2) * xx - yy - zz);
+  const T e6 = rho * (yy - zz);
+  const T e7 = rho * ux * uy;
+  const T e8 = rho * uy * uz;
+  const T e9 = rho * ux * uz;
+  const T fx = ux * Fx, fy = uy * Fy, fz = uz * Fz;
+  const T q4 = T(2) * (fx + fy + fz);
+  const T q5 = T(2) * (T(2) * fx - fy - fz);
+  const T q6 = T(2) * (fy - fz);
+  const T q7 = ux * Fy + uy * Fx;
+  const T q8 = uy * Fz + uz * Fy;
+  const T q9 = ux * Fz + uz * Fx;
+
+  T p[15];
+  p[0] = e4 + k.gb * (m4 - e4) + k.hb * q4;
+  p[1] = e5 + k.gs * (m5 - e5) + k.hs * q5;
+  p[2] = e6 + k.gs * (m6 - e6) + k.hs * q6;
+  p[3] = e7 + k.gs * (m7 - e7) + k.hs * q7;
+  p[4] = e8 + k.gs * (m8 - e8) + k.hs * q8;
+  p[5] = e9 + k.gs * (m9 - e9) + k.hs * q9;
+  p[6] = k.gg * m10;
+  p[7] = k.gg * m11;
+  p[8] = k.gg * m12;
+  p[9] = k.gg * m13;
+  p[10] = k.gg * m14;
+  p[11] = k.gg * m15;
+  p[12] = k.gg * m16;
+  p[13] = k.gg * m17;
+  p[14] = k.gg * m18;
+  if (k.noise) {
+    const T amp = tsqrt<T>(k.mu * rho);
+#pragma unroll
+    for (int v = 0; v < 15; ++v) {
+      const uint32_t w = hw[v >> 1];
+      const uint32_t h = (v & 1) ? (w >> 16) : (w & 0xFFFFu);
+      p[v] += amp * k.ns[v] * ((T)(int)h - T(32767.5));
+    }
+  }
+
+  // back transform: d_i = w_i sum_k e_k(c_i) m*_k / b_k
+  const T M0 = drho;
+  const T M1 = T(3) * (jx + Fx), M2 = T(3) * (jy + Fy), M3 = T(3) * (jz + Fz);
+  const T M4 = T(1.5) * p[0], M5 = T(0.75) * p[1], M6 = T(2.25) * p[2];
+  const T M7 = T(9) * p[3], M8 = T(9) * p[4], M9 = T(9) * p[5];
+  const T M10 = T(1.5) * p[6], M11 = T(1.5) * p[7], M12 = T(1.5) * p[8];
+  const T M13 = T(4.5) * p[9], M14 = T(4.5) * p[10], M15 = T(4.5) * p[11];
+  const T M16 = T(0.5) * p[12], M17 = T(0.75) * p[13], M18 = T(2.25) * p[14];
+
+  const T w1 = T(1) / T(18), w2 = T(1) / T(36);
+  d[0] = (M0 - M4 + M16) * (T(1) / T(3));
+  const T Eax = M0 - T(2) * M16 + M17;  // shared by the three axis pairs
+  const T Ex = M0 + T(2) * M5 - T(2) * M16 - T(2) * M17, Ox = M1 - T(2) * M10;
+  const T Ey = Eax - M5 + M6 - M18, Oy = M2 - T(2) * M11;
+  const T Ez = Eax - M5 - M6 + M18, Oz = M3 - T(2) * M12;
+  d[1] = (Ex + Ox) * w1;
+  d[2] = (Ex - Ox) * w1;
+  d[3] = (Ey + Oy) * w1;
+  d[4] = (Ey - Oy) * w1;
+  d[5] = (Ez + Oz) * w1;
+  d[6] = (Ez - Oz) * w1;
+  const T D = M0 + M4 + M16;
+  const T Dxy = D + M5 + M6 + M17 + M18;
+  const T Dxz = D + M5 - M6 + M17 - M18;
+  const T Dyz = D - T(2) * M5 - T(2) * M17;
+  const T E78 = Dxy + M7, O78 = M1 + M2 + M10 + M11 + M13 - M14;
+  const T E9a = Dxy - M7, O9a = M1 - M2 + M10 - M11 + M13 + M14;
+  const T Ebc = Dxz + M9, Obc = M1 + M3 + M10 + M12 - M13 + M15;
+  const T Ede = Dxz - M9, Ode = M1 - M3 + M10 - M12 - M13 - M15;
+  const T Efg = Dyz + M8, Ofg = M2 + M3 + M11 + M12 + M14 - M15;
+  const T Ehi = Dyz - M8, Ohi = M2 - M3 + M11 - M12 + M14 + M15;
+  d[7] = (E78 + O78) * w2;
+  d[8] = (E78 - O78) * w2;
+  d[9] = (E9a + O9a) * w2;
+  d[10] = (E9a - O9a) * w2;
+  d[11] = (Ebc + Obc) * w2;
+  d[12] = (Ebc - Obc) * w2;
+  d[13] = (Ede + Ode) * w2;
+  d[14] = (Ede - Ode) * w2;
+  d[15] = (Efg + Ofg) * w2;
+  d[16] = (Efg - Ofg) * w2;
+  d[17] = (Ehi + Ohi) * w2;
+  d[18] = (Ehi - Ohi) * w2;
+}
+
+// Density deviation and momentum of 19 population deviations.
+template <typename T>
+__host__ __device__ __forceinline__ void moments_deviation(const T d[19], T& drho, T& jx, T& jy,
+                                                           T& jz) {
+  const T a12 = d[1] - d[2], a34 = d[3] - d[4], a56 = d[5] - d[6];
+  const T a78 = d[7] - d[8], a9a = d[9] - d[10], abc = d[11] - d[12];
+  const T ade = d[13] - d[14], afg = d[15] - d[16], ahi = d[17] - d[18];
+  T s = d[0];
+#pragma unroll
+  for (int i = 1; i < 19; ++i) s += d[i];
+  drho = s;
+  jx = a12 + a78 + a9a + abc + ade;
+  jy = a34 + a78 - a9a + afg + ahi;
+  jz = a56 + abc - ade + afg - ahi;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice geometry.  Site index r = x + nx*(y + ny*z).  Populations live in
+// "pull" storage: buffer[i][s] holds the post-collision value produced at
+// site s, so the post-stream value at r is buffer[i][r - c_i].
+// ---------------------------------------------------------------------------
+struct Geom {
+  int nx, ny, nz;
+  int S;          // nx*ny*nz
+  double inv_nx;  // 1/nx, 1/ny for the division helpers
+  double inv_ny;
+};
+
+// n / d for 0 <= n < 2^31 via a double reciprocal and one correction step.
+__host__ __device__ __forceinline__ int div_fast(int n, int d, double inv_d, int& rem) {
+  int q = (int)((double)n * inv_d);
+  int r = n - q * d;
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= d) {
+    q += 1;
+    r -= d;
+  }
+  rem = r;
+  return q;
+}
+
+__host__ __device__ __forceinline__ void site_coords(const Geom& g, int r, int& x, int& y, int& z) {
+  int row = div_fast(r, g.nx, g.inv_nx, x);
+  z = div_fast(row, g.ny, g.inv_ny, y);
+}
+
+// Pull sources of the 19 populations at site (x, y, z): src[i] = r - c_i.
+__host__ __device__ __forceinline__ void pull_sources(const Geom& g, int x, int y, int z,
+                                                      int src[19]) {
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+  const int r00 = g.nx * (y + g.ny * z);
+  const int rm0 = g.nx * (ym + g.ny * z), rp0 = g.nx * (yp + g.ny * z);
+  const int r0m = g.nx * (y + g.ny * zm), r0p = g.nx * (y + g.ny * zp);
+  const int rmm = g.nx * (ym + g.ny * zm), rpp = g.nx * (yp + g.ny * zp);
+  const int rmp = g.nx * (ym + g.ny * zp), rpm = g.nx * (yp + g.ny * zm);
+  src[0] = x + r00;
+  src[1] = xm + r00;   // +x came from x-1
+  src[2] = xp + r00;   // -x
+  src[3] = x + rm0;    // +y
+  src[4] = x + rp0;    // -y
+  src[5] = x + r0m;    // +z
+  src[6] = x + r0p;    // -z
+  src[7] = xm + rm0;   // (1,1,0)
+  src[8] = xp + rp0;   // (-1,-1,0)
+  src[9] = xm + rp0;   // (1,-1,0)
+  src[10] = xp + rm0;  // (-1,1,0)
+  src[11] = xm + r0m;  // (1,0,1)
+  src[12] = xp + r0p;  // (-1,0,-1)
+  src[13] = xm + r0p;  // (1,0,-1)
+  src[14] = xp + r0m;  // (-1,0,1)
+  src[15] = x + rmm;   // (0,1,1)
+  src[16] = x + rpp;   // (0,-1,-1)
+  src[17] = x + rmp;   // (0,1,-1)
+  src[18] = x + rpm;   // (0,-1,1)
+}
+
+}  // namespace lbmd_dev

@@ -1,0 +1,216 @@
+"""ctypes binding of the C ABI in ``include/lbmd.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblbmd.so``.  PyTorch provides the device memory (workspace, particle
+arrays) and the stream.  Importing this module on a machine without the
+built library raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmd.so")
+
+OK, EINVAL, ESTATE, EHIP, ENOSPACE, ENONFINITE = 0, -1, -2, -3, -4, -5
+NTOTALS = 14
+TOT = dict(mass=0, pfluid=slice(1, 4), pseen=slice(4, 7), ppart=slice(7, 10), ke=10,
+           u2=11, t_lb=12, t_md=13)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("n_sub", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
+        ("n_particles", C.c_int32), ("force_model", C.c_int32), ("chain_len", C.c_int32),
+        ("replica", C.c_uint32), ("seed", C.c_uint64),
+        ("rho0", C.c_double), ("nu", C.c_double), ("nu_bulk", C.c_double),
+        ("gamma_ghost", C.c_double), ("kT", C.c_double), ("friction", C.c_double),
+        ("particle_mass", C.c_double),
+        ("body_force", C.c_double * 3), ("f_ext", C.c_double * 3),
+        ("k_bond", C.c_double), ("r0_bond", C.c_double),
+        ("wca_eps", C.c_double), ("wca_sigma", C.c_double),
+    ]
+
+
+class LbmdError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {lib().lbmd_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbmd.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1610_02733_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.lbmd_workspace_bytes.argtypes = [C.POINTER(Params)]
+        L.lbmd_workspace_bytes.restype = C.c_size_t
+        L.lb_create.argtypes = [C.POINTER(Params), P, C.c_size_t, P, C.POINTER(P)]
+        L.lb_destroy.argtypes = [P]
+        L.lbmd_bind_particles.argtypes = [P, P, P, P]
+        L.md_couple_substep.argtypes = [P]
+        L.lb_step.argtypes = [P]
+        L.lb_moments.argtypes = [P, P, P, P]
+        L.lbmd_get_populations.argtypes = [P, P]
+        L.lbmd_set_populations.argtypes = [P, P]
+        L.lbmd_get_transfer.argtypes = [P, P]
+        L.lbmd_get_counters.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int32)]
+        L.lbmd_set_counters.argtypes = [P, C.c_int64, C.c_int64, C.c_int32]
+        L.lbmd_strerror.argtypes = [C.c_int]
+        L.lbmd_strerror.restype = C.c_char_p
+        for n in ("lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
+                  "lb_step", "lb_moments", "lbmd_get_populations", "lbmd_set_populations",
+                  "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters"):
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+DEFAULTS = dict(n_sub=1, variant=2, precision=32, n_particles=0, force_model=0, chain_len=1,
+                replica=0, seed=0, rho0=1.0, nu=1.0 / 6.0, nu_bulk=-1.0, gamma_ghost=0.0,
+                kT=0.0, friction=0.0, particle_mass=1.0, body_force=(0.0, 0.0, 0.0),
+                f_ext=(0.0, 0.0, 0.0), k_bond=0.0, r0_bond=1.0, wca_eps=0.0, wca_sigma=1.0)
+
+
+def make_params(shape, **kw) -> Params:
+    p = dict(DEFAULTS)
+    unknown = set(kw) - set(p)
+    if unknown:
+        raise TypeError(f"unknown parameters {sorted(unknown)}")
+    p.update(kw)
+    s = Params()
+    s.nx, s.ny, s.nz = (int(v) for v in shape)
+    for k, v in p.items():
+        if k in ("body_force", "f_ext"):
+            setattr(s, k, (C.c_double * 3)(*[float(t) for t in v]))
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise LbmdError(rc, what)
+    return rc
+
+
+class Lattice:
+    """One LB/MD system on one GPU: a periodic lattice plus N particles.
+
+    >>> sim = Lattice((64, 64, 64), precision=32, n_sub=5, kT=1e-4, ...)
+    >>> sim.bind_particles(x, v)          # torch tensors [3, N] on the device
+    >>> for _ in range(steps): sim.cycle()  # n_sub MD steps + one LB step
+    """
+
+    def __init__(self, shape, device="cuda", stream=None, **kw):
+        self.shape = tuple(int(v) for v in shape)
+        self.nsites = int(np.prod(self.shape))
+        self.params = make_params(self.shape, **kw)
+        self.kw = dict(DEFAULTS, **kw)
+        self.dtype = torch.float32 if self.params.precision == 32 else torch.float64
+        self.device = torch.device(device)
+        self.N = self.params.n_particles
+        nbytes = lib().lbmd_workspace_bytes(C.byref(self.params))
+        if nbytes == 0:
+            raise LbmdError(EINVAL, "lbmd_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().lb_create(C.byref(self.params), _ptr(self.ws), nbytes,
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lb_create")
+        self._h = h
+        self.x = self.v = self.img = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state -----------------------------------------------------------
+    def bind_particles(self, x, v, img=None):
+        N = self.N
+        self.x = torch.as_tensor(x, dtype=self.dtype, device=self.device).reshape(3, N).contiguous()
+        self.v = torch.as_tensor(v, dtype=self.dtype, device=self.device).reshape(3, N).contiguous()
+        if img is None:
+            self.img = torch.zeros((3, N), dtype=torch.int32, device=self.device)
+        else:
+            self.img = torch.as_tensor(img, dtype=torch.int32, device=self.device).reshape(3, N).contiguous()
+        _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
+               "lbmd_bind_particles")
+
+    def populations(self):
+        out = torch.empty((19, self.nsites), dtype=self.dtype, device=self.device)
+        _check(lib().lbmd_get_populations(self._h, _ptr(out)), "lbmd_get_populations")
+        return out
+
+    def set_populations(self, dev):
+        t = torch.as_tensor(dev, dtype=self.dtype, device=self.device).reshape(19, self.nsites).contiguous()
+        _check(lib().lbmd_set_populations(self._h, _ptr(t)), "lbmd_set_populations")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def transfer(self):
+        out = torch.empty((3, self.nsites), dtype=self.dtype, device=self.device)
+        _check(lib().lbmd_get_transfer(self._h, _ptr(out)), "lbmd_get_transfer")
+        return out
+
+    def counters(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().lbmd_get_counters(self._h, C.byref(a), C.byref(b), C.byref(c)), "counters")
+        return dict(t_lb=a.value, t_md=b.value, subs=c.value)
+
+    def set_counters(self, t_lb, t_md, subs):
+        _check(lib().lbmd_set_counters(self._h, t_lb, t_md, subs), "set_counters")
+
+    # ---- steps -----------------------------------------------------------
+    def md_couple_substep(self):
+        return _check(lib().md_couple_substep(self._h), "md_couple_substep")
+
+    def lb_step(self):
+        return _check(lib().lb_step(self._h), "lb_step")
+
+    def cycle(self, ncycles=1):
+        n = self.params.n_sub
+        L = lib()
+        for _ in range(ncycles):
+            if self.N > 0:
+                for _ in range(n):
+                    rc = L.md_couple_substep(self._h)
+                    if rc != OK:
+                        raise LbmdError(rc, "md_couple_substep")
+            rc = L.lb_step(self._h)
+            if rc != OK:
+                raise LbmdError(rc, "lb_step")
+
+    def moments(self, fields=False, allow_nonfinite=False):
+        tot = np.zeros(NTOTALS)
+        rho = u = None
+        if fields:
+            rho = torch.empty(self.nsites, dtype=self.dtype, device=self.device)
+            u = torch.empty((3, self.nsites), dtype=self.dtype, device=self.device)
+        rc = lib().lb_moments(self._h, _ptr(rho), _ptr(u), tot.ctypes.data_as(C.c_void_p))
+        if rc != OK and not (allow_nonfinite and rc == ENONFINITE):
+            raise LbmdError(rc, "lb_moments")
+        return (tot, rho, u) if fields else tot

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (per population, after the stated number of LB steps): relative
+1e-12 for FP64 runs and 1e-5 for FP32 runs, measured as
+max_{i,r} |f_gpu - f_ref| / (w_i rho0) on full populations f = w_i rho0 + df,
+i.e. relative to each population's own scale (its rest value).  Thermal
+noise can carry an individual population close to zero, where a ratio to the
+instantaneous value would only measure rounding of a near-cancellation.
+Particles: |dx_unwrapped| <= tol * L, |dv| <= tol * max(|v|, sqrt(kT/m)).
+The only tolerated sources of difference are the order of floating-point
+sums (atomics, FMA contraction) and, for FP32 runs, the storage precision.
+"""
+import numpy as np
+import pytest
+
+from paper_1610_02733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-12, 32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_02733_amd import lbmd
+    lbmd.lib()
+    return lbmd
+
+
+def full_pops(dev, w, rho0):
+    return np.asarray(dev, np.float64) + w[:, None] * rho0
+
+
+def pop_err(gpu_dev, ref_full, w, rho0):
+    g = full_pops(gpu_dev, w, rho0)
+    return (np.abs(g - ref_full) / (w[:, None] * rho0)).max()
+
+
+def run_pair(lb, orc, shape, cycles, x=None, v=None, dev0=None, **kw):
+    """Run the same seeded system on the GPU and in the oracle."""
+    prec = kw.pop("precision")
+    dt = np.float32 if prec == 32 else np.float64
+    c, w, e, b = orc.tables()
+    rho0 = kw.get("rho0", 1.0)
+    N = kw.get("n_particles", 0)
+    g = lb.Lattice(shape, precision=prec, **kw)
+    o = orc.Oracle(*shape, **kw)
+    if dev0 is not None:
+        d0 = np.asarray(dev0, dt)
+        g.set_populations(d0)
+        o.set_populations(d0.astype(np.float64) + w[:, None] * rho0)
+    if N > 0:
+        xs, vs = wl.to_cast(x, dt), wl.to_cast(v, dt)
+        g.bind_particles(xs, vs)
+        o.set_particles(xs, vs)
+    g.cycle(cycles)
+    o.cycle(cycles)
+    return g, o, w, rho0
+
+
+def check_particles(g, o, shape, tol, kT, m=1.0):
+    xg = g.x.double().cpu().numpy() + np.asarray(shape, float)[:, None] * g.img.cpu().numpy()
+    xo, vo, io = o.particles()
+    xo = xo + np.asarray(shape, float)[:, None] * io
+    vg = g.v.double().cpu().numpy()
+    assert np.abs(xg - xo).max() <= tol * max(shape), np.abs(xg - xo).max()
+    vs = max(np.abs(vo).max(), np.sqrt(kT / m))
+    assert np.abs(vg - vo).max() <= tol * vs, np.abs(vg - vo).max() / vs
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_fluid_only_c1_shape(lb, orc, prec):
+    """16^3, nu = 1/6, kT = 1e-3, fluid at rest, 100 LB steps, Philox seed 1."""
+    cfg = wl.CONFIGS["c1"]
+    g, o, w, rho0 = run_pair(lb, orc, cfg["shape"], 100, precision=prec, kT=cfg["kT"],
+                             nu=cfg["nu"], seed=1)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    print(f"fluid-only 16^3 fp{prec}: max rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape", [(13, 7, 5), (64, 3, 2), (2, 2, 2)])
+def test_random_state_rates_force(lb, orc, prec, shape):
+    """Ragged lattices (site counts not a multiple of the 64-wide wavefront),
+    distinct shear / bulk / kinetic rates, body force, noise."""
+    c, w, e, b = orc.tables()
+    dt = np.float32 if prec == 32 else np.float64
+    d0 = wl.perturbed_deviations(shape, w, 1.3, 0.05, seed=7, dtype=dt)
+    kw = dict(rho0=1.3, nu=0.31, nu_bulk=0.12, gamma_ghost=0.25, kT=2e-4, seed=99,
+              body_force=(1e-5, -2e-5, 3e-6))
+    g, o, w, rho0 = run_pair(lb, orc, shape, 20, dev0=d0, precision=prec, **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_c1_coupled(lb, orc, prec, variant):
+    """The plain-method case: 16^3, 32 particles, gamma = 1, n = 5, 100 LB
+    steps (500 MD steps), both variants."""
+    cfg = wl.CONFIGS["c1"]
+    x, v = wl.free_particles(cfg["shape"], cfg["n_particles"], cfg["kT"], 1.0, cfg["seed"])
+    kw = dict(kT=cfg["kT"], nu=cfg["nu"], seed=1, n_particles=cfg["n_particles"],
+              friction=cfg["friction"], n_sub=cfg["n_sub"], variant=variant, particle_mass=1.0)
+    g, o, w, rho0 = run_pair(lb, orc, cfg["shape"], cfg["lb_steps"], x=x, v=v, precision=prec, **kw)
+    gd, fo = g.populations().cpu().numpy(), o.populations()
+    err = pop_err(gd, fo, w, rho0)
+    inst = (np.abs(full_pops(gd, w, rho0) - fo) / np.abs(fo)).max()
+    print(f"c1 variant {variant} fp{prec}: max err / (w rho0) {err:.3e}, "
+          f"max err / |f| {inst:.3e}, min f / (w rho0) {(fo / w[:, None]).min():.3f}")
+    assert err < TOL[prec]
+    check_particles(g, o, cfg["shape"], TOL[prec], cfg["kT"])
+    tg, to = g.moments(), o.moments()
+    # total mass: exact up to rounding in FP64; FP32 storage of the deviations
+    # lets the sum drift by rounding of each site's back-transform
+    assert abs(tg[0] - to[0]) < {64: 1e-12, 32: 1e-6}[prec] * to[0], abs(tg[0] - to[0]) / to[0]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_dense_particles_share_sites(lb, orc, prec):
+    """Many particles per cube (the variant-2 read-before-write hazard and
+    atomic contention): 4^3 lattice, 300 particles, both variants."""
+    shape = (4, 4, 4)
+    x, v = wl.free_particles(shape, 300, 1e-3, 1.0, 17)
+    for variant in (1, 2):
+        kw = dict(kT=1e-3, seed=5, n_particles=300, friction=0.5, n_sub=4, variant=variant,
+                  rho0=2.0)
+        g, o, w, rho0 = run_pair(lb, orc, shape, 10, x=x, v=v, precision=prec, **kw)
+        err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+        assert err < TOL[prec], (variant, err)
+        check_particles(g, o, shape, TOL[prec], 1e-3)
+
+
+def test_n1_variants_coincide(lb, orc):
+    """For n = 1 the two variants are the same algorithm (Sec. 3)."""
+    shape = (8, 8, 8)
+    x, v = wl.free_particles(shape, 40, 1e-3, 1.0, 3)
+    res = []
+    for variant in (1, 2):
+        g = lb.Lattice(shape, precision=64, n_sub=1, variant=variant, kT=1e-3, seed=3,
+                       n_particles=40, friction=1.0)
+        g.bind_particles(x, v)
+        g.cycle(30)
+        res.append((g.populations().cpu().numpy(), g.v.cpu().numpy()))
+    assert np.abs(res[0][0] - res[1][0]).max() < 1e-15
+    assert np.abs(res[0][1] - res[1][1]).max() < 1e-15
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_momentum_granularity_gpu(lb, variant):
+    """Sec. 3: variant 2 conserves fluid + particle momentum at every MD step,
+    variant 1 only at LB steps; FP64 reductions on the GPU, FP32 run."""
+    shape = (24, 16, 8)
+    N = 200
+    x, v = wl.free_particles(shape, N, 1e-3, 1.0, 8)
+    g = lb.Lattice(shape, precision=32, n_sub=5, variant=variant, kT=1e-3, seed=4,
+                   n_particles=N, friction=2.0)
+    g.bind_particles(x, v)
+    t0 = g.moments()
+    seen0 = t0[4:7] + t0[7:10]
+    tot0 = t0[1:4] + t0[7:10]
+    dev = 0.0
+    for _ in range(3):
+        for _ in range(5):
+            g.md_couple_substep()
+            t = g.moments()
+            assert np.abs(t[1:4] + t[7:10] - tot0).max() < 1e-6
+            dev = max(dev, np.abs(t[4:7] + t[7:10] - seen0).max())
+        g.lb_step()
+        t = g.moments()
+        assert np.abs(t[4:7] + t[7:10] - seen0).max() < 1e-6
+        assert abs(t[0] - t0[0]) < 1e-6 * t0[0]
+    if variant == 2:
+        assert dev < 1e-6
+    else:
+        assert dev > 1e-4
+
+
+def test_error_codes(lb):
+    import torch
+    with pytest.raises(lb.LbmdError) as ei:
+        lb.Lattice((16, 16, 16), n_sub=0)
+    assert ei.value.code == lb.EINVAL
+    with pytest.raises(lb.LbmdError):
+        lb.Lattice((16, 16, 16), variant=3)
+    with pytest.raises(lb.LbmdError):
+        lb.Lattice((1, 16, 16))
+    g = lb.Lattice((8, 8, 8), n_sub=2, n_particles=4)
+    assert lb.lib().lb_step(g._h) == lb.ESTATE           # particles not bound / no MD steps
+    x, v = wl.free_particles((8, 8, 8), 4, 0.0, 1.0, 1)
+    g.bind_particles(x, v)
+    g.md_couple_substep()
+    assert lb.lib().lb_step(g._h) == lb.ESTATE           # 1 of 2 MD steps done
+    g.md_couple_substep()
+    assert lb.lib().md_couple_substep(g._h) == lb.ESTATE  # a third MD step
+    g.lb_step()
+    # non-finite particle: flagged, skipped, reported by lb_moments
+    g.x[0, 1] = float("nan")
+    g.cycle(1)
+    tot = g.moments(allow_nonfinite=True)
+    with pytest.raises(lb.LbmdError) as ei:
+        g.moments()
+    assert ei.value.code == lb.ENONFINITE
+    assert np.isfinite(g.populations().cpu().numpy()).all()
+    torch.cuda.synchronize()
