@@ -12,8 +12,9 @@
  * two population buffers, the momentum-transfer field and particle scratch,
  * and the particle arrays handed to lbmd_bind_particles().  The library never
  * allocates or frees device memory.  Buffers must stay alive until
- * lb_destroy().  All floating-point device arrays use the context precision
- * (float for precision 32, double for precision 64).
+ * lb_destroy().  Lattice arrays (populations, densities, velocities,
+ * transfer) use the context precision (float for precision 32, double for
+ * precision 64); particle positions and velocities are double in both.
  *
  * Streams.  A context is bound to one HIP stream.  Every call is an
  * asynchronous enqueue on it, except lb_moments() with a host totals pointer
@@ -110,8 +111,8 @@ int lb_destroy(lbmd *c);
 
 /*
  * Bind the caller's particle arrays (device, SoA [3][N]: x, then y, then z
- * rows).  d_x: positions in [0, L) per axis; d_v: velocities; d_img: int32
- * periodic image counters (unwrapped position = x + L * img).  The library
+ * rows).  d_x: double positions in [0, L) per axis; d_v: double velocities;
+ * d_img: int32 periodic image counters (unwrapped position = x + L * img).  The library
  * updates them in place at every md_couple_substep().  Computes the
  * conservative forces at the bound positions.
  */

@@ -46,10 +46,13 @@ Layout layout(const lbmd_params* p) {
   L.pop[1] = o; o = up(o + 19 * S * t);
   L.transfer = o; o = up(o + 4 * S * t);
   L.mark = o; o = up(o + ((S + 63) / 64) * 8);
-  L.fcons = o; o = up(o + 3 * N * t);
+  L.fcons = o; o = up(o + 3 * N * 8);
   L.rec_cell = o; o = up(o + 3 * N * 4);
-  L.rec_frac = o; o = up(o + 3 * N * t);
-  L.rec_dp = o; o = up(o + 3 * N * t);
+  L.rec_frac = o; o = up(o + 3 * N * 8);
+  L.rec_dp = o; o = up(o + 3 * N * 8);
+  L.cc = o; o = up(o + 32 * N * t);
+  L.cc_cell = o; o = up(o + N * 4);
+  L.cc_stamp = o; o = up(o + N * 4);
   L.flags = o; o = up(o + 16 * 4);
   L.partials = o; o = up(o + (size_t)kRedBlocks * kRedWidth * 8);
   L.totals = o; o = up(o + kRedWidth * 8);
@@ -204,7 +207,9 @@ int lbmd_get_populations(lbmd* c, void* d_dst) {
 int lbmd_set_populations(lbmd* c, const void* d_src) {
   if (!c || !d_src) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  return fail(c, launch_set_populations(c, d_src));
+  const int rc = fail(c, launch_set_populations(c, d_src));
+  if (rc) return rc;
+  return fail(c, invalidate_corner_cache(c));
 }
 
 int lbmd_get_transfer(lbmd* c, void* d_dst) {
@@ -223,10 +228,11 @@ int lbmd_get_counters(lbmd* c, int64_t* t_lb, int64_t* t_md, int32_t* subs) {
 
 int lbmd_set_counters(lbmd* c, int64_t t_lb, int64_t t_md, int32_t subs) {
   if (!c || t_lb < 0 || t_md < 0 || subs < 0 || subs > c->p.n_sub) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
   c->t_lb = t_lb;
   c->t_md = t_md;
   c->subs = subs;
-  return LBMD_OK;
+  return fail(c, invalidate_corner_cache(c));
 }
 
 const char* lbmd_strerror(int code) {

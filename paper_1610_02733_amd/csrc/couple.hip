@@ -7,23 +7,29 @@
 namespace lbmd_impl {
 using namespace lbmd_dev;
 
+// T is the lattice precision (populations, transfer field, corner cache);
+// particle state and all particle arithmetic are FP64 in both precisions.
 template <typename T>
 struct CoupleArgs {
-  T* __restrict__ x;
-  T* __restrict__ v;
+  double* __restrict__ x;
+  double* __restrict__ v;
   int32_t* __restrict__ img;
-  const T* __restrict__ fcons;
+  const double* __restrict__ fcons;
   const T* __restrict__ pop;
   Vec4<T>* __restrict__ J;
   unsigned long long* __restrict__ mark;
   int32_t* __restrict__ rec_cell;
-  T* __restrict__ rec_frac;
-  T* __restrict__ rec_dp;
+  double* __restrict__ rec_frac;
+  double* __restrict__ rec_dp;
+  T* __restrict__ cc;
+  int32_t* __restrict__ cc_cell;
+  int32_t* __restrict__ cc_stamp;
   int32_t* __restrict__ flags;
   Geom g;
   int N;
-  T rho0, gamma, amp, tau, h;  // h = tau / (2 m)
-  T L[3];
+  int stamp;  // LB step + 1: identifies the post-stream state the cache holds
+  double rho0, gamma, amp, tau, h;  // h = tau / (2 m)
+  double L[3];
   uint32_t key0, key1, step_lo, step_hi, tag;
   int variant;
   int noise;
@@ -31,12 +37,11 @@ struct CoupleArgs {
 
 // Periodic wrap with image counting; a value that lands on exactly L after
 // adding L stays at 0 in its old image.
-template <typename T>
-__device__ __forceinline__ void wrap_coord(T& x, int32_t& im, T L) {
+__device__ __forceinline__ void wrap_coord(double& x, int32_t& im, double L) {
   if (x >= L) {
     x -= L;
     im += 1;
-  } else if (x < T(0)) {
+  } else if (x < 0.0) {
     x += L;
     im -= 1;
     if (x >= L) {
@@ -53,204 +58,323 @@ __device__ __forceinline__ int cell_of(int c, int n) {
   return c < 0 ? c + n : c;
 }
 
-template <typename T>
-__device__ __forceinline__ void corner_weights(const T s[3], T w[8]) {
+// D3Q19 velocities in the library's order (opposite pairs adjacent).
+__device__ const int8_t kVel[19][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+struct Cube {
+  int base[3];
+  double s[3];
+};
+
+__device__ __forceinline__ void cube_of(const double X[3], const Geom& g, Cube& q) {
+  const int n3[3] = {g.nx, g.ny, g.nz};
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const T a = (k & 1) ? s[0] : T(1) - s[0];
-    const T b = (k & 2) ? s[1] : T(1) - s[1];
-    const T cc = (k & 4) ? s[2] : T(1) - s[2];
-    w[k] = a * b * cc;
+  for (int d = 0; d < 3; ++d) {
+    const double fl = floor(X[d]);
+    q.s[d] = X[d] - fl;
+    q.base[d] = cell_of((int)fl, n3[d]);
   }
 }
 
-__device__ __forceinline__ void corner_sites(const Geom& g, const int base[3], int site[8],
-                                             int cx[8], int cy[8], int cz[8]) {
-  const int x1 = base[0] + 1 == g.nx ? 0 : base[0] + 1;
-  const int y1 = base[1] + 1 == g.ny ? 0 : base[1] + 1;
-  const int z1 = base[2] + 1 == g.nz ? 0 : base[2] + 1;
+// Site and trilinear weight (Eq. 5) of corner k of the cube.
+__device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, int& cx, int& cy,
+                                          int& cz, int& site, double& w) {
+  cx = q.base[0] + (k & 1);
+  cy = q.base[1] + ((k >> 1) & 1);
+  cz = q.base[2] + ((k >> 2) & 1);
+  cx = cx == g.nx ? 0 : cx;
+  cy = cy == g.ny ? 0 : cy;
+  cz = cz == g.nz ? 0 : cz;
+  site = cx + g.nx * (cy + g.ny * cz);
+  w = ((k & 1) ? q.s[0] : 1.0 - q.s[0]) * ((k & 2) ? q.s[1] : 1.0 - q.s[1]) *
+      ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
+}
+
+// Density deviation and momentum of the post-stream state at one site,
+// gathered from pull storage (one lane does all 19 reads).
+template <typename T>
+__device__ __forceinline__ void site_moments(const CoupleArgs<T>& a, int cx, int cy, int cz,
+                                             T& drho, T& jx, T& jy, T& jz) {
+  int src[19];
+  pull_sources(a.g, cx, cy, cz, src);
+  const size_t S = (size_t)a.g.S;
+  T d[19];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    cx[k] = (k & 1) ? x1 : base[0];
-    cy[k] = (k & 2) ? y1 : base[1];
-    cz[k] = (k & 4) ? z1 : base[2];
-    site[k] = cx[k] + g.nx * (cy[k] + g.ny * cz[k]);
-  }
+  for (int i = 0; i < 19; ++i) d[i] = a.pop[(size_t)i * S + src[i]];
+  moments_deviation<T>(d, drho, jx, jy, jz);
+}
+
+// Corner cache entry k of particle p: (jx, jy, jz, 1/rho) of the corner.
+template <typename T>
+__device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int p, int k) {
+  return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * 8 + k;
+}
+
+// ---------------------------------------------------------------------------
+// Corner-cache refill, once per LB interval (before its first MD step):
+// (j, 1/rho) of the post-stream state at the 8 corners of every particle's
+// cube.  32 lanes per particle, 4 per corner, which split the corner's 19
+// pulled populations; the state does not change until the next LB step, so
+// the MD steps of the interval read 8 contiguous vectors per particle instead
+// of 8 x 19 scattered populations.  Also marks the 8 sites as receivers of
+// momentum transfer for the LB step.
+// ---------------------------------------------------------------------------
+constexpr int kRefillLanes = 32;
+
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {  // over the 4 lanes of a corner
+  v += __shfl_xor(v, 1, kRefillLanes);
+  v += __shfl_xor(v, 2, kRefillLanes);
+  return v;
 }
 
 template <typename T>
-__device__ __forceinline__ void transfer(const CoupleArgs<T>& a, const int site[8], const T w[8],
-                                         const T dp[3]) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    Vec4<T>* q = a.J + site[k];
-    atomicAdd(&q->x, -w[k] * dp[0]);
-    atomicAdd(&q->y, -w[k] * dp[1]);
-    atomicAdd(&q->z, -w[k] * dp[2]);
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void mark_sites(const CoupleArgs<T>& a, const int site[8]) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    atomicOr(a.mark + (site[k] >> 6), 1ull << (site[k] & 63));
-}
-
-// One MD step for one particle.  Variant 1 transfers its momentum right
-// away (nothing in this MD step reads J); variant 2 stores (cube, weights
-// source, dP) for the spreading kernel, because every particle must first
-// read the velocities as of the end of the previous MD step.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= a.N) return;
+__global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int p = t / kRefillLanes;
+  if (p >= a.N) return;  // the 32 lanes of a particle leave together
+  const int sl = threadIdx.x & (kRefillLanes - 1);
+  const int k = sl >> 2, c = sl & 3;
   const int N = a.N;
-  T X[3], V[3];
+  double X[3];
   bool finite = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     X[d] = a.x[d * N + p];
-    V[d] = a.v[d * N + p];
-    finite = finite && isfinite(X[d]) && isfinite(V[d]);
+    finite = finite && isfinite(X[d]);
   }
-  if (!finite) {
-    a.flags[0] = 1;
-    if (a.variant == 2) a.rec_cell[p] = -1;
-    return;
-  }
-  int base[3];
-  T s[3];
-  const int n3[3] = {a.g.nx, a.g.ny, a.g.nz};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const T fl = floor(X[d]);
-    s[d] = X[d] - fl;
-    base[d] = cell_of((int)fl, n3[d]);
-  }
-  int site[8], cx[8], cy[8], cz[8];
-  corner_sites(a.g, base, site, cx, cy, cz);
-  T w[8];
-  corner_weights<T>(s, w);
-
-  // fluid velocity at the particle (Eq. 5) from the post-stream state
+  if (!finite) return;
+  Cube q;
+  cube_of(X, a.g, q);
+  int cx, cy, cz, site;
+  double w;
+  corner_of(q, a.g, k, cx, cy, cz, site, w);
   const size_t S = (size_t)a.g.S;
-  T u[3] = {T(0), T(0), T(0)};
-#pragma unroll 1
-  for (int k = 0; k < 8; ++k) {
-    int src[19];
-    pull_sources(a.g, cx[k], cy[k], cz[k], src);
-    T d[19];
+  T drho = T(0), qx = T(0), qy = T(0), qz = T(0);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = a.pop[(size_t)i * S + src[i]];
-    T drho, jx, jy, jz;
-    moments_deviation<T>(d, drho, jx, jy, jz);
-    if (a.variant == 2) {
-      const Vec4<T> jv = a.J[site[k]];
-      jx += jv.x;
-      jy += jv.y;
-      jz += jv.z;
+  for (int m = 0; m < 5; ++m) {
+    const int i = c + 4 * m;
+    if (i < 19) {
+      const int ex = kVel[i][0], ey = kVel[i][1], ez = kVel[i][2];
+      int sx = cx - ex, sy = cy - ey, sz = cz - ez;
+      sx = sx < 0 ? sx + a.g.nx : (sx >= a.g.nx ? sx - a.g.nx : sx);
+      sy = sy < 0 ? sy + a.g.ny : (sy >= a.g.ny ? sy - a.g.ny : sy);
+      sz = sz < 0 ? sz + a.g.nz : (sz >= a.g.nz ? sz - a.g.nz : sz);
+      const T d = a.pop[(size_t)i * S + sx + a.g.nx * (sy + a.g.ny * sz)];
+      drho += d;
+      qx += (T)ex * d;
+      qy += (T)ey * d;
+      qz += (T)ez * d;
     }
-    const T inv = T(1) / (a.rho0 + drho);
-    u[0] += w[k] * (jx * inv);
-    u[1] += w[k] * (jy * inv);
-    u[2] += w[k] * (jz * inv);
   }
+  drho = quad_sum(drho);
+  qx = quad_sum(qx);
+  qy = quad_sum(qy);
+  qz = quad_sum(qz);
+  const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)a.rho0 + drho)));
+  a.cc[(size_t)p * 32 + sl] = mine;
+  if (sl == 0) {
+    a.cc_cell[p] = q.base[0] + a.g.nx * (q.base[1] + a.g.ny * q.base[2]);
+    a.cc_stamp[p] = a.stamp;
+  }
+  if (c == 0) atomicOr(a.mark + (site >> 6), 1ull << (site & 63));
+}
 
-  // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
-  T xi[3] = {T(0), T(0), T(0)};
-  if (a.noise) {
-    const Words4 o = philox10(Words4{(uint32_t)p, a.step_lo, a.tag, a.step_hi}, a.key0, a.key1);
-    const uint32_t ws[3] = {o.w0, o.w1, o.w2};
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      xi[d] = T(3.4641016151377546) *
-              (((T)(int)(ws[d] >> 8) + T(0.5)) * T(5.9604644775390625e-08) - T(0.5));
-  }
-  T Fc[3], dp[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    Fc[d] = -a.gamma * (V[d] - u[d]) + a.amp * xi[d];
-    dp[d] = a.tau * Fc[d];
-  }
-
-  // velocity Verlet with the coupling force held over the step; the
-  // conservative force of force models 0/1 does not depend on position
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const T fc = a.fcons[d * N + p];
-    int32_t im = a.img[d * N + p];
-    V[d] += a.h * (fc + Fc[d]);
-    X[d] += a.tau * V[d];
-    wrap_coord<T>(X[d], im, a.L[d]);
-    V[d] += a.h * (fc + Fc[d]);
-    a.x[d * N + p] = X[d];
-    a.v[d * N + p] = V[d];
-    a.img[d * N + p] = im;
-  }
-
-  // momentum transfer to the fluid (Eq. 7-8)
-  mark_sites<T>(a, site);
-  if (a.variant == 1) {
-    transfer<T>(a, site, w, dp);
-  } else {
-    a.rec_cell[p] = base[0];
-    a.rec_cell[N + p] = base[1];
-    a.rec_cell[2 * N + p] = base[2];
+// ---------------------------------------------------------------------------
+// One MD step (Sec. 3, Eq. 4-8), one lane per particle.
+//
+// Fluid velocity at the particle from the cached corner moments (a particle
+// that left its cube since the refill gathers the new corners itself),
+// friction + noise, velocity Verlet.  Variant 1 then transfers the momentum
+// right away: the block stages (cube, dP) of its 256 particles in LDS and
+// re-issues the 24 adds of each particle from 24 consecutive lanes, so one
+// atomic instruction covers ~3 particles and a handful of cache lines rather
+// than 64 unrelated lines.  Variant 2 stores (cube, dP) for the spreading
+// kernel, because every particle must first read the velocities as of the
+// end of the previous MD step.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
+  __shared__ int sh_base[3][kBlock];
+  __shared__ double sh_s[3][kBlock];
+  __shared__ double sh_dp[3][kBlock];
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int N = a.N;
+  bool live = p < N;
+  double X[3] = {0.0, 0.0, 0.0}, V[3] = {0.0, 0.0, 0.0};
+  if (live) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      a.rec_frac[d * N + p] = s[d];
-      a.rec_dp[d * N + p] = dp[d];
+      X[d] = a.x[d * N + p];
+      V[d] = a.v[d * N + p];
+      live = live && isfinite(X[d]) && isfinite(V[d]);
     }
+    if (!live) {
+      a.flags[0] = 1;
+      if (a.variant == 2) a.rec_cell[p] = -1;
+    }
+  }
+  Cube q;
+  double dp[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    cube_of(X, a.g, q);
+    const int cell = q.base[0] + a.g.nx * (q.base[1] + a.g.ny * q.base[2]);
+    Vec4<T> cv[8];
+    if (a.cc_stamp[p] == a.stamp && a.cc_cell[p] == cell) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cv[k] = *cache_entry(a, p, k);
+    } else {
+      // left the cube of the refill: gather the new corners here
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) {
+        int cx, cy, cz, site;
+        double w;
+        corner_of(q, a.g, k, cx, cy, cz, site, w);
+        T drho, jx, jy, jz;
+        site_moments<T>(a, cx, cy, cz, drho, jx, jy, jz);
+        cv[k] = Vec4<T>{jx, jy, jz, T(1) / ((T)a.rho0 + drho)};
+        *cache_entry(a, p, k) = cv[k];
+        atomicOr(a.mark + (site >> 6), 1ull << (site & 63));
+      }
+      a.cc_cell[p] = cell;
+      a.cc_stamp[p] = a.stamp;
+    }
+    // fluid velocity at the particle (Eq. 5)
+    double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int cx, cy, cz, site;
+      double w;
+      corner_of(q, a.g, k, cx, cy, cz, site, w);
+      double jx = (double)cv[k].x, jy = (double)cv[k].y, jz = (double)cv[k].z;
+      if (a.variant == 2) {
+        const Vec4<T> jv = a.J[site];
+        jx += (double)jv.x;
+        jy += (double)jv.y;
+        jz += (double)jv.z;
+      }
+      const double wi = w * (double)cv[k].w;
+      u[0] += wi * jx;
+      u[1] += wi * jy;
+      u[2] += wi * jz;
+    }
+    // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (a.noise) {
+      const Words4 o = philox10(Words4{(uint32_t)p, a.step_lo, a.tag, a.step_hi}, a.key0, a.key1);
+      const uint32_t ws[3] = {o.w0, o.w1, o.w2};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
+    }
+    // velocity Verlet with the coupling force held over the step (force
+    // models 0/1: position-independent conservative force)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double Fc = -a.gamma * (V[d] - u[d]) + a.amp * xi[d];
+      dp[d] = a.tau * Fc;
+      const double fc = a.fcons[d * N + p];
+      int32_t im = a.img[d * N + p];
+      V[d] += a.h * (fc + Fc);
+      X[d] += a.tau * V[d];
+      wrap_coord(X[d], im, a.L[d]);
+      V[d] += a.h * (fc + Fc);
+      a.x[d * N + p] = X[d];
+      a.v[d * N + p] = V[d];
+      a.img[d * N + p] = im;
+    }
+    if (a.variant == 2) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.rec_cell[d * N + p] = q.base[d];
+        a.rec_frac[d * N + p] = q.s[d];
+        a.rec_dp[d * N + p] = dp[d];
+      }
+    }
+  }
+  if (a.variant != 1) return;  // uniform: no thread of the block continues
+
+  // momentum transfer to the fluid (Eq. 7-8), 24 consecutive lanes per particle
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    sh_base[d][threadIdx.x] = live ? q.base[d] : -1;
+    sh_s[d][threadIdx.x] = live ? q.s[d] : 0.0;
+    sh_dp[d][threadIdx.x] = dp[d];
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < 24 * kBlock; g += kBlock) {
+    const int pp = g / 24, r = g - 24 * pp;
+    if (sh_base[0][pp] < 0) continue;
+    const int k = r / 3, c = r - 3 * k;
+    Cube qq;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      qq.base[d] = sh_base[d][pp];
+      qq.s[d] = sh_s[d][pp];
+    }
+    int cx, cy, cz, site;
+    double w;
+    corner_of(qq, a.g, k, cx, cy, cz, site, w);
+    atomicAdd(((T*)(a.J + site)) + c, (T)(-w * sh_dp[c][pp]));
   }
 }
 
+// Variant-2 momentum transfer of the MD step just taken, 24 lanes per
+// particle (one per corner and component).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int p = (int)(g / 24);
   if (p >= a.N) return;
+  const int r = (int)(g - 24 * (int64_t)p);
+  const int k = r / 3, c = r - 3 * k;
   const int N = a.N;
-  const int base[3] = {a.rec_cell[p], a.rec_cell[N + p], a.rec_cell[2 * N + p]};
-  if (base[0] < 0) return;
-  T s[3], dp[3];
+  Cube q;
+  q.base[0] = a.rec_cell[p];
+  if (q.base[0] < 0) return;
+  q.base[1] = a.rec_cell[N + p];
+  q.base[2] = a.rec_cell[2 * N + p];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    s[d] = a.rec_frac[d * N + p];
-    dp[d] = a.rec_dp[d * N + p];
-  }
-  int site[8], cx[8], cy[8], cz[8];
-  corner_sites(a.g, base, site, cx, cy, cz);
-  T w[8];
-  corner_weights<T>(s, w);
-  transfer<T>(a, site, w, dp);
+  for (int d = 0; d < 3; ++d) q.s[d] = a.rec_frac[d * N + p];
+  int cx, cy, cz, site;
+  double w;
+  corner_of(q, a.g, k, cx, cy, cz, site, w);
+  atomicAdd(((T*)(a.J + site)) + c, (T)(-w * a.rec_dp[c * N + p]));
 }
 
 template <typename T>
 static CoupleArgs<T> couple_args(Context* c) {
   CoupleArgs<T> a;
   const int N = c->p.n_particles;
-  a.x = (T*)c->x;
-  a.v = (T*)c->v;
+  a.x = (double*)c->x;
+  a.v = (double*)c->v;
   a.img = c->img;
-  a.fcons = (const T*)at(c, c->lay.fcons);
+  a.fcons = (const double*)at(c, c->lay.fcons);
   a.pop = (const T*)at(c, c->lay.pop[c->cur]);
   a.J = (Vec4<T>*)at(c, c->lay.transfer);
   a.mark = (unsigned long long*)at(c, c->lay.mark);
   a.rec_cell = (int32_t*)at(c, c->lay.rec_cell);
-  a.rec_frac = (T*)at(c, c->lay.rec_frac);
-  a.rec_dp = (T*)at(c, c->lay.rec_dp);
+  a.rec_frac = (double*)at(c, c->lay.rec_frac);
+  a.rec_dp = (double*)at(c, c->lay.rec_dp);
+  a.cc = (T*)at(c, c->lay.cc);
+  a.cc_cell = (int32_t*)at(c, c->lay.cc_cell);
+  a.cc_stamp = (int32_t*)at(c, c->lay.cc_stamp);
   a.flags = (int32_t*)at(c, c->lay.flags);
   a.g = c->geom;
   a.N = N;
+  a.stamp = (int)(((uint64_t)c->t_lb & 0x3FFFFFFFu) + 1);
   const double tau = 1.0 / c->p.n_sub;
-  a.rho0 = (T)c->p.rho0;
-  a.gamma = (T)c->p.friction;
-  a.amp = (T)std::sqrt(2.0 * c->p.friction * c->p.kT / tau);
-  a.tau = (T)tau;
-  a.h = (T)(tau / (2.0 * c->p.particle_mass));
-  a.L[0] = (T)c->p.nx;
-  a.L[1] = (T)c->p.ny;
-  a.L[2] = (T)c->p.nz;
+  a.rho0 = c->p.rho0;
+  a.gamma = c->p.friction;
+  a.amp = std::sqrt(2.0 * c->p.friction * c->p.kT / tau);
+  a.tau = tau;
+  a.h = tau / (2.0 * c->p.particle_mass);
+  a.L[0] = (double)c->p.nx;
+  a.L[1] = (double)c->p.ny;
+  a.L[2] = (double)c->p.nz;
   a.key0 = (uint32_t)(c->p.seed & 0xFFFFFFFFu);
   a.key1 = (uint32_t)(c->p.seed >> 32);
   a.step_lo = (uint32_t)((uint64_t)c->t_md & 0xFFFFFFFFu);
@@ -264,11 +388,17 @@ static CoupleArgs<T> couple_args(Context* c) {
 template <typename T>
 static hipError_t couple_t(Context* c) {
   CoupleArgs<T> a = couple_args<T>(c);
+  hipError_t e;
+  if (c->subs == 0) {
+    const int rb = (int)(((int64_t)a.N * kRefillLanes + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_refill<T>, dim3(rb), dim3(kBlock), 0, c->stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int blocks = (a.N + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_couple<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.variant == 1) return e;
-  hipLaunchKernelGGL(k_spread<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
+  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
+  const int sb = (int)(((int64_t)a.N * 24 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_spread<T>, dim3(sb), dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }
 
@@ -277,9 +407,15 @@ hipError_t launch_couple(Context* c) {
   return c->p.precision == 32 ? couple_t<float>(c) : couple_t<double>(c);
 }
 
+// Forget cached corner moments (after the populations or counters were
+// replaced from outside).
+hipError_t invalidate_corner_cache(Context* c) {
+  if (c->p.n_particles == 0) return hipSuccess;
+  return hipMemsetAsync(at(c, c->lay.cc_stamp), 0, sizeof(int32_t) * c->p.n_particles, c->stream);
+}
+
 // Conservative forces at the bound positions (force models 0 and 1).
-template <typename T>
-__global__ void k_const_force(T* __restrict__ f, int N, T fx, T fy, T fz) {
+__global__ void k_const_force(double* __restrict__ f, int N, double fx, double fy, double fz) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= N) return;
   f[p] = fx;
@@ -287,20 +423,17 @@ __global__ void k_const_force(T* __restrict__ f, int N, T fx, T fy, T fz) {
   f[2 * N + p] = fz;
 }
 
-template <typename T>
-static hipError_t init_forces_t(Context* c) {
+hipError_t launch_init_forces(Context* c) {
+  if (c->p.n_particles == 0) return hipSuccess;
   const int N = c->p.n_particles;
   const bool cst = c->p.force_model == 1;
   const int blocks = (N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_const_force<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
-                     (T*)at(c, c->lay.fcons), N, (T)(cst ? c->p.f_ext[0] : 0.0),
-                     (T)(cst ? c->p.f_ext[1] : 0.0), (T)(cst ? c->p.f_ext[2] : 0.0));
-  return hipGetLastError();
-}
-
-hipError_t launch_init_forces(Context* c) {
-  if (c->p.n_particles == 0) return hipSuccess;
-  return c->p.precision == 32 ? init_forces_t<float>(c) : init_forces_t<double>(c);
+  hipLaunchKernelGGL(k_const_force, dim3(blocks), dim3(kBlock), 0, c->stream,
+                     (double*)at(c, c->lay.fcons), N, cst ? c->p.f_ext[0] : 0.0,
+                     cst ? c->p.f_ext[1] : 0.0, cst ? c->p.f_ext[2] : 0.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return invalidate_corner_cache(c);
 }
 
 }  // namespace lbmd_impl

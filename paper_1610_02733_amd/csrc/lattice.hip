@@ -39,9 +39,11 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   int src[19];
   pull_sources(a.g, x, y, z, src);
   const size_t S = (size_t)a.g.S;
+  // every population is read once and written once per step: stream it past
+  // the caches (non-temporal hint) so they keep the transfer and mark data
   T d[19];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = a.src[(size_t)i * S + src[i]];
+  for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(a.src + (size_t)i * S + src[i]);
 
   T Fx = a.k.g[0], Fy = a.k.g[1], Fz = a.k.g[2];
   if ((word >> (r & 63)) & 1ull) {
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   }
   collide_deviation<T>(d, Fx, Fy, Fz, hw, a.k);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) a.dst[(size_t)i * S + r] = d[i];
+  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], a.dst + (size_t)i * S + r);
   if ((r & 63) == 0 && word) a.mark[r >> 6] = 0ull;
 }
 
@@ -130,7 +132,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(const T* __restrict__ pop,
                                                     const Vec4<T>* __restrict__ J, Geom g, T rho0,
                                                     T* __restrict__ rho_out, T* __restrict__ u_out,
-                                                    const T* __restrict__ v, int N,
+                                                    const double* __restrict__ v, int N,
                                                     double* __restrict__ partials) {
   double acc[kRedWidth];
 #pragma unroll
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const T* __restrict__ pop,
   }
   if (v) {
     for (int p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
-      const double a = (double)v[p], b = (double)v[N + p], cc = (double)v[2 * N + p];
+      const double a = v[p], b = v[N + p], cc = v[2 * N + p];
       acc[8] += a;
       acc[9] += b;
       acc[10] += cc;
@@ -195,7 +197,7 @@ static hipError_t moments_t(Context* c, void* d_rho, void* d_u, double* d_totals
   hipLaunchKernelGGL(k_moments<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
                      (const T*)at(c, c->lay.pop[c->cur]), (const Vec4<T>*)at(c, c->lay.transfer),
                      c->geom, (T)c->p.rho0, (T*)d_rho, (T*)d_u,
-                     (const T*)(c->bound ? c->v : nullptr), c->p.n_particles, partials);
+                     (const double*)(c->bound ? c->v : nullptr), c->p.n_particles, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !d_totals) return e;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, partials, blocks, d_totals);

@@ -15,10 +15,13 @@ struct Layout {
   size_t pop[2];     // [19][S] population deviations, pull storage
   size_t transfer;   // [S] Vec4<T>: pending momentum transfer J (x, y, z, unused)
   size_t mark;       // [ceil(S/64)] uint64: bit set <=> J may be non-zero at the site
-  size_t fcons;      // [3][N] conservative force at the current positions
+  size_t fcons;      // [3][N] double: conservative force at the current positions
   size_t rec_cell;   // [3][N] int32: lower corner of the particle's cube (-1: skipped)
-  size_t rec_frac;   // [3][N] T: fractional position inside the cube
-  size_t rec_dp;     // [3][N] T: momentum change dP of the current MD step
+  size_t rec_frac;   // [3][N] double: fractional position inside the cube
+  size_t rec_dp;     // [3][N] double: momentum change dP of the current MD step
+  size_t cc;         // [32][N] T: corner cache, per corner k: 1/rho, jx, jy, jz
+  size_t cc_cell;    // [N] int32: cube (linear index of its lower corner) cached
+  size_t cc_stamp;   // [N] int32: LB step + 1 at which the cache was filled
   size_t flags;      // int32[16]: [0] non-finite particle seen
   size_t partials;   // double[kRedBlocks][kRedWidth]
   size_t totals;     // double[kRedWidth]
@@ -59,5 +62,6 @@ hipError_t launch_set_populations(Context* c, const void* src);
 hipError_t launch_get_transfer(Context* c, void* dst);
 hipError_t launch_couple(Context* c);
 hipError_t launch_init_forces(Context* c);
+hipError_t invalidate_corner_cache(Context* c);
 
 }  // namespace lbmd_impl

@@ -152,8 +152,9 @@ class Lattice:
     # ---- state -----------------------------------------------------------
     def bind_particles(self, x, v, img=None):
         N = self.N
-        self.x = torch.as_tensor(x, dtype=self.dtype, device=self.device).reshape(3, N).contiguous()
-        self.v = torch.as_tensor(v, dtype=self.dtype, device=self.device).reshape(3, N).contiguous()
+        f64 = torch.float64  # particle state is FP64 in both lattice precisions
+        self.x = torch.as_tensor(x, dtype=f64, device=self.device).reshape(3, N).contiguous()
+        self.v = torch.as_tensor(v, dtype=f64, device=self.device).reshape(3, N).contiguous()
         if img is None:
             self.img = torch.zeros((3, N), dtype=torch.int32, device=self.device)
         else:

@@ -53,19 +53,18 @@ def run_pair(lb, orc, shape, cycles, x=None, v=None, dev0=None, **kw):
         g.set_populations(d0)
         o.set_populations(d0.astype(np.float64) + w[:, None] * rho0)
     if N > 0:
-        xs, vs = wl.to_cast(x, dt), wl.to_cast(v, dt)
-        g.bind_particles(xs, vs)
-        o.set_particles(xs, vs)
+        g.bind_particles(x, v)  # particle state is FP64 in both precisions
+        o.set_particles(x, v)
     g.cycle(cycles)
     o.cycle(cycles)
     return g, o, w, rho0
 
 
 def check_particles(g, o, shape, tol, kT, m=1.0):
-    xg = g.x.double().cpu().numpy() + np.asarray(shape, float)[:, None] * g.img.cpu().numpy()
+    xg = g.x.cpu().numpy() + np.asarray(shape, float)[:, None] * g.img.cpu().numpy()
     xo, vo, io = o.particles()
     xo = xo + np.asarray(shape, float)[:, None] * io
-    vg = g.v.double().cpu().numpy()
+    vg = g.v.cpu().numpy()
     assert np.abs(xg - xo).max() <= tol * max(shape), np.abs(xg - xo).max()
     vs = max(np.abs(vo).max(), np.sqrt(kT / m))
     assert np.abs(vg - vo).max() <= tol * vs, np.abs(vg - vo).max() / vs

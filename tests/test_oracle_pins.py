@@ -485,3 +485,27 @@ def test_bond_and_wca_forces_are_gradients(orc):
     assert np.abs(F).max() > 10  # the configuration exercises both force laws
     assert np.allclose(np.mod(x1, 10), xo, atol=1e-10)
     assert np.abs(vo.sum(1)).max() < 1e-14 * np.abs(vo).max() * N  # Newton's third law
+
+
+def test_variant2_stability_bound_for_clustered_particles(orc):
+    """Explicit friction step with the immediate lattice update of variant B:
+    the relative velocity obeys w <- w (1 - gamma tau (1/m + S/rho)),
+    S = sum_k delta_k^2, so at gamma tau / m = 1 two coincident particles next
+    to a site (S ~ 0.86, doubled friction) exceed the bound and diverge in
+    variant 2, while at the cube centre (S = 1/8) they relax; variant 1 (factor
+    1 - gamma tau/m = 0) relaxes in both places.  This is why the 256^3 scale
+    workload, which has ~300 same-cube particle pairs, diverges in variant 2."""
+    def vmax(variant, R):
+        o = orc.Oracle(8, 8, 8, n_sub=10, variant=variant, friction=10.0, n_particles=2)
+        o.set_particles(np.array([R, R]).T.copy(), np.array([[0.01, 0, 0], [0.01, 0, 0]]).T.copy())
+        peak = 0.0
+        for _ in range(2):
+            for _ in range(10):
+                o.md_couple_substep()
+                peak = max(peak, np.abs(o.particles()[1]).max())
+            o.lb_step()
+        return peak
+    assert vmax(2, [3.05, 3.05, 3.05]) > 100 * 0.01  # grows ~1.4x per MD step
+    assert vmax(2, [3.5, 3.5, 3.5]) < 0.01
+    assert vmax(1, [3.05, 3.05, 3.05]) < 0.01
+    assert vmax(1, [3.5, 3.5, 3.5]) < 0.01
