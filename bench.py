@@ -37,6 +37,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(launches_bytes_key="traffic_bytes"):
+    """HBM bytes per collide-stream launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "traffic_collide_stream_scale256_fp32.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    h = hashlib.sha256()
+    for src in ("paper_1610_02733_amd/csrc/lattice.hip", "paper_1610_02733_amd/csrc/lbmd_device.hpp"):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec[launches_bytes_key]
+
+
 def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup):
     shape = cfg["shape"]
     sim = lbmd.Lattice(shape, precision=cfg["precision"], n_sub=cfg["n_sub"], variant=variant,
@@ -147,6 +164,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--variants", default="1,2")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the lattice "
@@ -156,6 +176,18 @@ def main():
     import torch
     from paper_1610_02733_amd import lbmd
     from paper_1610_02733_amd import workloads as wl
+
+    if args.copy_calibration:
+        n = 19 * 256 ** 3  # one FP32 population buffer of the 256^3 lattice
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_dispatch": 4 * n,
+                                               "bytes_written_per_dispatch": 4 * n,
+                                               "dispatches": 5}}), flush=True)
+        return
 
     cfg = dict(wl.CONFIGS["c3"])
     shape = cfg["shape"]
@@ -195,7 +227,8 @@ def main():
         "lb_only_mlups": round(S / (k1_ms * 1e-3) / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "collide_stream (fused pull MRT+noise+Guo)",
+                     "traffic": measured_traffic(),
+                     "kernel": "collide_stream (fused pull MRT+noise+Guo)",
                      "bytes_per_site": bpu, "launch_ms": round(k1_ms, 4)},
         "finite_after_run": {f"variant{vv}": res[vv][2] for vv in res},
     }
