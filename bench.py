@@ -54,12 +54,27 @@ def measured_traffic(launches_bytes_key="traffic_bytes"):
     return rec[launches_bytes_key]
 
 
+WORKLOAD_NAMES = {
+    "c3": "scale-256^3: 256^3 lattice, 1e5 free particles, n=10, gamma=10, kT=1e-4, "
+          "FP32 deviations, variant 2",
+    "c2": "polymer-128^3: 128^3 lattice, 200 chains x 50 beads (harmonic k=30 + WCA, cell "
+          "list), n=10, gamma=20, kT=1, FP32 deviations, variant 2",
+}
+FORCE_KEYS = ("force_model", "chain_len", "k_bond", "r0_bond", "wca_eps", "wca_sigma", "f_ext")
+
+
+def sim_kwargs(cfg, variant):
+    kw = dict(precision=cfg["precision"], n_sub=cfg["n_sub"], variant=variant, kT=cfg["kT"],
+              nu=cfg["nu"], rho0=cfg["rho0"], friction=cfg["friction"],
+              n_particles=cfg["n_particles"], seed=cfg["seed"],
+              particle_mass=cfg["particle_mass"])
+    kw.update({k: cfg[k] for k in FORCE_KEYS if k in cfg})
+    return kw
+
+
 def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup):
     shape = cfg["shape"]
-    sim = lbmd.Lattice(shape, precision=cfg["precision"], n_sub=cfg["n_sub"], variant=variant,
-                       kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"], friction=cfg["friction"],
-                       n_particles=cfg["n_particles"], seed=cfg["seed"],
-                       particle_mass=cfg["particle_mass"])
+    sim = lbmd.Lattice(shape, **sim_kwargs(cfg, variant))
     sim.bind_particles(x, v)
     stream = sim.stream
     L = lbmd.lib()
@@ -82,11 +97,17 @@ def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup):
     for _ in range(warmup):
         cycle()
     torch.cuda.synchronize()
-    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    # HIP events bracket the collide-stream launch of every 4th cycle (an
+    # event pair between kernels costs a few microseconds of idle time)
+    every = 4
+    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, every)]
+    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, every)]
     t0 = time.perf_counter()
     for k in range(steps):
-        cycle(ev_a[k], ev_b[k])
+        if k % every == 0:
+            cycle(ev_a[k // every], ev_b[k // every])
+        else:
+            cycle()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     k1_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev_a, ev_b)]))
@@ -104,10 +125,9 @@ def parity_probe(lbmd, cfg, x, v, nsample=2048):
     sites one by one)."""
     import oracle
     shape = cfg["shape"]
-    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
-              friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
-              particle_mass=cfg["particle_mass"])
-    sim = lbmd.Lattice(shape, precision=cfg["precision"], **kw)
+    kw = sim_kwargs(cfg, 2)
+    prec = kw.pop("precision")
+    sim = lbmd.Lattice(shape, precision=prec, **kw)
     sim.bind_particles(x, v)
     o = oracle.Oracle(*shape, **kw)
     o.set_particles(x, v)
@@ -164,6 +184,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--variants", default="1,2")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"],
+                    help="c3: 256^3, 1e5 free particles (default); c2: 128^3 polymer "
+                         "solution, 200 chains x 50 beads, bonds + WCA")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -189,11 +212,15 @@ def main():
                                                "dispatches": 5}}), flush=True)
         return
 
-    cfg = dict(wl.CONFIGS["c3"])
+    cfg = dict(wl.CONFIGS[args.workload])
     shape = cfg["shape"]
     S = int(np.prod(shape))
-    x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
-                             cfg["seed"])
+    if args.workload == "c2":
+        x, v = wl.chains(shape, cfg["n_particles"] // cfg["chain_len"], cfg["chain_len"],
+                         cfg["kT"], cfg["particle_mass"], cfg["seed"])
+    else:
+        x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
+                                 cfg["seed"])
 
     res = {}
     for variant in [int(t) for t in args.variants.split(",")]:
@@ -219,8 +246,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "scale-256^3: 256^3 lattice, 1e5 free particles, n=10, "
-                               "gamma=10, kT=1e-4, FP32 deviations, variant 2",
+        "config": {"workload": WORKLOAD_NAMES[args.workload],
                    "lattice": list(shape), "particles": cfg["n_particles"],
                    "n_sub": cfg["n_sub"], "variant": main_v},
         "coupled_substeps_per_s": round(cfg["n_sub"] * args.steps / wall, 1),

@@ -562,19 +562,21 @@ static void site_velocity(const orc_ctx *c, int64_t r, double u[3]) {
   }
 }
 
-/* Periodic wrap of a coordinate into [0, L) with image counting.  A value
- * that rounds to exactly L after adding L is left unwrapped at 0. */
+/* Periodic wrap of a coordinate into [0, L) with image counting, for any
+ * displacement: x -= k L with k = floor(x / L).  A value that rounds to
+ * exactly L after the shift is moved to 0 in the next image. */
 static void wrap_position(double *x, int32_t *img, double L) {
+  if (*x >= 0.0 && *x < L) return;
+  double k = floor(*x / L);
+  if (fabs(k) > 1e9) k = copysign(1e9, k); /* keep the image count in range */
+  *x -= k * L;
+  *img += (int32_t)k;
   if (*x >= L) {
     *x -= L;
     *img += 1;
   } else if (*x < 0.0) {
     *x += L;
     *img -= 1;
-    if (*x >= L) {
-      *x -= L;
-      *img += 1;
-    }
   }
 }
 

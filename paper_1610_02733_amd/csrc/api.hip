@@ -30,7 +30,12 @@ bool valid(const lbmd_params* p) {
   if (!(p->nu_bulk < 0.0 || p->nu_bulk > 0.0)) return false;
   if (!(fabs(p->gamma_ghost) < 1.0)) return false;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return false;
-  if (p->force_model < 0 || p->force_model > 1) return false;
+  if (p->force_model < 0 || p->force_model > 2) return false;
+  if (p->force_model == 2) {
+    if (p->chain_len < 1 || (p->n_particles % p->chain_len) != 0) return false;
+    if (!(p->wca_sigma > 0.0) || !(p->wca_eps >= 0.0) || !(p->k_bond >= 0.0)) return false;
+    if (!isfinite(p->r0_bond)) return false;
+  }
   for (int d = 0; d < 3; ++d)
     if (!isfinite(p->body_force[d]) || !isfinite(p->f_ext[d])) return false;
   return true;
@@ -53,6 +58,14 @@ Layout layout(const lbmd_params* p) {
   L.cc = o; o = up(o + 32 * N * t);
   L.cc_cell = o; o = up(o + N * 4);
   L.cc_stamp = o; o = up(o + N * 4);
+  L.fc_held = o; o = up(o + 3 * N * 8);
+  const size_t ncell = (size_t)std::max<int64_t>(force_cells(p), 1);
+  L.bin_count = o; o = up(o + ncell * 4);
+  L.bin_start = o; o = up(o + (ncell + 1) * 4);
+  L.bin_tiles = o; o = up(o + ((ncell + 1023) / 1024 + 1) * 4);
+  L.bin_of = o; o = up(o + N * 4);
+  L.bin_rank = o; o = up(o + N * 4);
+  L.bin_sorted = o; o = up(o + N * 4);
   L.flags = o; o = up(o + 16 * 4);
   L.partials = o; o = up(o + (size_t)kRedBlocks * kRedWidth * 8);
   L.totals = o; o = up(o + kRedWidth * 8);
@@ -150,8 +163,12 @@ int md_couple_substep(lbmd* c) {
   if (c->sticky) return c->sticky;
   if (c->subs >= c->p.n_sub) return LBMD_ESTATE;
   if (c->p.n_particles > 0 && !c->bound) return LBMD_ESTATE;
-  const int rc = fail(c, launch_couple(c));
+  int rc = fail(c, launch_couple(c));
   if (rc) return rc;
+  if (c->p.force_model == 2 && c->p.n_particles > 0) {
+    rc = fail(c, launch_forces_and_kick(c));
+    if (rc) return rc;
+  }
   c->t_md += 1;
   c->subs += 1;
   return LBMD_OK;

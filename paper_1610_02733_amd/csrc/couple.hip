@@ -25,8 +25,10 @@ struct CoupleArgs {
   int32_t* __restrict__ cc_cell;
   int32_t* __restrict__ cc_stamp;
   int32_t* __restrict__ flags;
+  double* __restrict__ fc_held;  // coupling force of the step (split kick)
   Geom g;
   int N;
+  int split_kick;
   int stamp;  // LB step + 1: identifies the post-stream state the cache holds
   double rho0, gamma, amp, tau, h;  // h = tau / (2 m)
   double L[3];
@@ -35,19 +37,21 @@ struct CoupleArgs {
   int noise;
 };
 
-// Periodic wrap with image counting; a value that lands on exactly L after
-// adding L stays at 0 in its old image.
+// Periodic wrap into [0, L) with image counting for any displacement
+// (x -= k L, k = floor(x / L)); a value that rounds to exactly L after the
+// shift moves to 0 in the next image.
 __device__ __forceinline__ void wrap_coord(double& x, int32_t& im, double L) {
+  if (x >= 0.0 && x < L) return;
+  double k = floor(x / L);
+  if (fabs(k) > 1e9) k = copysign(1e9, k);  // keep the image count in range
+  x -= k * L;
+  im += (int32_t)k;
   if (x >= L) {
     x -= L;
     im += 1;
   } else if (x < 0.0) {
     x += L;
     im -= 1;
-    if (x >= L) {
-      x -= L;
-      im += 1;
-    }
   }
 }
 
@@ -270,8 +274,9 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       for (int d = 0; d < 3; ++d)
         xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
     }
-    // velocity Verlet with the coupling force held over the step (force
-    // models 0/1: position-independent conservative force)
+    // velocity Verlet with the coupling force held over the step; with
+    // position-dependent conservative forces the second half-kick waits for
+    // the forces at the new positions (k_kick)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double Fc = -a.gamma * (V[d] - u[d]) + a.amp * xi[d];
@@ -281,7 +286,10 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       V[d] += a.h * (fc + Fc);
       X[d] += a.tau * V[d];
       wrap_coord(X[d], im, a.L[d]);
-      V[d] += a.h * (fc + Fc);
+      if (a.split_kick)
+        a.fc_held[d * N + p] = Fc;
+      else
+        V[d] += a.h * (fc + Fc);
       a.x[d * N + p] = X[d];
       a.v[d * N + p] = V[d];
       a.img[d * N + p] = im;
@@ -363,6 +371,8 @@ static CoupleArgs<T> couple_args(Context* c) {
   a.cc_cell = (int32_t*)at(c, c->lay.cc_cell);
   a.cc_stamp = (int32_t*)at(c, c->lay.cc_stamp);
   a.flags = (int32_t*)at(c, c->lay.flags);
+  a.fc_held = (double*)at(c, c->lay.fc_held);
+  a.split_kick = c->p.force_model == 2 ? 1 : 0;
   a.g = c->geom;
   a.N = N;
   a.stamp = (int)(((uint64_t)c->t_lb & 0x3FFFFFFFu) + 1);
@@ -412,28 +422,6 @@ hipError_t launch_couple(Context* c) {
 hipError_t invalidate_corner_cache(Context* c) {
   if (c->p.n_particles == 0) return hipSuccess;
   return hipMemsetAsync(at(c, c->lay.cc_stamp), 0, sizeof(int32_t) * c->p.n_particles, c->stream);
-}
-
-// Conservative forces at the bound positions (force models 0 and 1).
-__global__ void k_const_force(double* __restrict__ f, int N, double fx, double fy, double fz) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  f[p] = fx;
-  f[N + p] = fy;
-  f[2 * N + p] = fz;
-}
-
-hipError_t launch_init_forces(Context* c) {
-  if (c->p.n_particles == 0) return hipSuccess;
-  const int N = c->p.n_particles;
-  const bool cst = c->p.force_model == 1;
-  const int blocks = (N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_const_force, dim3(blocks), dim3(kBlock), 0, c->stream,
-                     (double*)at(c, c->lay.fcons), N, cst ? c->p.f_ext[0] : 0.0,
-                     cst ? c->p.f_ext[1] : 0.0, cst ? c->p.f_ext[2] : 0.0);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return invalidate_corner_cache(c);
 }
 
 }  // namespace lbmd_impl

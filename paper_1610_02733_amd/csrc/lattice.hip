@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   int src[19];
   pull_sources(a.g, x, y, z, src);
   const size_t S = (size_t)a.g.S;
-  // every population is read once and written once per step: stream it past
-  // the caches (non-temporal hint) so they keep the transfer and mark data
+  // every population is read once per step: non-temporal loads keep the
+  // stream from evicting the transfer field and the mark words
   T d[19];
 #pragma unroll
   for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(a.src + (size_t)i * S + src[i]);
@@ -61,6 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
     hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
   }
   collide_deviation<T>(d, Fx, Fy, Fz, hw, a.k);
+  // every population is written once per step: stream the stores past the
+  // caches (non-temporal hint)
 #pragma unroll
   for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], a.dst + (size_t)i * S + r);
   if ((r & 63) == 0 && word) a.mark[r >> 6] = 0ull;

@@ -22,6 +22,13 @@ struct Layout {
   size_t cc;         // [32][N] T: corner cache, per corner k: 1/rho, jx, jy, jz
   size_t cc_cell;    // [N] int32: cube (linear index of its lower corner) cached
   size_t cc_stamp;   // [N] int32: LB step + 1 at which the cache was filled
+  size_t fc_held;    // [3][N] double: coupling force of the MD step (split kick)
+  size_t bin_count;  // [ncell] int32: particles per force cell
+  size_t bin_start;  // [ncell + 1] int32: exclusive scan of bin_count
+  size_t bin_tiles;  // [ceil(ncell / 1024)] int32: scan tile totals
+  size_t bin_of;     // [N] int32: force cell of each particle (-1: none)
+  size_t bin_rank;   // [N] int32: slot inside the cell
+  size_t bin_sorted; // [N] int32: particles ordered by cell
   size_t flags;      // int32[16]: [0] non-finite particle seen
   size_t partials;   // double[kRedBlocks][kRedWidth]
   size_t totals;     // double[kRedWidth]
@@ -63,5 +70,8 @@ hipError_t launch_get_transfer(Context* c, void* dst);
 hipError_t launch_couple(Context* c);
 hipError_t launch_init_forces(Context* c);
 hipError_t invalidate_corner_cache(Context* c);
+hipError_t launch_forces(Context* c);
+hipError_t launch_forces_and_kick(Context* c);
+int64_t force_cells(const lbmd_params* p);
 
 }  // namespace lbmd_impl

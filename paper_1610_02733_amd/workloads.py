@@ -50,19 +50,37 @@ def free_particles(shape, n, kT, mass, seed):
     return x, v
 
 
-def chains(shape, n_chains, chain_len, kT, mass, seed, bond=1.0):
+def chains(shape, n_chains, chain_len, kT, mass, seed, bond=1.0, min_dist=0.0):
     """Bead-spring chains as random walks of fixed step `bond` from uniform
-    starting points, wrapped into the box; consecutive indices are bonded."""
+    starting points, wrapped into the box; consecutive indices are bonded.
+    With min_dist > 0 a step (or chain start) closer than min_dist to any
+    earlier bead (minimum image) is redrawn."""
     rng = np.random.default_rng(seed)
     L = np.asarray(shape, np.float64)
     x = np.zeros((3, n_chains * chain_len))
+    placed = 0
+
+    def clear(pos):
+        if min_dist <= 0.0 or placed == 0:
+            return True
+        d = x[:, :placed] - pos[:, None]
+        d -= L[:, None] * np.round(d / L[:, None])
+        return np.min(np.sum(d * d, 0)) >= min_dist ** 2
+
     for c in range(n_chains):
-        pos = rng.random(3) * L
+        prev = None
         for b in range(chain_len):
-            if b > 0:
-                d = rng.normal(size=3)
-                pos = pos + bond * d / np.linalg.norm(d)
+            for _ in range(1000):
+                if prev is None:
+                    pos = rng.random(3) * L
+                else:
+                    d = rng.normal(size=3)
+                    pos = prev + bond * d / np.linalg.norm(d)
+                if clear(pos):
+                    break
             x[:, c * chain_len + b] = pos
+            prev = pos
+            placed += 1
     x = np.mod(x, L.reshape(3, 1))
     x = np.minimum(x, np.nextafter(L.reshape(3, 1), 0))
     v = rng.normal(0.0, np.sqrt(kT / mass) if kT > 0 else 0.0, x.shape)

@@ -206,3 +206,46 @@ def test_error_codes(lb):
     assert ei.value.code == lb.ENONFINITE
     assert np.isfinite(g.populations().cpu().numpy()).all()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_polymer_forces_coupled(lb, orc, prec, variant):
+    """Bead-spring chains (harmonic bonds + WCA through the GPU cell list)
+    coupled to the fluid, against the oracle's all-pairs forces: 20^3 lattice,
+    12 chains x 10 beads, tau_MD = 0.02 (stable for WCA), 10 LB steps."""
+    shape = (20, 20, 20)
+    x, v = wl.chains(shape, 12, 10, 1e-3, 1.0, seed=31, bond=0.97, min_dist=0.95)
+    kw = dict(kT=1e-3, seed=8, n_particles=120, friction=1.0, n_sub=50, variant=variant,
+              force_model=2, chain_len=10, k_bond=30.0, r0_bond=1.0, wca_eps=1.0, wca_sigma=1.0)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 10, x=x, v=v, precision=prec, **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < TOL[prec], err
+    check_particles(g, o, shape, TOL[prec] * 10, 1e-3)
+
+
+def test_polymer_small_box_cell_grid(lb, orc):
+    """A box narrower than three WCA cells per axis (cell stencil must not
+    visit a cell twice), FP64."""
+    shape = (3, 4, 3)
+    x, v = wl.chains(shape, 2, 4, 1e-3, 1.0, seed=5, bond=0.97, min_dist=0.9)
+    kw = dict(kT=0.0, seed=8, n_particles=8, friction=0.5, n_sub=50, variant=2,
+              force_model=2, chain_len=4, k_bond=30.0, r0_bond=1.0, wca_eps=1.0, wca_sigma=1.0)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 4, x=x, v=v, precision=64, **kw)
+    check_particles(g, o, shape, 1e-12, 1e-3)
+
+
+def test_fast_particles_wrap(lb, orc):
+    """Displacements of several box lengths per MD step: positions stay in
+    [0, L), image counters agree with the oracle (FP64)."""
+    shape = (8, 6, 5)
+    rng = np.random.default_rng(12)
+    x = rng.random((3, 10)) * np.array(shape, float)[:, None]
+    v = rng.uniform(-40, 40, (3, 10))
+    kw = dict(kT=0.0, seed=2, n_particles=10, friction=0.05, n_sub=2, variant=2)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 3, x=x, v=v, precision=64, **kw)
+    xo, vo, io = o.particles()
+    assert (g.img.cpu().numpy() == io).all()
+    check_particles(g, o, shape, 1e-12, 1.0)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < 1e-12, err

@@ -509,3 +509,17 @@ def test_variant2_stability_bound_for_clustered_particles(orc):
     assert vmax(2, [3.5, 3.5, 3.5]) < 0.01
     assert vmax(1, [3.05, 3.05, 3.05]) < 0.01
     assert vmax(1, [3.5, 3.5, 3.5]) < 0.01
+
+
+def test_wrap_any_displacement(orc):
+    """Periodic wrap keeps x in [0, L) and counts images for displacements of
+    several box lengths in one MD step; the unwrapped path is x + L img."""
+    o = orc.Oracle(4, 5, 6, n_sub=2, variant=1, friction=0.0, n_particles=2)
+    x0 = np.array([[1.5, 3.9], [0.2, 4.99], [5.5, 0.0]])
+    v0 = np.array([[20.0, -33.0], [-7.3, 0.0], [1e-3, -2.0]])
+    o.set_particles(x0, v0)
+    o.md_couple_substep()
+    x, v, img = o.particles()
+    L = np.array([[4.0], [5.0], [6.0]])
+    assert (x >= 0).all() and (x < L).all()
+    assert np.allclose(x + L * img, x0 + 0.5 * v0, rtol=0, atol=1e-12)
