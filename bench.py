@@ -153,6 +153,67 @@ def parity_probe(lbmd, cfg, x, v, nsample=2048):
                 ok=bool(max(perr, xerr, verr) < tol))
 
 
+def batch_measure(lbmd, torch, nrep=512, cycles=20, serial_cycles=2):
+    """Batched ensemble: nrep independent replicas (edges in {24,32,40,48},
+    20..400 free particles, gamma in [1,20], kT=1e-3, n=5, FP32, variant 2)
+    in one batch (captured cycles, autotuned launch shapes) against the same
+    replicas as separate systems launched one after another."""
+    import tempfile
+    from paper_1610_02733_amd import workloads as wl
+    edges, nps, gammas = wl.batch_replicas(nrep, seed=4)
+    reps, xs, vs = [], [], []
+    for r in range(nrep):
+        shape = (int(edges[r]),) * 3
+        kw = dict(precision=32, n_sub=5, variant=2, kT=1e-3, nu=1.0 / 6.0, seed=4, replica=r,
+                  n_particles=int(nps[r]), friction=float(gammas[r]), particle_mass=1.0)
+        x, v = wl.free_particles(shape, int(nps[r]), 1e-3, 1.0, 4000 + r)
+        reps.append((shape, kw))
+        xs.append(x)
+        vs.append(v)
+    sites = int(sum(int(e) ** 3 for e in edges))
+    B = lbmd.Batch(reps)
+    B.bind_particles(xs, vs)
+    tune = B.autotune(os.path.join(tempfile.gettempdir(), "lbmd_autotune.json"))
+    B.run_cycles(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.run_cycles(cycles)
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) / cycles
+    tot = B.moments()
+    T = 2 * tot[:, 10] / (3 * np.maximum(nps, 1)) / 1e-3
+    ok = np.isfinite(T)
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    sims = []
+    for r in range(nrep):
+        s = lbmd.Lattice(reps[r][0], **reps[r][1])
+        s.bind_particles(xs[r], vs[r])
+        sims.append(s)
+    for s in sims:
+        s.cycle(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(serial_cycles):
+        for s in sims:
+            s.cycle(1)
+    torch.cuda.synchronize()
+    serial = (time.perf_counter() - t0) / serial_cycles
+    for s in sims:
+        s.close()
+    del sims
+    torch.cuda.empty_cache()
+    return dict(replicas=nrep, sites=sites, particles=int(nps.sum()),
+                batched_ms_per_cycle=round(batched * 1e3, 3),
+                serial_ms_per_cycle=round(serial * 1e3, 3),
+                speedup=round(serial / batched, 2),
+                batched_mlups=round(sites / batched / 1e6, 1),
+                autotune=tune, cycles_after_warmup=cycles + 2,
+                finite_replicas=int(ok.sum()),
+                mean_T_over_kT_finite=round(float(np.mean(T[ok])), 4) if ok.any() else None)
+
+
 def cpu_baseline(cfg, x_density_seed=3, nz=32, cycles=4):
     """FP64 oracle, single thread, on a 256 x 256 x nz slab of the workload
     (same per-site work, same particle density and parameters)."""
@@ -187,6 +248,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"],
                     help="c3: 256^3, 1e5 free particles (default); c2: 128^3 polymer "
                          "solution, 200 chains x 50 beads, bonds + WCA")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-replica batched-ensemble measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -261,6 +324,9 @@ def main():
     if 1 in res and 2 in res:
         out["variant1_ms_per_step"] = round(res[1][0] / args.steps * 1e3, 4)
         out["variant2_over_variant1"] = round(res[2][0] / res[1][0], 4)
+    if not args.no_batch:
+        log("batched ensemble: 512 replicas, batched vs serial")
+        out["batch"] = batch_measure(lbmd, torch)
     if not args.no_parity:
         log("parity probe: one cycle vs the FP64 oracle (sampled sites, all particles)")
         out["parity"] = parity_probe(lbmd, cfg, x, v)

@@ -171,6 +171,50 @@ int lbmd_set_counters(lbmd *c, int64_t t_lb, int64_t t_md, int32_t subs);
 /* Message for a status code. */
 const char *lbmd_strerror(int code);
 
+/*
+ * Captured cycles.  Runs ncycles coupled cycles (n_sub md_couple_substep()
+ * steps and one lb_step() each, the schedule of Sec. 3 / Fig. 2) by replaying
+ * one HIP graph of the cycle on the context's stream; identical in effect to
+ * the step-by-step calls.  The graph is captured on first use and again after
+ * lbmd_bind_particles() or lbmd_autotune().  Must start at an LB-step
+ * boundary (LBMD_ESTATE otherwise).  Asynchronous.
+ */
+int lbmd_run_cycles(lbmd *c, int32_t ncycles);
+
+/*
+ * Batched replicas: n_rep independent periodic systems, each described by its
+ * own lbmd_params (box size, particle count, friction, kT, seed, replica id
+ * ...), advanced in lockstep by the same calls as a single system, every
+ * kernel covering all replicas in one launch.  They must share n_sub,
+ * precision and variant (LBMD_EINVAL otherwise).  A replica draws the noise
+ * of a single system created with the same seed and replica id, so its
+ * trajectory is that system's trajectory.  Lattices are stored one after
+ * the other; particle arrays bound with lbmd_bind_particles() are the
+ * replicas' [3][N_r] arrays concatenated along the particle axis (row x of
+ * all replicas, then y, then z; replica order, N = sum of N_r).
+ */
+size_t lbmd_batch_workspace_bytes(const lbmd_params *per_rep, int32_t n_rep);
+int lb_create_batch(const lbmd_params *per_rep, int32_t n_rep, void *d_ws, size_t ws_bytes,
+                    void *hip_stream, lbmd **out);
+int lbmd_replica_count(lbmd *c);
+/* totals of every replica, host double[n_rep][LBMD_NTOTALS]; synchronizes */
+int lbmd_batch_moments(lbmd *c, double *h_totals);
+/* per-replica versions of the population / transfer copies (replica rep) */
+int lbmd_batch_get_populations(lbmd *c, int32_t rep, void *d_dst);
+int lbmd_batch_set_populations(lbmd *c, int32_t rep, const void *d_src);
+int lbmd_batch_get_transfer(lbmd *c, int32_t rep, void *d_dst);
+
+/*
+ * Launch-shape autotuner: times candidate persistent-grid sizes of the LB
+ * kernels and of the particle kernels on this context, keeps the fastest and
+ * caches them in a JSON file at cache_path (nullable: no cache), keyed by
+ * device architecture, precision, variant, replica count and size class.
+ * Must run at an LB-step boundary (LBMD_ESTATE otherwise); the simulation
+ * state is left unchanged.  Synchronizes.  Outputs (nullable): the chosen
+ * block counts (0 = one block per work item).
+ */
+int lbmd_autotune(lbmd *c, const char *cache_path, int32_t *lb_blocks, int32_t *part_blocks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,27 +1,35 @@
-// C ABI entry points: parameter checks, workspace carving, step bookkeeping.
+// C ABI entry points: parameter checks, workspace carving, per-replica
+// tables, step bookkeeping, captured cycles and the launch-shape autotuner.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
+#include <string>
 
 #include "lbmd_internal.hpp"
 
 using namespace lbmd_impl;
 
-struct lbmd : Context {};
+struct lbmd : Context {
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph_def = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
 
 namespace {
 
 constexpr size_t kAlign = 256;
 size_t up(size_t a) { return (a + kAlign - 1) / kAlign * kAlign; }
 
-bool valid(const lbmd_params* p) {
+bool valid_one(const lbmd_params* p) {
   if (!p) return false;
   if (p->nx < 2 || p->ny < 2 || p->nz < 2) return false;
   const int64_t S = (int64_t)p->nx * p->ny * p->nz;
-  if (S > (int64_t)0x7FFFFFFF - 64) return false;
+  if (S > (int64_t)0x3FFFFFFF) return false;
   if (p->n_sub < 1) return false;
   if (p->variant != 1 && p->variant != 2) return false;
   if (p->precision != 32 && p->precision != 64) return false;
@@ -41,59 +49,166 @@ bool valid(const lbmd_params* p) {
   return true;
 }
 
-Layout layout(const lbmd_params* p) {
-  Layout L;
-  const size_t S = (size_t)p->nx * p->ny * p->nz;
-  const size_t N = (size_t)std::max(p->n_particles, 1);
-  const size_t t = p->precision == 32 ? 4 : 8;
+// Replicas advance in lockstep through shared kernels: they must agree on
+// the time-scale contrast, the precision and the coupling variant.
+bool valid_set(const lbmd_params* p, int32_t R) {
+  if (!p || R < 1 || R > (1 << 20)) return false;
+  int64_t S = 0, N = 0, C = 0;
+  for (int r = 0; r < R; ++r) {
+    if (!valid_one(p + r)) return false;
+    if (p[r].n_sub != p[0].n_sub || p[r].precision != p[0].precision ||
+        p[r].variant != p[0].variant)
+      return false;
+    S += ((int64_t)p[r].nx * p[r].ny * p[r].nz + 63) / 64 * 64;
+    N += p[r].n_particles;
+    C += force_cells(p + r);
+  }
+  return S < (int64_t)0x7FFFFFFF - 256 && N < (int64_t)0x7FFFFFFF / 32 &&
+         C < (int64_t)0x7FFFFFFF - 1;
+}
+
+Plan make_plan(const lbmd_params* p, int32_t R) {
+  Plan pl;
+  pl.R = R;
+  pl.prec = p[0].precision;
+  pl.n_sub = p[0].n_sub;
+  pl.Stot = pl.Ntot = pl.Ctot = 0;
+  pl.nitems = 0;
+  pl.any_forces2 = false;
+  for (int r = 0; r < R; ++r) {
+    const int64_t S = (int64_t)p[r].nx * p[r].ny * p[r].nz;
+    pl.site_off.push_back(pl.Stot);
+    pl.part_off.push_back(pl.Ntot);
+    pl.cell_off.push_back(pl.Ctot);
+    pl.item_off.push_back(pl.nitems);
+    pl.Stot += (S + 63) / 64 * 64;
+    pl.Ntot += p[r].n_particles;
+    pl.Ctot += force_cells(p + r);
+    pl.nitems += (int)((S + kBlock - 1) / kBlock);
+    pl.any_forces2 = pl.any_forces2 || (p[r].force_model == 2 && p[r].n_particles > 0);
+  }
+  pl.item_off.push_back(pl.nitems);
+  Layout& L = pl.lay;
+  const size_t S = (size_t)pl.Stot, N = (size_t)std::max<int64_t>(pl.Ntot, 1);
+  const size_t C = (size_t)std::max<int64_t>(pl.Ctot, 1);
+  const size_t t = pl.prec == 32 ? 4 : 8;
   size_t o = 0;
   L.pop[0] = o; o = up(o + 19 * S * t);
   L.pop[1] = o; o = up(o + 19 * S * t);
   L.transfer = o; o = up(o + 4 * S * t);
-  L.mark = o; o = up(o + ((S + 63) / 64) * 8);
+  L.mark = o; o = up(o + (S / 64) * 8);
+  L.rep_lb = o; o = up(o + (size_t)R * (pl.prec == 32 ? sizeof(RepLB<float>) : sizeof(RepLB<double>)));
+  L.rep_md = o; o = up(o + (size_t)R * sizeof(RepMD));
+  L.item_rep = o; o = up(o + (size_t)(R + 1) * 4);
+  L.part_rep = o; o = up(o + N * 4);
+  L.clock = o; o = up(o + sizeof(Clock));
   L.fcons = o; o = up(o + 3 * N * 8);
   L.rec_cell = o; o = up(o + 3 * N * 4);
   L.rec_frac = o; o = up(o + 3 * N * 8);
   L.rec_dp = o; o = up(o + 3 * N * 8);
+  L.fc_held = o; o = up(o + 3 * N * 8);
   L.cc = o; o = up(o + 32 * N * t);
   L.cc_cell = o; o = up(o + N * 4);
   L.cc_stamp = o; o = up(o + N * 4);
-  L.fc_held = o; o = up(o + 3 * N * 8);
-  const size_t ncell = (size_t)std::max<int64_t>(force_cells(p), 1);
-  L.bin_count = o; o = up(o + ncell * 4);
-  L.bin_start = o; o = up(o + (ncell + 1) * 4);
-  L.bin_tiles = o; o = up(o + ((ncell + 1023) / 1024 + 1) * 4);
+  L.bin_count = o; o = up(o + C * 4);
+  L.bin_start = o; o = up(o + (C + 1) * 4);
+  L.bin_tiles = o; o = up(o + ((C + 1023) / 1024 + 1) * 4);
   L.bin_of = o; o = up(o + N * 4);
   L.bin_rank = o; o = up(o + N * 4);
   L.bin_sorted = o; o = up(o + N * 4);
   L.flags = o; o = up(o + 16 * 4);
-  L.partials = o; o = up(o + (size_t)kRedBlocks * kRedWidth * 8);
-  L.totals = o; o = up(o + kRedWidth * 8);
+  L.partials = o; o = up(o + (size_t)pl.nitems * kRedWidth * 8);
+  L.totals = o; o = up(o + (size_t)R * kRedWidth * 8);
   L.total = o;
-  return L;
+  return pl;
 }
 
 // Mode norms b_k of the D3Q19 basis, k = 4..18 (stress, then kinetic modes).
 const double kNorm[15] = {2.0 / 3, 4.0 / 3, 4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3,
                           2.0 / 3, 2.0 / 9, 2.0 / 9, 2.0 / 9, 2.0,     4.0 / 3, 4.0 / 9};
 
-void derive(Context* c) {
-  const lbmd_params& p = c->p;
-  c->gs = (6.0 * p.nu - 1.0) / (6.0 * p.nu + 1.0);
-  c->gb = p.nu_bulk < 0.0 ? c->gs : (9.0 * p.nu_bulk - 1.0) / (9.0 * p.nu_bulk + 1.0);
-  c->gg = p.gamma_ghost;
-  c->mu = 3.0 * p.kT;
+Geom geom_of(const lbmd_params& p) {
+  Geom g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.S = p.nx * p.ny * p.nz;
+  g.inv_nx = 1.0 / p.nx;
+  g.inv_ny = 1.0 / p.ny;
+  return g;
+}
+
+template <typename T>
+RepLB<T> rep_lb(const Context* c, int r) {
+  const lbmd_params& p = c->p[r];
+  RepLB<T> q;
+  q.g = geom_of(p);
+  q.site_off = (int)c->plan.site_off[r];
+  q.item_off = (int)c->plan.item_off[r];
+  q.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  q.key1 = (uint32_t)(p.seed >> 32);
+  q.tag0 = lbmd_dev::noise_tag(lbmd_dev::kPurposeFluid, p.replica, 0);
+  q.tag1 = lbmd_dev::noise_tag(lbmd_dev::kPurposeFluid, p.replica, 1);
+  const double gs = (6.0 * p.nu - 1.0) / (6.0 * p.nu + 1.0);
+  const double gb = p.nu_bulk < 0.0 ? gs : (9.0 * p.nu_bulk - 1.0) / (9.0 * p.nu_bulk + 1.0);
+  const double gg = p.gamma_ghost;
+  q.k.rho0 = (T)p.rho0;
+  q.k.gs = (T)gs;
+  q.k.gb = (T)gb;
+  q.k.gg = (T)gg;
+  q.k.hs = (T)(0.5 * (1.0 + gs));
+  q.k.hb = (T)(0.5 * (1.0 + gb));
+  q.k.mu = (T)(3.0 * p.kT);
   for (int v = 0; v < 15; ++v) {
     const int k = v + 4;
-    const double g = k == 4 ? c->gb : (k <= 9 ? c->gs : c->gg);
-    c->ns[v] = sqrt(kNorm[v] * (1.0 - g * g)) * sqrt(12.0) / 65536.0;
+    const double g = k == 4 ? gb : (k <= 9 ? gs : gg);
+    q.k.ns[v] = (T)(sqrt(kNorm[v] * (1.0 - g * g)) * sqrt(12.0) / 65536.0);
   }
-  c->geom.nx = p.nx;
-  c->geom.ny = p.ny;
-  c->geom.nz = p.nz;
-  c->geom.S = (int)c->S;
-  c->geom.inv_nx = 1.0 / p.nx;
-  c->geom.inv_ny = 1.0 / p.ny;
+  for (int d = 0; d < 3; ++d) q.k.g[d] = (T)p.body_force[d];
+  q.k.noise = p.kT > 0.0 ? 1 : 0;
+  return q;
+}
+
+RepMD rep_md(const Context* c, int r) {
+  const lbmd_params& p = c->p[r];
+  RepMD m;
+  memset(&m, 0, sizeof(m));
+  m.g = geom_of(p);
+  m.site_off = (int)c->plan.site_off[r];
+  m.part_off = (int)c->plan.part_off[r];
+  m.N = p.n_particles;
+  m.cell_off = (int)c->plan.cell_off[r];
+  m.variant = p.variant;
+  m.noise = (p.kT > 0.0 && p.friction > 0.0) ? 1 : 0;
+  m.split_kick = p.force_model == 2 ? 1 : 0;
+  m.force_model = p.force_model;
+  m.chain_len = p.force_model == 2 ? p.chain_len : 1;
+  m.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  m.key1 = (uint32_t)(p.seed >> 32);
+  m.tag = lbmd_dev::noise_tag(lbmd_dev::kPurposeParticle, p.replica, 0);
+  const double tau = 1.0 / p.n_sub;
+  m.rho0 = p.rho0;
+  m.gamma = p.friction;
+  m.amp = sqrt(2.0 * p.friction * p.kT / tau);
+  m.tau = tau;
+  m.h = p.n_particles > 0 ? tau / (2.0 * p.particle_mass) : 0.0;
+  m.L[0] = p.nx;
+  m.L[1] = p.ny;
+  m.L[2] = p.nz;
+  for (int d = 0; d < 3; ++d) m.f_ext[d] = p.f_ext[d];
+  m.k_bond = p.k_bond;
+  m.r0_bond = p.r0_bond;
+  m.wca_eps = p.wca_eps;
+  m.wca_sigma = p.wca_sigma;
+  const double rc = pow(2.0, 1.0 / 6.0) * p.wca_sigma;
+  const int Ls[3] = {p.nx, p.ny, p.nz};
+  for (int d = 0; d < 3; ++d) {
+    int n = (int)floor((double)Ls[d] / rc);
+    n = n < 1 ? 1 : n;
+    m.nb[d] = n;
+    m.inv_edge[d] = (double)n / (double)Ls[d];
+  }
+  return m;
 }
 
 int fail(Context* c, hipError_t e) {
@@ -102,38 +217,88 @@ int fail(Context* c, hipError_t e) {
   return LBMD_EHIP;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t lbmd_workspace_bytes(const lbmd_params* p) {
-  if (!valid(p)) return 0;
-  return layout(p).total;
+// Per-replica tables and the clock, uploaded once at creation.
+hipError_t upload_tables(Context* c) {
+  const Plan& pl = c->plan;
+  const int R = pl.R;
+  hipError_t e;
+  if (pl.prec == 32) {
+    std::vector<RepLB<float>> lb(R);
+    for (int r = 0; r < R; ++r) lb[r] = rep_lb<float>(c, r);
+    e = hipMemcpyAsync(at(c, pl.lay.rep_lb), lb.data(), sizeof(RepLB<float>) * R,
+                       hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    std::vector<RepLB<double>> lb(R);
+    for (int r = 0; r < R; ++r) lb[r] = rep_lb<double>(c, r);
+    e = hipMemcpyAsync(at(c, pl.lay.rep_lb), lb.data(), sizeof(RepLB<double>) * R,
+                       hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) return e;
+  std::vector<RepMD> md(R);
+  for (int r = 0; r < R; ++r) md[r] = rep_md(c, r);
+  std::vector<int32_t> items(pl.item_off.begin(), pl.item_off.end());
+  std::vector<int32_t> prep((size_t)std::max<int64_t>(pl.Ntot, 1), 0);
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < c->p[r].n_particles; ++q) prep[pl.part_off[r] + q] = r;
+  Clock clk{0, 0, 0, 0};
+  if ((e = hipMemcpyAsync(at(c, pl.lay.rep_md), md.data(), sizeof(RepMD) * R,
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(at(c, pl.lay.item_rep), items.data(), sizeof(int32_t) * items.size(),
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(at(c, pl.lay.part_rep), prep.data(), sizeof(int32_t) * prep.size(),
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(at(c, pl.lay.clock), &clk, sizeof(clk), hipMemcpyHostToDevice,
+                          c->stream)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(c->stream);
 }
 
-int lb_create(const lbmd_params* p, void* d_ws, size_t ws_bytes, void* hip_stream, lbmd** out) {
+hipError_t write_clock(Context* c) {
+  Clock clk{(long long)c->t_lb, (long long)(c->t_md - c->subs), c->cur, 0};
+  hipError_t e = hipMemcpyAsync(at(c, c->plan.lay.clock), &clk, sizeof(clk), hipMemcpyHostToDevice,
+                                c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+void drop_graph(lbmd* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph_def) (void)hipGraphDestroy(c->graph_def);
+  c->graph_exec = nullptr;
+  c->graph_def = nullptr;
+}
+
+int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* hip_stream,
+           lbmd** out) {
   if (!out) return LBMD_EINVAL;
   *out = nullptr;
-  if (!valid(p) || !d_ws || ((uintptr_t)d_ws % kAlign) != 0) return LBMD_EINVAL;
-  const Layout L = layout(p);
-  if (ws_bytes < L.total) return LBMD_ENOSPACE;
+  if (!valid_set(p, R) || !d_ws || ((uintptr_t)d_ws % kAlign) != 0) return LBMD_EINVAL;
+  Plan pl = make_plan(p, R);
+  if (ws_bytes < pl.lay.total) return LBMD_ENOSPACE;
   lbmd* c = new (std::nothrow) lbmd();
   if (!c) return LBMD_EINVAL;
-  c->p = *p;
-  c->lay = L;
+  c->p.assign(p, p + R);
+  c->plan = pl;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_ws;
-  c->S = (int64_t)p->nx * p->ny * p->nz;
-  c->cur = 0;
   c->x = c->v = nullptr;
   c->img = nullptr;
   c->bound = false;
   c->t_lb = c->t_md = 0;
   c->subs = 0;
+  c->cur = 0;
   c->sticky = LBMD_OK;
-  derive(c);
+  c->tune.lb_blocks = 0;
+  c->tune.part_blocks = 0;
+  c->graph_ok = false;
   // fluid at rest (all deviations zero), nothing transferred yet
-  hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+  hipError_t e = hipMemsetAsync(c->ws, 0, pl.lay.total, c->stream);
+  if (e == hipSuccess) e = upload_tables(c);
   if (e != hipSuccess) {
     delete c;
     return LBMD_EHIP;
@@ -142,33 +307,70 @@ int lb_create(const lbmd_params* p, void* d_ws, size_t ws_bytes, void* hip_strea
   return LBMD_OK;
 }
 
+int check_rep(lbmd* c, int32_t rep) {
+  if (!c || rep < 0 || rep >= c->plan.R) return LBMD_EINVAL;
+  return c->sticky;
+}
+
+// One MD step of every replica (no host-side checks).
+hipError_t substep_launches(Context* c, int substep) {
+  hipError_t e = launch_couple(c, substep);
+  if (e == hipSuccess && c->plan.any_forces2) e = launch_forces_and_kick(c);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbmd_workspace_bytes(const lbmd_params* p) {
+  if (!valid_set(p, 1)) return 0;
+  return make_plan(p, 1).lay.total;
+}
+
+size_t lbmd_batch_workspace_bytes(const lbmd_params* per_rep, int32_t n_rep) {
+  if (!valid_set(per_rep, n_rep)) return 0;
+  return make_plan(per_rep, n_rep).lay.total;
+}
+
+int lb_create(const lbmd_params* p, void* d_ws, size_t ws_bytes, void* hip_stream, lbmd** out) {
+  return create(p, 1, d_ws, ws_bytes, hip_stream, out);
+}
+
+int lb_create_batch(const lbmd_params* per_rep, int32_t n_rep, void* d_ws, size_t ws_bytes,
+                    void* hip_stream, lbmd** out) {
+  return create(per_rep, n_rep, d_ws, ws_bytes, hip_stream, out);
+}
+
 int lb_destroy(lbmd* c) {
+  if (!c) return LBMD_OK;
+  drop_graph(c);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   delete c;
   return LBMD_OK;
 }
 
+int lbmd_replica_count(lbmd* c) { return c ? c->plan.R : LBMD_EINVAL; }
+
 int lbmd_bind_particles(lbmd* c, void* d_x, void* d_v, int32_t* d_img) {
   if (!c) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  if (c->p.n_particles > 0 && (!d_x || !d_v || !d_img)) return LBMD_EINVAL;
+  if (c->plan.Ntot > 0 && (!d_x || !d_v || !d_img)) return LBMD_EINVAL;
   c->x = d_x;
   c->v = d_v;
   c->img = d_img;
-  c->bound = c->p.n_particles > 0;
+  c->bound = c->plan.Ntot > 0;
+  drop_graph(c);
   return fail(c, launch_init_forces(c));
 }
 
 int md_couple_substep(lbmd* c) {
   if (!c) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  if (c->subs >= c->p.n_sub) return LBMD_ESTATE;
-  if (c->p.n_particles > 0 && !c->bound) return LBMD_ESTATE;
-  int rc = fail(c, launch_couple(c));
+  if (c->subs >= c->plan.n_sub) return LBMD_ESTATE;
+  if (c->plan.Ntot > 0 && !c->bound) return LBMD_ESTATE;
+  const int rc = fail(c, substep_launches(c, c->subs));
   if (rc) return rc;
-  if (c->p.force_model == 2 && c->p.n_particles > 0) {
-    rc = fail(c, launch_forces_and_kick(c));
-    if (rc) return rc;
-  }
   c->t_md += 1;
   c->subs += 1;
   return LBMD_OK;
@@ -177,8 +379,9 @@ int md_couple_substep(lbmd* c) {
 int lb_step(lbmd* c) {
   if (!c) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  if (c->p.n_particles > 0 && c->subs != c->p.n_sub) return LBMD_ESTATE;
-  const int rc = fail(c, launch_collide_stream(c));
+  if (c->plan.Ntot > 0 && c->subs != c->plan.n_sub) return LBMD_ESTATE;
+  int rc = fail(c, launch_collide_stream(c));
+  if (!rc) rc = fail(c, launch_clock_advance(c));
   if (rc) return rc;
   c->cur = 1 - c->cur;
   c->t_lb += 1;
@@ -186,54 +389,124 @@ int lb_step(lbmd* c) {
   return LBMD_OK;
 }
 
-int lb_moments(lbmd* c, void* d_rho, void* d_u, double* h_totals) {
-  if (!c) return LBMD_EINVAL;
+int lbmd_run_cycles(lbmd* c, int32_t ncycles) {
+  if (!c || ncycles < 0) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  double* d_tot = h_totals ? (double*)at(c, c->lay.totals) : nullptr;
-  int rc = fail(c, launch_moments(c, d_rho, d_u, d_tot));
-  if (rc || !h_totals) return rc;
-  double tot[kRedWidth];
-  int32_t flags[16];
-  rc = fail(c, hipMemcpyAsync(tot, d_tot, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
-  if (rc) return rc;
-  rc = fail(c, hipMemcpyAsync(flags, at(c, c->lay.flags), sizeof(flags), hipMemcpyDeviceToHost,
-                              c->stream));
-  if (rc) return rc;
-  rc = fail(c, hipStreamSynchronize(c->stream));
-  if (rc) return rc;
-  const double m = c->p.particle_mass;
-  h_totals[LBMD_TOT_MASS] = c->p.rho0 * (double)c->S + tot[0];
-  for (int d = 0; d < 3; ++d) {
-    h_totals[LBMD_TOT_PFLUID + d] = tot[1 + d] + tot[4 + d];
-    h_totals[LBMD_TOT_PSEEN + d] = tot[1 + d] + (c->p.variant == 2 ? tot[4 + d] : 0.0);
-    h_totals[LBMD_TOT_PPART + d] = m * tot[8 + d];
+  if (c->subs != 0) return LBMD_ESTATE;
+  if (c->plan.Ntot > 0 && !c->bound) return LBMD_ESTATE;
+  if (ncycles == 0) return LBMD_OK;
+  const int n = c->plan.Ntot > 0 ? c->plan.n_sub : 0;
+  if (!c->graph_exec) {
+    // capture one cycle (n MD steps + one LB step) on a private stream; the
+    // kernels read the step clock from device memory, so the same graph
+    // serves every cycle
+    if (!c->capture_stream) {
+      int rc = fail(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+      if (rc) return rc;
+    }
+    hipStream_t user = c->stream;
+    c->stream = c->capture_stream;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    const int32_t saved_subs = c->subs;
+    for (int s = 0; s < n && e == hipSuccess; ++s) e = substep_launches(c, s);
+    c->subs = n;  // MD steps the clock advance accounts for
+    if (e == hipSuccess) e = launch_collide_stream(c);
+    if (e == hipSuccess) e = launch_clock_advance(c);
+    c->subs = saved_subs;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    c->stream = user;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    c->graph_def = g;
+    int rc = fail(c, e);
+    if (rc) {
+      drop_graph(c);
+      return rc;
+    }
   }
-  h_totals[LBMD_TOT_KEPART] = 0.5 * m * tot[11];
-  h_totals[LBMD_TOT_U2FLUID] = tot[7] / (double)c->S;
-  h_totals[LBMD_TOT_TLB] = (double)c->t_lb;
-  h_totals[LBMD_TOT_TMD] = (double)c->t_md;
+  for (int32_t k = 0; k < ncycles; ++k) {
+    int rc = fail(c, hipGraphLaunch(c->graph_exec, c->stream));
+    if (rc) return rc;
+  }
+  c->t_lb += ncycles;
+  c->t_md += (int64_t)ncycles * n;
+  if (ncycles & 1) c->cur = 1 - c->cur;
+  return LBMD_OK;
+}
+
+static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* h_totals,
+                          int all) {
+  int rc = check_rep(c, rep);
+  if (rc) return rc;
+  const int R = c->plan.R;
+  double* d_tot = h_totals ? (double*)at(c, c->plan.lay.totals) : nullptr;
+  rc = fail(c, launch_moments(c, rep, d_rho, d_u, d_tot));
+  if (rc || !h_totals) return rc;
+  std::vector<double> tot((size_t)R * kRedWidth);
+  int32_t flags[16];
+  rc = fail(c, hipMemcpyAsync(tot.data(), d_tot, sizeof(double) * tot.size(),
+                              hipMemcpyDeviceToHost, c->stream));
+  if (!rc)
+    rc = fail(c, hipMemcpyAsync(flags, at(c, c->plan.lay.flags), sizeof(flags),
+                                hipMemcpyDeviceToHost, c->stream));
+  if (!rc) rc = fail(c, hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  const int r0 = all ? 0 : rep, r1 = all ? R : rep + 1;
+  for (int r = r0; r < r1; ++r) {
+    const double* t = &tot[(size_t)r * kRedWidth];
+    double* h = h_totals + (size_t)(all ? r : 0) * LBMD_NTOTALS;
+    const lbmd_params& p = c->p[r];
+    const double m = p.particle_mass;
+    const double S = (double)p.nx * p.ny * p.nz;
+    h[LBMD_TOT_MASS] = p.rho0 * S + t[0];
+    for (int d = 0; d < 3; ++d) {
+      h[LBMD_TOT_PFLUID + d] = t[1 + d] + t[4 + d];
+      h[LBMD_TOT_PSEEN + d] = t[1 + d] + (p.variant == 2 ? t[4 + d] : 0.0);
+      h[LBMD_TOT_PPART + d] = m * t[8 + d];
+    }
+    h[LBMD_TOT_KEPART] = 0.5 * m * t[11];
+    h[LBMD_TOT_U2FLUID] = t[7] / S;
+    h[LBMD_TOT_TLB] = (double)c->t_lb;
+    h[LBMD_TOT_TMD] = (double)c->t_md;
+  }
   return flags[0] ? LBMD_ENONFINITE : LBMD_OK;
 }
 
-int lbmd_get_populations(lbmd* c, void* d_dst) {
-  if (!c || !d_dst) return LBMD_EINVAL;
-  if (c->sticky) return c->sticky;
-  return fail(c, launch_get_populations(c, d_dst));
+int lb_moments(lbmd* c, void* d_rho, void* d_u, double* h_totals) {
+  return moments_common(c, 0, d_rho, d_u, h_totals, 0);
 }
 
-int lbmd_set_populations(lbmd* c, const void* d_src) {
-  if (!c || !d_src) return LBMD_EINVAL;
-  if (c->sticky) return c->sticky;
-  const int rc = fail(c, launch_set_populations(c, d_src));
+int lbmd_batch_moments(lbmd* c, double* h_totals) {
+  if (!h_totals) return LBMD_EINVAL;
+  return moments_common(c, 0, nullptr, nullptr, h_totals, 1);
+}
+
+int lbmd_batch_get_populations(lbmd* c, int32_t rep, void* d_dst) {
+  int rc = check_rep(c, rep);
+  if (rc || !d_dst) return rc ? rc : LBMD_EINVAL;
+  return fail(c, launch_get_populations(c, rep, d_dst));
+}
+
+int lbmd_batch_set_populations(lbmd* c, int32_t rep, const void* d_src) {
+  int rc = check_rep(c, rep);
+  if (rc || !d_src) return rc ? rc : LBMD_EINVAL;
+  rc = fail(c, launch_set_populations(c, rep, d_src));
   if (rc) return rc;
   return fail(c, invalidate_corner_cache(c));
 }
 
-int lbmd_get_transfer(lbmd* c, void* d_dst) {
-  if (!c || !d_dst) return LBMD_EINVAL;
-  if (c->sticky) return c->sticky;
-  return fail(c, launch_get_transfer(c, d_dst));
+int lbmd_batch_get_transfer(lbmd* c, int32_t rep, void* d_dst) {
+  int rc = check_rep(c, rep);
+  if (rc || !d_dst) return rc ? rc : LBMD_EINVAL;
+  return fail(c, launch_get_transfer(c, rep, d_dst));
 }
+
+int lbmd_get_populations(lbmd* c, void* d_dst) { return lbmd_batch_get_populations(c, 0, d_dst); }
+int lbmd_set_populations(lbmd* c, const void* d_src) {
+  return lbmd_batch_set_populations(c, 0, d_src);
+}
+int lbmd_get_transfer(lbmd* c, void* d_dst) { return lbmd_batch_get_transfer(c, 0, d_dst); }
 
 int lbmd_get_counters(lbmd* c, int64_t* t_lb, int64_t* t_md, int32_t* subs) {
   if (!c) return LBMD_EINVAL;
@@ -244,12 +517,150 @@ int lbmd_get_counters(lbmd* c, int64_t* t_lb, int64_t* t_md, int32_t* subs) {
 }
 
 int lbmd_set_counters(lbmd* c, int64_t t_lb, int64_t t_md, int32_t subs) {
-  if (!c || t_lb < 0 || t_md < 0 || subs < 0 || subs > c->p.n_sub) return LBMD_EINVAL;
+  if (!c || t_lb < 0 || t_md < subs || subs < 0 || subs > c->plan.n_sub) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
   c->t_lb = t_lb;
   c->t_md = t_md;
   c->subs = subs;
+  int rc = fail(c, write_clock(c));
+  if (rc) return rc;
   return fail(c, invalidate_corner_cache(c));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate persistent-grid sizes of the LB kernels and of
+// the particle kernels on this context and keeps the fastest; results are
+// cached in a small JSON file keyed by device, precision, variant and size
+// class.  Must run at an LB-step boundary; it leaves the state as it was
+// (the collide-stream launches write only the spare population buffer and
+// find no pending transfer; particle state is saved and restored).
+// ---------------------------------------------------------------------------
+namespace {
+
+std::string tune_key(lbmd* c) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    snprintf(prop.gcnArchName, sizeof(prop.gcnArchName), "unknown");
+  char buf[256];
+  const int ls = (int)std::floor(std::log2((double)std::max<int64_t>(c->plan.Stot, 1)));
+  const int ln = (int)std::floor(std::log2((double)std::max<int64_t>(c->plan.Ntot, 1)));
+  snprintf(buf, sizeof(buf), "%s|fp%d|v%d|R%d|S2^%d|N2^%d", prop.gcnArchName, c->plan.prec,
+           c->p[0].variant, c->plan.R, ls, ln);
+  for (char* q = buf; *q; ++q)
+    if (*q == '"' || *q == ':') *q = '_';
+  return std::string(buf);
+}
+
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> m;
+  FILE* f = path ? fopen(path, "r") : nullptr;
+  if (!f) return m;
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    char key[300];
+    int a, b;
+    if (sscanf(line, " \"%299[^\"]\": [%d, %d]", key, &a, &b) == 3) m[key] = {a, b};
+  }
+  fclose(f);
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m)
+    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.first, kv.second.second,
+            ++i < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+// mean milliseconds of `reps` calls of fn on the context stream
+template <typename F>
+double time_ms(lbmd* c, F fn, int reps, hipError_t* err) {
+  hipEvent_t a, b;
+  *err = hipEventCreate(&a);
+  if (*err == hipSuccess) *err = hipEventCreate(&b);
+  if (*err != hipSuccess) return 0.0;
+  *err = fn();  // warm-up
+  if (*err == hipSuccess) *err = hipEventRecord(a, c->stream);
+  for (int k = 0; k < reps && *err == hipSuccess; ++k) *err = fn();
+  if (*err == hipSuccess) *err = hipEventRecord(b, c->stream);
+  if (*err == hipSuccess) *err = hipEventSynchronize(b);
+  float ms = 0.f;
+  if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
+                  int32_t* out_part_blocks) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (c->subs != 0) return LBMD_ESTATE;
+  const std::string key = tune_key(c);
+  auto cache = read_cache(cache_path);
+  auto hit = cache.find(key);
+  if (hit != cache.end()) {
+    c->tune.lb_blocks = hit->second.first;
+    c->tune.part_blocks = hit->second.second;
+  } else {
+    hipError_t e = hipSuccess;
+    int cu = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cu = 256;
+    // LB kernels: blocks in flight
+    const int lb_cand[5] = {0, 4 * cu, 8 * cu, 16 * cu, 32 * cu};
+    double best = 1e30;
+    int best_lb = 0;
+    for (int q : lb_cand) {
+      c->tune.lb_blocks = q;
+      const double ms = time_ms(c, [&] { return launch_collide_stream(c); }, 3, &e);
+      if (e != hipSuccess) return fail(c, e);
+      if (ms < best) {
+        best = ms;
+        best_lb = q;
+      }
+    }
+    c->tune.lb_blocks = best_lb;
+    // particle kernels: the cache refill reads particle positions only
+    int best_part = 0;
+    if (c->plan.Ntot > 0 && c->bound) {
+      const int part_cand[5] = {0, 2 * cu, 4 * cu, 8 * cu, 16 * cu};
+      best = 1e30;
+      for (int q : part_cand) {
+        c->tune.part_blocks = q;
+        const double ms = time_ms(c, [&] { return launch_couple_refill_only(c); }, 3, &e);
+        if (e != hipSuccess) return fail(c, e);
+        if (ms < best) {
+          best = ms;
+          best_part = q;
+        }
+      }
+    }
+    c->tune.part_blocks = best_part;
+    // the refill timing left marks and cached corners of this interval: the
+    // marks are harmless (no transfer is pending), the cache is valid
+    cache[key] = {c->tune.lb_blocks, c->tune.part_blocks};
+    write_cache(cache_path, cache);
+  }
+  drop_graph(c);
+  if (out_lb_blocks) *out_lb_blocks = c->tune.lb_blocks;
+  if (out_part_blocks) *out_part_blocks = c->tune.part_blocks;
+  return LBMD_OK;
 }
 
 const char* lbmd_strerror(int code) {

@@ -1,7 +1,10 @@
 // Particle coupling kernels (Sec. 3, Eq. 4-8): fluid velocity at the
 // particle by interpolation over the 8 sites of its cube, friction plus
 // noise, velocity Verlet, and transfer of -dP to the same 8 sites with the
-// same weights.
+// same weights.  Particles of all replicas in one launch; each particle
+// reads its replica's constants.
+#include <algorithm>
+
 #include "lbmd_internal.hpp"
 
 namespace lbmd_impl {
@@ -15,26 +18,25 @@ struct CoupleArgs {
   double* __restrict__ v;
   int32_t* __restrict__ img;
   const double* __restrict__ fcons;
-  const T* __restrict__ pop;
+  T* pop[2];
   Vec4<T>* __restrict__ J;
   unsigned long long* __restrict__ mark;
   int32_t* __restrict__ rec_cell;
   double* __restrict__ rec_frac;
   double* __restrict__ rec_dp;
+  double* __restrict__ fc_held;  // coupling force of the step (split kick)
   T* __restrict__ cc;
   int32_t* __restrict__ cc_cell;
   int32_t* __restrict__ cc_stamp;
   int32_t* __restrict__ flags;
-  double* __restrict__ fc_held;  // coupling force of the step (split kick)
-  Geom g;
-  int N;
-  int split_kick;
-  int stamp;  // LB step + 1: identifies the post-stream state the cache holds
-  double rho0, gamma, amp, tau, h;  // h = tau / (2 m)
-  double L[3];
-  uint32_t key0, key1, step_lo, step_hi, tag;
+  const RepMD* __restrict__ md;
+  const int32_t* __restrict__ part_rep;
+  const Clock* __restrict__ clock;
+  size_t P;     // population stride
+  int64_t N;    // particles over all replicas
+  int substep;  // MD step inside the LB interval
   int variant;
-  int noise;
+  int single;   // one replica: its constants are uniform across the grid
 };
 
 // Periodic wrap into [0, L) with image counting for any displacement
@@ -83,7 +85,7 @@ __device__ __forceinline__ void cube_of(const double X[3], const Geom& g, Cube& 
   }
 }
 
-// Site and trilinear weight (Eq. 5) of corner k of the cube.
+// Site (replica-local) and trilinear weight (Eq. 5) of corner k of the cube.
 __device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, int& cx, int& cy,
                                           int& cz, int& site, double& w) {
   cx = q.base[0] + (k & 1);
@@ -97,24 +99,14 @@ __device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, i
       ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
 }
 
-// Density deviation and momentum of the post-stream state at one site,
-// gathered from pull storage (one lane does all 19 reads).
-template <typename T>
-__device__ __forceinline__ void site_moments(const CoupleArgs<T>& a, int cx, int cy, int cz,
-                                             T& drho, T& jx, T& jy, T& jz) {
-  int src[19];
-  pull_sources(a.g, cx, cy, cz, src);
-  const size_t S = (size_t)a.g.S;
-  T d[19];
-#pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = a.pop[(size_t)i * S + src[i]];
-  moments_deviation<T>(d, drho, jx, jy, jz);
-}
-
 // Corner cache entry k of particle p: (jx, jy, jz, 1/rho) of the corner.
 template <typename T>
-__device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int p, int k) {
+__device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
   return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * 8 + k;
+}
+
+__device__ __forceinline__ int cache_stamp(const Clock* clk) {
+  return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,54 +129,61 @@ __device__ __forceinline__ T quad_sum(T v) {  // over the 4 lanes of a corner
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  const int p = t / kRefillLanes;
-  if (p >= a.N) return;  // the 32 lanes of a particle leave together
-  const int sl = threadIdx.x & (kRefillLanes - 1);
-  const int k = sl >> 2, c = sl & 3;
-  const int N = a.N;
-  double X[3];
-  bool finite = true;
+  const T* __restrict__ pop = a.pop[a.clock->cur];
+  const int stamp = cache_stamp(a.clock);
+  const int64_t lanes = a.N * kRefillLanes;
+  // lanes come in whole particles (32 | kBlock), so a particle's lanes stay
+  // together in every iteration
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / kRefillLanes;
+    const int sl = threadIdx.x & (kRefillLanes - 1);
+    const int k = sl >> 2, c = sl & 3;
+    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    const int64_t N = a.N;
+    double X[3];
+    bool finite = true;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    X[d] = a.x[d * N + p];
-    finite = finite && isfinite(X[d]);
-  }
-  if (!finite) return;
-  Cube q;
-  cube_of(X, a.g, q);
-  int cx, cy, cz, site;
-  double w;
-  corner_of(q, a.g, k, cx, cy, cz, site, w);
-  const size_t S = (size_t)a.g.S;
-  T drho = T(0), qx = T(0), qy = T(0), qz = T(0);
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const int i = c + 4 * m;
-    if (i < 19) {
-      const int ex = kVel[i][0], ey = kVel[i][1], ez = kVel[i][2];
-      int sx = cx - ex, sy = cy - ey, sz = cz - ez;
-      sx = sx < 0 ? sx + a.g.nx : (sx >= a.g.nx ? sx - a.g.nx : sx);
-      sy = sy < 0 ? sy + a.g.ny : (sy >= a.g.ny ? sy - a.g.ny : sy);
-      sz = sz < 0 ? sz + a.g.nz : (sz >= a.g.nz ? sz - a.g.nz : sz);
-      const T d = a.pop[(size_t)i * S + sx + a.g.nx * (sy + a.g.ny * sz)];
-      drho += d;
-      qx += (T)ex * d;
-      qy += (T)ey * d;
-      qz += (T)ez * d;
+    for (int d = 0; d < 3; ++d) {
+      X[d] = a.x[d * N + p];
+      finite = finite && isfinite(X[d]);
     }
+    if (!finite) continue;
+    Cube q;
+    cube_of(X, m.g, q);
+    int cx, cy, cz, site;
+    double w;
+    corner_of(q, m.g, k, cx, cy, cz, site, w);
+    T drho = T(0), qx = T(0), qy = T(0), qz = T(0);
+#pragma unroll
+    for (int mm = 0; mm < 5; ++mm) {
+      const int i = c + 4 * mm;
+      if (i < 19) {
+        const int ex = kVel[i][0], ey = kVel[i][1], ez = kVel[i][2];
+        int sx = cx - ex, sy = cy - ey, sz = cz - ez;
+        sx = sx < 0 ? sx + m.g.nx : (sx >= m.g.nx ? sx - m.g.nx : sx);
+        sy = sy < 0 ? sy + m.g.ny : (sy >= m.g.ny ? sy - m.g.ny : sy);
+        sz = sz < 0 ? sz + m.g.nz : (sz >= m.g.nz ? sz - m.g.nz : sz);
+        const T d = pop[(size_t)i * a.P + m.site_off + sx + m.g.nx * (sy + m.g.ny * sz)];
+        drho += d;
+        qx += (T)ex * d;
+        qy += (T)ey * d;
+        qz += (T)ez * d;
+      }
+    }
+    drho = quad_sum(drho);
+    qx = quad_sum(qx);
+    qy = quad_sum(qy);
+    qz = quad_sum(qz);
+    const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
+    a.cc[(size_t)p * 32 + sl] = mine;
+    if (sl == 0) {
+      a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+      a.cc_stamp[p] = stamp;
+    }
+    const int gs = m.site_off + site;
+    if (c == 0) atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
   }
-  drho = quad_sum(drho);
-  qx = quad_sum(qx);
-  qy = quad_sum(qy);
-  qz = quad_sum(qz);
-  const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)a.rho0 + drho)));
-  a.cc[(size_t)p * 32 + sl] = mine;
-  if (sl == 0) {
-    a.cc_cell[p] = q.base[0] + a.g.nx * (q.base[1] + a.g.ny * q.base[2]);
-    a.cc_stamp[p] = a.stamp;
-  }
-  if (c == 0) atomicOr(a.mark + (site >> 6), 1ull << (site & 63));
 }
 
 // ---------------------------------------------------------------------------
@@ -193,140 +192,161 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
 // Fluid velocity at the particle from the cached corner moments (a particle
 // that left its cube since the refill gathers the new corners itself),
 // friction + noise, velocity Verlet.  Variant 1 then transfers the momentum
-// right away: the block stages (cube, dP) of its 256 particles in LDS and
-// re-issues the 24 adds of each particle from 24 consecutive lanes, so one
-// atomic instruction covers ~3 particles and a handful of cache lines rather
-// than 64 unrelated lines.  Variant 2 stores (cube, dP) for the spreading
-// kernel, because every particle must first read the velocities as of the
-// end of the previous MD step.
+// right away: the block stages (replica, cube, dP) of its 256 particles in
+// LDS and re-issues the 24 adds of each particle from 24 consecutive lanes,
+// so one atomic instruction covers ~3 particles and a handful of cache lines
+// rather than 64 unrelated lines.  Variant 2 stores (cube, dP) for the
+// spreading kernel, because every particle must first read the velocities as
+// of the end of the previous MD step.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
+  __shared__ int sh_rep[kBlock];
   __shared__ int sh_base[3][kBlock];
   __shared__ double sh_s[3][kBlock];
   __shared__ double sh_dp[3][kBlock];
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  const int N = a.N;
-  bool live = p < N;
-  double X[3] = {0.0, 0.0, 0.0}, V[3] = {0.0, 0.0, 0.0};
-  if (live) {
+  const T* __restrict__ pop = a.pop[a.clock->cur];
+  const int stamp = cache_stamp(a.clock);
+  const unsigned long long t_md = (unsigned long long)(a.clock->t_md + a.substep);
+  const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
+  const int64_t N = a.N;
+  const int64_t rounds = (N + kBlock - 1) / kBlock;
+  for (int64_t blk = blockIdx.x; blk < rounds; blk += gridDim.x) {
+    const int64_t p = blk * kBlock + threadIdx.x;
+    bool live = p < N;
+    int rr = 0;
+    double X[3] = {0.0, 0.0, 0.0}, V[3] = {0.0, 0.0, 0.0};
+    if (live) {
+      rr = a.single ? 0 : a.part_rep[p];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      X[d] = a.x[d * N + p];
-      V[d] = a.v[d * N + p];
-      live = live && isfinite(X[d]) && isfinite(V[d]);
+      for (int d = 0; d < 3; ++d) {
+        X[d] = a.x[d * N + p];
+        V[d] = a.v[d * N + p];
+        live = live && isfinite(X[d]) && isfinite(V[d]);
+      }
+      if (!live) {
+        a.flags[0] = 1;
+        if (a.variant == 2) a.rec_cell[p] = -1;
+      }
     }
-    if (!live) {
-      a.flags[0] = 1;
-      if (a.variant == 2) a.rec_cell[p] = -1;
-    }
-  }
-  Cube q;
-  double dp[3] = {0.0, 0.0, 0.0};
-  if (live) {
-    cube_of(X, a.g, q);
-    const int cell = q.base[0] + a.g.nx * (q.base[1] + a.g.ny * q.base[2]);
-    Vec4<T> cv[8];
-    if (a.cc_stamp[p] == a.stamp && a.cc_cell[p] == cell) {
+    Cube q;
+    double dp[3] = {0.0, 0.0, 0.0};
+    if (live) {
+      const RepMD& m = a.md[rr];
+      cube_of(X, m.g, q);
+      const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+      Vec4<T> cv[8];
+      if (a.cc_stamp[p] == stamp && a.cc_cell[p] == cell) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) cv[k] = *cache_entry(a, p, k);
-    } else {
-      // left the cube of the refill: gather the new corners here
+        for (int k = 0; k < 8; ++k) cv[k] = *cache_entry(a, p, k);
+      } else {
+        // left the cube of the refill: gather the new corners here
 #pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+          int cx, cy, cz, site;
+          double w;
+          corner_of(q, m.g, k, cx, cy, cz, site, w);
+          int sidx[19];
+          pull_sources(m.g, cx, cy, cz, sidx);
+          T d[19];
+#pragma unroll
+          for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
+          T drho, jx, jy, jz;
+          moments_deviation<T>(d, drho, jx, jy, jz);
+          cv[k] = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
+          *cache_entry(a, p, k) = cv[k];
+          const int gs = m.site_off + site;
+          atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
+        }
+        a.cc_cell[p] = cell;
+        a.cc_stamp[p] = stamp;
+      }
+      // fluid velocity at the particle (Eq. 5)
+      double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
       for (int k = 0; k < 8; ++k) {
         int cx, cy, cz, site;
         double w;
-        corner_of(q, a.g, k, cx, cy, cz, site, w);
-        T drho, jx, jy, jz;
-        site_moments<T>(a, cx, cy, cz, drho, jx, jy, jz);
-        cv[k] = Vec4<T>{jx, jy, jz, T(1) / ((T)a.rho0 + drho)};
-        *cache_entry(a, p, k) = cv[k];
-        atomicOr(a.mark + (site >> 6), 1ull << (site & 63));
+        corner_of(q, m.g, k, cx, cy, cz, site, w);
+        double jx = (double)cv[k].x, jy = (double)cv[k].y, jz = (double)cv[k].z;
+        if (a.variant == 2) {
+          const Vec4<T> jv = a.J[m.site_off + site];
+          jx += (double)jv.x;
+          jy += (double)jv.y;
+          jz += (double)jv.z;
+        }
+        const double wi = w * (double)cv[k].w;
+        u[0] += wi * jx;
+        u[1] += wi * jy;
+        u[2] += wi * jz;
       }
-      a.cc_cell[p] = cell;
-      a.cc_stamp[p] = a.stamp;
-    }
-    // fluid velocity at the particle (Eq. 5)
-    double u[3] = {0.0, 0.0, 0.0};
+      // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
+      double xi[3] = {0.0, 0.0, 0.0};
+      if (m.noise) {
+        const uint32_t lp = (uint32_t)(p - m.part_off);
+        const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
+        const uint32_t ws[3] = {o.w0, o.w1, o.w2};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int cx, cy, cz, site;
-      double w;
-      corner_of(q, a.g, k, cx, cy, cz, site, w);
-      double jx = (double)cv[k].x, jy = (double)cv[k].y, jz = (double)cv[k].z;
-      if (a.variant == 2) {
-        const Vec4<T> jv = a.J[site];
-        jx += (double)jv.x;
-        jy += (double)jv.y;
-        jz += (double)jv.z;
+        for (int d = 0; d < 3; ++d)
+          xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
       }
-      const double wi = w * (double)cv[k].w;
-      u[0] += wi * jx;
-      u[1] += wi * jy;
-      u[2] += wi * jz;
-    }
-    // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
-    double xi[3] = {0.0, 0.0, 0.0};
-    if (a.noise) {
-      const Words4 o = philox10(Words4{(uint32_t)p, a.step_lo, a.tag, a.step_hi}, a.key0, a.key1);
-      const uint32_t ws[3] = {o.w0, o.w1, o.w2};
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
-    }
-    // velocity Verlet with the coupling force held over the step; with
-    // position-dependent conservative forces the second half-kick waits for
-    // the forces at the new positions (k_kick)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double Fc = -a.gamma * (V[d] - u[d]) + a.amp * xi[d];
-      dp[d] = a.tau * Fc;
-      const double fc = a.fcons[d * N + p];
-      int32_t im = a.img[d * N + p];
-      V[d] += a.h * (fc + Fc);
-      X[d] += a.tau * V[d];
-      wrap_coord(X[d], im, a.L[d]);
-      if (a.split_kick)
-        a.fc_held[d * N + p] = Fc;
-      else
-        V[d] += a.h * (fc + Fc);
-      a.x[d * N + p] = X[d];
-      a.v[d * N + p] = V[d];
-      a.img[d * N + p] = im;
-    }
-    if (a.variant == 2) {
+      // velocity Verlet with the coupling force held over the step; with
+      // position-dependent conservative forces the second half-kick waits
+      // for the forces at the new positions (k_kick)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.rec_cell[d * N + p] = q.base[d];
-        a.rec_frac[d * N + p] = q.s[d];
-        a.rec_dp[d * N + p] = dp[d];
+        const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
+        dp[d] = m.tau * Fc;
+        const double fc = a.fcons[d * N + p];
+        int32_t im = a.img[d * N + p];
+        V[d] += m.h * (fc + Fc);
+        X[d] += m.tau * V[d];
+        wrap_coord(X[d], im, m.L[d]);
+        if (m.split_kick)
+          a.fc_held[d * N + p] = Fc;
+        else
+          V[d] += m.h * (fc + Fc);
+        a.x[d * N + p] = X[d];
+        a.v[d * N + p] = V[d];
+        a.img[d * N + p] = im;
+      }
+      if (a.variant == 2) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.rec_cell[d * N + p] = q.base[d];
+          a.rec_frac[d * N + p] = q.s[d];
+          a.rec_dp[d * N + p] = dp[d];
+        }
       }
     }
-  }
-  if (a.variant != 1) return;  // uniform: no thread of the block continues
+    if (a.variant != 1) continue;  // uniform over the grid
 
-  // momentum transfer to the fluid (Eq. 7-8), 24 consecutive lanes per particle
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    sh_base[d][threadIdx.x] = live ? q.base[d] : -1;
-    sh_s[d][threadIdx.x] = live ? q.s[d] : 0.0;
-    sh_dp[d][threadIdx.x] = dp[d];
-  }
-  __syncthreads();
-  for (int g = threadIdx.x; g < 24 * kBlock; g += kBlock) {
-    const int pp = g / 24, r = g - 24 * pp;
-    if (sh_base[0][pp] < 0) continue;
-    const int k = r / 3, c = r - 3 * k;
-    Cube qq;
+    // momentum transfer to the fluid (Eq. 7-8), 24 consecutive lanes per particle
+    sh_rep[threadIdx.x] = rr;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      qq.base[d] = sh_base[d][pp];
-      qq.s[d] = sh_s[d][pp];
+      sh_base[d][threadIdx.x] = live ? q.base[d] : -1;
+      sh_s[d][threadIdx.x] = live ? q.s[d] : 0.0;
+      sh_dp[d][threadIdx.x] = dp[d];
     }
-    int cx, cy, cz, site;
-    double w;
-    corner_of(qq, a.g, k, cx, cy, cz, site, w);
-    atomicAdd(((T*)(a.J + site)) + c, (T)(-w * sh_dp[c][pp]));
+    __syncthreads();
+    for (int g = threadIdx.x; g < 24 * kBlock; g += kBlock) {
+      const int pp = g / 24, r = g - 24 * pp;
+      if (sh_base[0][pp] < 0) continue;
+      const int k = r / 3, c = r - 3 * k;
+      const RepMD& m = a.md[a.single ? 0 : sh_rep[pp]];
+      Cube qq;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        qq.base[d] = sh_base[d][pp];
+        qq.s[d] = sh_s[d][pp];
+      }
+      int cx, cy, cz, site;
+      double w;
+      corner_of(qq, m.g, k, cx, cy, cz, site, w);
+      atomicAdd(((T*)(a.J + m.site_off + site)) + c, (T)(-w * sh_dp[c][pp]));
+    }
+    __syncthreads();
   }
 }
 
@@ -334,94 +354,109 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
 // particle (one per corner and component).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int p = (int)(g / 24);
-  if (p >= a.N) return;
-  const int r = (int)(g - 24 * (int64_t)p);
-  const int k = r / 3, c = r - 3 * k;
-  const int N = a.N;
-  Cube q;
-  q.base[0] = a.rec_cell[p];
-  if (q.base[0] < 0) return;
-  q.base[1] = a.rec_cell[N + p];
-  q.base[2] = a.rec_cell[2 * N + p];
+  const int64_t N = a.N;
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < 24 * N;
+       g += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = g / 24;
+    const int r = (int)(g - 24 * p);
+    const int k = r / 3, c = r - 3 * k;
+    Cube q;
+    q.base[0] = a.rec_cell[p];
+    if (q.base[0] < 0) continue;
+    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    q.base[1] = a.rec_cell[N + p];
+    q.base[2] = a.rec_cell[2 * N + p];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) q.s[d] = a.rec_frac[d * N + p];
-  int cx, cy, cz, site;
-  double w;
-  corner_of(q, a.g, k, cx, cy, cz, site, w);
-  atomicAdd(((T*)(a.J + site)) + c, (T)(-w * a.rec_dp[c * N + p]));
+    for (int d = 0; d < 3; ++d) q.s[d] = a.rec_frac[d * N + p];
+    int cx, cy, cz, site;
+    double w;
+    corner_of(q, m.g, k, cx, cy, cz, site, w);
+    atomicAdd(((T*)(a.J + m.site_off + site)) + c, (T)(-w * a.rec_dp[c * N + p]));
+  }
 }
 
 template <typename T>
-static CoupleArgs<T> couple_args(Context* c) {
+static CoupleArgs<T> couple_args(Context* c, int substep) {
   CoupleArgs<T> a;
-  const int N = c->p.n_particles;
+  const Layout& L = c->plan.lay;
   a.x = (double*)c->x;
   a.v = (double*)c->v;
   a.img = c->img;
-  a.fcons = (const double*)at(c, c->lay.fcons);
-  a.pop = (const T*)at(c, c->lay.pop[c->cur]);
-  a.J = (Vec4<T>*)at(c, c->lay.transfer);
-  a.mark = (unsigned long long*)at(c, c->lay.mark);
-  a.rec_cell = (int32_t*)at(c, c->lay.rec_cell);
-  a.rec_frac = (double*)at(c, c->lay.rec_frac);
-  a.rec_dp = (double*)at(c, c->lay.rec_dp);
-  a.cc = (T*)at(c, c->lay.cc);
-  a.cc_cell = (int32_t*)at(c, c->lay.cc_cell);
-  a.cc_stamp = (int32_t*)at(c, c->lay.cc_stamp);
-  a.flags = (int32_t*)at(c, c->lay.flags);
-  a.fc_held = (double*)at(c, c->lay.fc_held);
-  a.split_kick = c->p.force_model == 2 ? 1 : 0;
-  a.g = c->geom;
-  a.N = N;
-  a.stamp = (int)(((uint64_t)c->t_lb & 0x3FFFFFFFu) + 1);
-  const double tau = 1.0 / c->p.n_sub;
-  a.rho0 = c->p.rho0;
-  a.gamma = c->p.friction;
-  a.amp = std::sqrt(2.0 * c->p.friction * c->p.kT / tau);
-  a.tau = tau;
-  a.h = tau / (2.0 * c->p.particle_mass);
-  a.L[0] = (double)c->p.nx;
-  a.L[1] = (double)c->p.ny;
-  a.L[2] = (double)c->p.nz;
-  a.key0 = (uint32_t)(c->p.seed & 0xFFFFFFFFu);
-  a.key1 = (uint32_t)(c->p.seed >> 32);
-  a.step_lo = (uint32_t)((uint64_t)c->t_md & 0xFFFFFFFFu);
-  a.step_hi = (uint32_t)((uint64_t)c->t_md >> 32);
-  a.tag = noise_tag(kPurposeParticle, c->p.replica, 0);
-  a.variant = c->p.variant;
-  a.noise = (c->p.kT > 0.0 && c->p.friction > 0.0) ? 1 : 0;
+  a.fcons = (const double*)at(c, L.fcons);
+  a.pop[0] = (T*)at(c, L.pop[0]);
+  a.pop[1] = (T*)at(c, L.pop[1]);
+  a.J = (Vec4<T>*)at(c, L.transfer);
+  a.mark = (unsigned long long*)at(c, L.mark);
+  a.rec_cell = (int32_t*)at(c, L.rec_cell);
+  a.rec_frac = (double*)at(c, L.rec_frac);
+  a.rec_dp = (double*)at(c, L.rec_dp);
+  a.fc_held = (double*)at(c, L.fc_held);
+  a.cc = (T*)at(c, L.cc);
+  a.cc_cell = (int32_t*)at(c, L.cc_cell);
+  a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
+  a.flags = (int32_t*)at(c, L.flags);
+  a.md = (const RepMD*)at(c, L.rep_md);
+  a.part_rep = (const int32_t*)at(c, L.part_rep);
+  a.clock = (const Clock*)at(c, L.clock);
+  a.P = (size_t)c->plan.Stot;
+  a.N = c->plan.Ntot;
+  a.substep = substep;
+  a.variant = c->p[0].variant;
+  a.single = c->plan.R == 1 ? 1 : 0;
   return a;
 }
 
+static int grid_for(int64_t work_blocks, int tuned) {
+  const int64_t g = tuned > 0 ? std::min<int64_t>(tuned, work_blocks) : work_blocks;
+  return (int)std::max<int64_t>(g, 1);
+}
+
 template <typename T>
-static hipError_t couple_t(Context* c) {
-  CoupleArgs<T> a = couple_args<T>(c);
+static hipError_t couple_t(Context* c, int substep) {
+  CoupleArgs<T> a = couple_args<T>(c, substep);
   hipError_t e;
-  if (c->subs == 0) {
-    const int rb = (int)(((int64_t)a.N * kRefillLanes + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_refill<T>, dim3(rb), dim3(kBlock), 0, c->stream, a);
+  const int64_t N = a.N;
+  if (substep == 0) {
+    hipLaunchKernelGGL(k_refill<T>,
+                       dim3(grid_for((N * kRefillLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
+                       dim3(kBlock), 0, c->stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int blocks = (a.N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_couple<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
+  hipLaunchKernelGGL(k_couple<T>, dim3(grid_for((N + kBlock - 1) / kBlock, c->tune.part_blocks)),
+                     dim3(kBlock), 0, c->stream, a);
   if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
-  const int sb = (int)(((int64_t)a.N * 24 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_spread<T>, dim3(sb), dim3(kBlock), 0, c->stream, a);
+  hipLaunchKernelGGL(k_spread<T>, dim3(grid_for((N * 24 + kBlock - 1) / kBlock, c->tune.part_blocks)),
+                     dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_couple(Context* c) {
-  if (c->p.n_particles == 0) return hipSuccess;
-  return c->p.precision == 32 ? couple_t<float>(c) : couple_t<double>(c);
+hipError_t launch_couple(Context* c, int substep) {
+  if (c->plan.Ntot == 0) return hipSuccess;
+  return c->plan.prec == 32 ? couple_t<float>(c, substep) : couple_t<double>(c, substep);
+}
+
+template <typename T>
+static hipError_t refill_t(Context* c) {
+  CoupleArgs<T> a = couple_args<T>(c, 0);
+  hipLaunchKernelGGL(k_refill<T>,
+                     dim3(grid_for((a.N * kRefillLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
+                     dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError();
+}
+
+// The corner-cache refill alone (reads particle positions, writes only the
+// cache and the marks of this LB interval): used to time launch shapes.
+hipError_t launch_couple_refill_only(Context* c) {
+  if (c->plan.Ntot == 0) return hipSuccess;
+  return c->plan.prec == 32 ? refill_t<float>(c) : refill_t<double>(c);
 }
 
 // Forget cached corner moments (after the populations or counters were
 // replaced from outside).
 hipError_t invalidate_corner_cache(Context* c) {
-  if (c->p.n_particles == 0) return hipSuccess;
-  return hipMemsetAsync(at(c, c->lay.cc_stamp), 0, sizeof(int32_t) * c->p.n_particles, c->stream);
+  if (c->plan.Ntot == 0) return hipSuccess;
+  return hipMemsetAsync(at(c, c->plan.lay.cc_stamp), 0, sizeof(int32_t) * c->plan.Ntot,
+                        c->stream);
 }
 
 }  // namespace lbmd_impl

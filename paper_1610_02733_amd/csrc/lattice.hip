@@ -1,10 +1,28 @@
 // Lattice kernels: the fused pull collide-and-stream step (Eq. 3 with the
 // MRT collision, fluid noise and Guo forcing of Sec. 2-3), the FP64 moment
-// reductions (Eq. 1-2) and population / transfer copies.
+// reductions (Eq. 1-2) and population / transfer copies.  All kernels cover
+// every replica of a context in one launch.
+#include <algorithm>
+
 #include "lbmd_internal.hpp"
 
 namespace lbmd_impl {
 using namespace lbmd_dev;
+
+// Replica of a 256-site work item: binary search over the item offsets
+// (uniform across the block).
+__device__ __forceinline__ int replica_of_item(const int32_t* __restrict__ item_off, int R,
+                                               int item) {
+  int lo = 0, hi = R;  // item_off[lo] <= item < item_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (item_off[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 
 // ---------------------------------------------------------------------------
 // Fused collide-and-stream, one thread per site, pull scheme.
@@ -15,101 +33,118 @@ using namespace lbmd_dev;
 // this LB step, collides and writes its 19 results at r in the other buffer
 // (coalesced).  J is only read where the site's bit in `mark` is set (the
 // coupling sets it when it transfers momentum there), and is cleared with it,
-// so the untouched bulk of the lattice costs no transfer traffic.  Threads
-// map linearly onto sites, so one wavefront owns exactly one 64-bit mark word.
+// so the untouched bulk of the lattice costs no transfer traffic.  A work
+// item is 256 consecutive sites of one replica; replica offsets are
+// multiples of 64, so one wavefront owns exactly one 64-bit mark word.
+// Persistent grid: blocks stride over the items.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct StreamArgs {
-  const T* __restrict__ src;
-  T* __restrict__ dst;
+  T* pop[2];
   Vec4<T>* __restrict__ J;
   unsigned long long* __restrict__ mark;
-  Geom g;
-  uint32_t key0, key1, step_lo, step_hi, tag0, tag1;
-  CollideConsts<T> k;
+  const RepLB<T>* __restrict__ rep;
+  const int32_t* __restrict__ item_off;
+  const Clock* __restrict__ clock;
+  size_t P;  // population stride (padded total sites)
+  int R, nitems;
 };
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= a.g.S) return;
-  const unsigned long long word = a.mark[r >> 6];
-  int x, y, z;
-  site_coords(a.g, r, x, y, z);
-  int src[19];
-  pull_sources(a.g, x, y, z, src);
-  const size_t S = (size_t)a.g.S;
-  // every population is read once per step: non-temporal loads keep the
-  // stream from evicting the transfer field and the mark words
-  T d[19];
+  const int cur = a.clock->cur;
+  const long long t = a.clock->t_lb;
+  const T* __restrict__ src = a.pop[cur];
+  T* __restrict__ dst = a.pop[1 - cur];
+  const uint32_t step_lo = (uint32_t)((unsigned long long)t & 0xFFFFFFFFull);
+  const uint32_t step_hi = (uint32_t)((unsigned long long)t >> 32);
+  for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    const int rr = a.R == 1 ? 0 : replica_of_item(a.item_off, a.R, item);
+    const RepLB<T>& q = a.rep[rr];
+    const int local = (item - q.item_off) * kBlock + threadIdx.x;
+    if (local >= q.g.S) continue;
+    const int gsite = q.site_off + local;
+    const unsigned long long word = a.mark[gsite >> 6];
+    int x, y, z;
+    site_coords(q.g, local, x, y, z);
+    int sidx[19];
+    pull_sources(q.g, x, y, z, sidx);
+    const T* __restrict__ sbase = src + q.site_off;
+    T d[19];
+    // every population is read once per step: non-temporal loads keep the
+    // stream from evicting the transfer field and the mark words
 #pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(a.src + (size_t)i * S + src[i]);
+    for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(sbase + (size_t)i * a.P + sidx[i]);
 
-  T Fx = a.k.g[0], Fy = a.k.g[1], Fz = a.k.g[2];
-  if ((word >> (r & 63)) & 1ull) {
-    const Vec4<T> jv = a.J[r];
-    Fx += jv.x;
-    Fy += jv.y;
-    Fz += jv.z;
-    a.J[r] = Vec4<T>{T(0), T(0), T(0), T(0)};
-  }
-  uint32_t hw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (a.k.noise) {
-    const Words4 o0 = philox10(Words4{(uint32_t)r, a.step_lo, a.tag0, a.step_hi}, a.key0, a.key1);
-    const Words4 o1 = philox10(Words4{(uint32_t)r, a.step_lo, a.tag1, a.step_hi}, a.key0, a.key1);
-    hw[0] = o0.w0; hw[1] = o0.w1; hw[2] = o0.w2; hw[3] = o0.w3;
-    hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
-  }
-  collide_deviation<T>(d, Fx, Fy, Fz, hw, a.k);
-  // every population is written once per step: stream the stores past the
-  // caches (non-temporal hint)
+    T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
+    if ((word >> (gsite & 63)) & 1ull) {
+      const Vec4<T> jv = a.J[gsite];
+      Fx += jv.x;
+      Fy += jv.y;
+      Fz += jv.z;
+      a.J[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
+    }
+    uint32_t hw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (q.k.noise) {
+      const Words4 o0 = philox10(Words4{(uint32_t)local, step_lo, q.tag0, step_hi}, q.key0, q.key1);
+      const Words4 o1 = philox10(Words4{(uint32_t)local, step_lo, q.tag1, step_hi}, q.key0, q.key1);
+      hw[0] = o0.w0; hw[1] = o0.w1; hw[2] = o0.w2; hw[3] = o0.w3;
+      hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
+    }
+    collide_deviation<T>(d, Fx, Fy, Fz, hw, q.k);
+    // every population is written once per step: stream the stores past the
+    // caches (non-temporal hint)
 #pragma unroll
-  for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], a.dst + (size_t)i * S + r);
-  if ((r & 63) == 0 && word) a.mark[r >> 6] = 0ull;
+    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], dst + (size_t)i * a.P + gsite);
+    if ((gsite & 63) == 0 && word) a.mark[gsite >> 6] = 0ull;
+  }
 }
 
 template <typename T>
-static CollideConsts<T> make_consts(const Context* c) {
-  CollideConsts<T> k;
-  k.rho0 = (T)c->p.rho0;
-  k.gs = (T)c->gs;
-  k.gb = (T)c->gb;
-  k.gg = (T)c->gg;
-  k.hs = (T)(0.5 * (1.0 + c->gs));
-  k.hb = (T)(0.5 * (1.0 + c->gb));
-  k.mu = (T)c->mu;
-  for (int v = 0; v < 15; ++v) k.ns[v] = (T)c->ns[v];
-  for (int d = 0; d < 3; ++d) k.g[d] = (T)c->p.body_force[d];
-  k.noise = c->p.kT > 0.0 ? 1 : 0;
-  return k;
+static StreamArgs<T> stream_args(Context* c) {
+  StreamArgs<T> a;
+  a.pop[0] = (T*)at(c, c->plan.lay.pop[0]);
+  a.pop[1] = (T*)at(c, c->plan.lay.pop[1]);
+  a.J = (Vec4<T>*)at(c, c->plan.lay.transfer);
+  a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
+  a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
+  a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
+  a.clock = (const Clock*)at(c, c->plan.lay.clock);
+  a.P = (size_t)c->plan.Stot;
+  a.R = c->plan.R;
+  a.nitems = c->plan.nitems;
+  return a;
 }
 
 template <typename T>
 static hipError_t collide_stream_t(Context* c) {
-  StreamArgs<T> a;
-  a.src = (const T*)at(c, c->lay.pop[c->cur]);
-  a.dst = (T*)at(c, c->lay.pop[1 - c->cur]);
-  a.J = (Vec4<T>*)at(c, c->lay.transfer);
-  a.mark = (unsigned long long*)at(c, c->lay.mark);
-  a.g = c->geom;
-  a.key0 = (uint32_t)(c->p.seed & 0xFFFFFFFFu);
-  a.key1 = (uint32_t)(c->p.seed >> 32);
-  a.step_lo = (uint32_t)((uint64_t)c->t_lb & 0xFFFFFFFFu);
-  a.step_hi = (uint32_t)((uint64_t)c->t_lb >> 32);
-  a.tag0 = noise_tag(kPurposeFluid, c->p.replica, 0);
-  a.tag1 = noise_tag(kPurposeFluid, c->p.replica, 1);
-  a.k = make_consts<T>(c);
-  const int blocks = (int)((c->S + kBlock - 1) / kBlock);
+  StreamArgs<T> a = stream_args<T>(c);
+  const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
   hipLaunchKernelGGL(k_collide_stream<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_collide_stream(Context* c) {
-  return c->p.precision == 32 ? collide_stream_t<float>(c) : collide_stream_t<double>(c);
+  return c->plan.prec == 32 ? collide_stream_t<float>(c) : collide_stream_t<double>(c);
+}
+
+// End of an LB step: advance the device clock (graph-capturable).
+__global__ void k_clock_advance(Clock* __restrict__ clk, int md_steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    clk->t_lb += 1;
+    clk->t_md += md_steps;
+    clk->cur = 1 - clk->cur;
+  }
+}
+
+hipError_t launch_clock_advance(Context* c) {
+  hipLaunchKernelGGL(k_clock_advance, dim3(1), dim3(64), 0, c->stream,
+                     (Clock*)at(c, c->plan.lay.clock), (int)c->subs);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Block reduction of kRedWidth doubles per thread into partials[blockIdx].
+// Block reduction of kRedWidth doubles per thread into out[0..kRedWidth).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void block_reduce_store(double acc[kRedWidth], double* out) {
   __shared__ double sh[kBlock / 64][kRedWidth];
@@ -126,155 +161,174 @@ __device__ __forceinline__ void block_reduce_store(double acc[kRedWidth], double
     for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
     out[threadIdx.x] = s;
   }
+  __syncthreads();
 }
 
-// Columns: 0 sum drho, 1-3 sum j, 4-6 sum J, 7 sum |j/rho|^2, 8-10 sum v,
-// 11 sum |v|^2 (mass applied on the host).
+// Per-item partial sums.  Columns: 0 sum drho, 1-3 sum j, 4-6 sum J,
+// 7 sum |j/rho|^2.  Fields (density, velocity) of replica `field_rep`.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_moments(const T* __restrict__ pop,
-                                                    const Vec4<T>* __restrict__ J, Geom g, T rho0,
-                                                    T* __restrict__ rho_out, T* __restrict__ u_out,
-                                                    const double* __restrict__ v, int N,
+__global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_rep,
+                                                    T* __restrict__ rho_out,
+                                                    T* __restrict__ u_out,
                                                     double* __restrict__ partials) {
-  double acc[kRedWidth];
+  const T* __restrict__ src = a.pop[a.clock->cur];
+  for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    const int rr = a.R == 1 ? 0 : replica_of_item(a.item_off, a.R, item);
+    const RepLB<T>& q = a.rep[rr];
+    const int local = (item - q.item_off) * kBlock + threadIdx.x;
+    double acc[kRedWidth];
 #pragma unroll
-  for (int q = 0; q < kRedWidth; ++q) acc[q] = 0.0;
-  const size_t S = (size_t)g.S;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < g.S; r += gridDim.x * kBlock) {
-    int x, y, z, src[19];
-    site_coords(g, r, x, y, z);
-    pull_sources(g, x, y, z, src);
-    T d[19];
+    for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+    if (local < q.g.S) {
+      int x, y, z, sidx[19];
+      site_coords(q.g, local, x, y, z);
+      pull_sources(q.g, x, y, z, sidx);
+      T d[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * S + src[i]];
-    T drho, jx, jy, jz;
-    moments_deviation<T>(d, drho, jx, jy, jz);
-    const T rho = rho0 + drho;
-    const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    if (rho_out) rho_out[r] = rho;
-    if (u_out) {
-      u_out[r] = ux;
-      u_out[S + r] = uy;
-      u_out[2 * S + r] = uz;
+      for (int i = 0; i < 19; ++i) d[i] = src[(size_t)i * a.P + q.site_off + sidx[i]];
+      T drho, jx, jy, jz;
+      moments_deviation<T>(d, drho, jx, jy, jz);
+      const T rho = q.k.rho0 + drho;
+      if (rr == field_rep) {
+        if (rho_out) rho_out[local] = rho;
+        if (u_out) {
+          const size_t S = (size_t)q.g.S;
+          u_out[local] = jx / rho;
+          u_out[S + local] = jy / rho;
+          u_out[2 * S + local] = jz / rho;
+        }
+      }
+      const Vec4<T> jv = a.J[q.site_off + local];
+      acc[0] = (double)drho;
+      acc[1] = (double)jx;
+      acc[2] = (double)jy;
+      acc[3] = (double)jz;
+      acc[4] = (double)jv.x;
+      acc[5] = (double)jv.y;
+      acc[6] = (double)jv.z;
+      const double ux = (double)jx / (double)rho, uy = (double)jy / (double)rho,
+                   uz = (double)jz / (double)rho;
+      acc[7] = ux * ux + uy * uy + uz * uz;
     }
-    const Vec4<T> jv = J[r];
-    acc[0] += (double)drho;
-    acc[1] += (double)jx;
-    acc[2] += (double)jy;
-    acc[3] += (double)jz;
-    acc[4] += (double)jv.x;
-    acc[5] += (double)jv.y;
-    acc[6] += (double)jv.z;
-    const double dux = (double)jx / (double)rho, duy = (double)jy / (double)rho,
-                 duz = (double)jz / (double)rho;
-    acc[7] += dux * dux + duy * duy + duz * duz;
+    block_reduce_store(acc, partials + (size_t)item * kRedWidth);
   }
-  if (v) {
-    for (int p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
-      const double a = v[p], b = v[N + p], cc = v[2 * N + p];
-      acc[8] += a;
-      acc[9] += b;
-      acc[10] += cc;
-      acc[11] += a * a + b * b + cc * cc;
-    }
-  }
-  block_reduce_store(acc, partials + (size_t)blockIdx.x * kRedWidth);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
-                                                     int nblocks, double* __restrict__ totals) {
+// One block per replica: sum its items' partials, then its particles'
+// momentum and kinetic energy (columns 8-10 sum v, 11 sum |v|^2).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finalize(StreamArgs<T> a,
+                                                     const RepMD* __restrict__ md,
+                                                     const double* __restrict__ partials,
+                                                     const double* __restrict__ v, int64_t Ntot,
+                                                     double* __restrict__ totals) {
+  const int rr = blockIdx.x;
+  const int i0 = a.item_off[rr], i1 = a.item_off[rr + 1];
   double acc[kRedWidth];
 #pragma unroll
-  for (int q = 0; q < kRedWidth; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+  for (int it = i0 + threadIdx.x; it < i1; it += kBlock)
 #pragma unroll
-    for (int q = 0; q < kRedWidth; ++q) acc[q] += partials[(size_t)b * kRedWidth + q];
-  block_reduce_store(acc, totals);
+    for (int k = 0; k < 8; ++k) acc[k] += partials[(size_t)it * kRedWidth + k];
+  if (v) {
+    const int p0 = md[rr].part_off, n = md[rr].N;
+    for (int p = p0 + threadIdx.x; p < p0 + n; p += kBlock) {
+      const double vx = v[p], vy = v[Ntot + p], vz = v[2 * Ntot + p];
+      acc[8] += vx;
+      acc[9] += vy;
+      acc[10] += vz;
+      acc[11] += vx * vx + vy * vy + vz * vz;
+    }
+  }
+  block_reduce_store(acc, totals + (size_t)rr * kRedWidth);
 }
 
 template <typename T>
-static hipError_t moments_t(Context* c, void* d_rho, void* d_u, double* d_totals) {
-  const int blocks = (int)std::min<int64_t>(kRedBlocks, (c->S + kBlock - 1) / kBlock);
-  double* partials = (double*)at(c, c->lay.partials);
-  hipLaunchKernelGGL(k_moments<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
-                     (const T*)at(c, c->lay.pop[c->cur]), (const Vec4<T>*)at(c, c->lay.transfer),
-                     c->geom, (T)c->p.rho0, (T*)d_rho, (T*)d_u,
-                     (const double*)(c->bound ? c->v : nullptr), c->p.n_particles, partials);
+static hipError_t moments_t(Context* c, int rep, void* d_rho, void* d_u, double* d_totals) {
+  StreamArgs<T> a = stream_args<T>(c);
+  double* partials = (double*)at(c, c->plan.lay.partials);
+  const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
+  hipLaunchKernelGGL(k_moments<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a, rep, (T*)d_rho,
+                     (T*)d_u, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !d_totals) return e;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, partials, blocks, d_totals);
+  hipLaunchKernelGGL(k_finalize<T>, dim3(c->plan.R), dim3(kBlock), 0, c->stream, a,
+                     (const RepMD*)at(c, c->plan.lay.rep_md), partials,
+                     (const double*)(c->bound ? c->v : nullptr), c->plan.Ntot, d_totals);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(Context* c, void* d_rho, void* d_u, double* d_totals) {
-  return c->p.precision == 32 ? moments_t<float>(c, d_rho, d_u, d_totals)
-                              : moments_t<double>(c, d_rho, d_u, d_totals);
+hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals) {
+  return c->plan.prec == 32 ? moments_t<float>(c, rep, d_rho, d_u, d_totals)
+                            : moments_t<double>(c, rep, d_rho, d_u, d_totals);
 }
 
 // ---------------------------------------------------------------------------
-// Copies between pull storage and the plain post-stream layout.
+// Copies between pull storage and the plain post-stream layout of one
+// replica ([19][S] and [3][S] arrays in the run precision).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_get_pop(const T* __restrict__ pop, Geom g,
-                                                    T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_copy_pop(T* __restrict__ pop, size_t P, int site_off,
+                                                     Geom g, T* __restrict__ plain, int to_plain) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= g.S) return;
-  int x, y, z, src[19];
+  int x, y, z, sidx[19];
   site_coords(g, r, x, y, z);
-  pull_sources(g, x, y, z, src);
+  pull_sources(g, x, y, z, sidx);
   const size_t S = (size_t)g.S;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) out[(size_t)i * S + r] = pop[(size_t)i * S + src[i]];
+  for (int i = 0; i < 19; ++i) {
+    T* q = pop + (size_t)i * P + site_off + sidx[i];
+    if (to_plain)
+      plain[(size_t)i * S + r] = *q;
+    else
+      *q = plain[(size_t)i * S + r];
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_set_pop(T* __restrict__ pop, Geom g,
-                                                    const T* __restrict__ in) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= g.S) return;
-  int x, y, z, src[19];
-  site_coords(g, r, x, y, z);
-  pull_sources(g, x, y, z, src);
-  const size_t S = (size_t)g.S;
-#pragma unroll
-  for (int i = 0; i < 19; ++i) pop[(size_t)i * S + src[i]] = in[(size_t)i * S + r];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_get_transfer(const Vec4<T>* __restrict__ J, int S,
-                                                         T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_get_transfer(const Vec4<T>* __restrict__ J, int site_off,
+                                                         int S, T* __restrict__ out) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= S) return;
-  const Vec4<T> jv = J[r];
+  const Vec4<T> jv = J[site_off + r];
   out[r] = jv.x;
   out[(size_t)S + r] = jv.y;
   out[2 * (size_t)S + r] = jv.z;
 }
 
 template <typename T>
-static hipError_t copy_t(Context* c, void* dst, const void* src, int what) {
-  const int blocks = (int)((c->S + kBlock - 1) / kBlock);
-  T* pop = (T*)at(c, c->lay.pop[c->cur]);
-  if (what == 0)
-    hipLaunchKernelGGL(k_get_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop, c->geom,
-                       (T*)dst);
-  else if (what == 1)
-    hipLaunchKernelGGL(k_set_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop, c->geom,
-                       (const T*)src);
-  else
+static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
+  const lbmd_params& p = c->p[rep];
+  Geom g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.S = p.nx * p.ny * p.nz;
+  g.inv_nx = 1.0 / p.nx;
+  g.inv_ny = 1.0 / p.ny;
+  const int blocks = (g.S + kBlock - 1) / kBlock;
+  const int site_off = (int)c->plan.site_off[rep];
+  if (what == 2) {
     hipLaunchKernelGGL(k_get_transfer<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
-                       (const Vec4<T>*)at(c, c->lay.transfer), c->geom.S, (T*)dst);
+                       (const Vec4<T>*)at(c, c->plan.lay.transfer), site_off, g.S, (T*)plain);
+    return hipGetLastError();
+  }
+  T* pop = (T*)at(c, c->plan.lay.pop[c->cur]);
+  hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
+                     (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_get_populations(Context* c, void* dst) {
-  return c->p.precision == 32 ? copy_t<float>(c, dst, nullptr, 0) : copy_t<double>(c, dst, nullptr, 0);
+hipError_t launch_get_populations(Context* c, int rep, void* dst) {
+  return c->plan.prec == 32 ? copy_t<float>(c, rep, dst, 0) : copy_t<double>(c, rep, dst, 0);
 }
-hipError_t launch_set_populations(Context* c, const void* src) {
-  return c->p.precision == 32 ? copy_t<float>(c, nullptr, src, 1) : copy_t<double>(c, nullptr, src, 1);
+hipError_t launch_set_populations(Context* c, int rep, const void* src) {
+  return c->plan.prec == 32 ? copy_t<float>(c, rep, (void*)src, 1)
+                            : copy_t<double>(c, rep, (void*)src, 1);
 }
-hipError_t launch_get_transfer(Context* c, void* dst) {
-  return c->p.precision == 32 ? copy_t<float>(c, dst, nullptr, 2) : copy_t<double>(c, dst, nullptr, 2);
+hipError_t launch_get_transfer(Context* c, int rep, void* dst) {
+  return c->plan.prec == 32 ? copy_t<float>(c, rep, dst, 2) : copy_t<double>(c, rep, dst, 2);
 }
 
 }  // namespace lbmd_impl

@@ -1,73 +1,143 @@
 // Host-side context of the library and the kernel launchers behind the C ABI.
+//
+// A context holds R >= 1 independent periodic systems ("replicas") that
+// advance in lockstep: the plain API is the case R = 1.  Replica lattices are
+// concatenated in one site index space (each starting at a multiple of 64,
+// so a 64-bit mark word never spans two replicas) and particles in one
+// particle index space.  Kernels cover all replicas in one launch through
+// per-replica tables in device memory.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/lbmd.h"
 #include "lbmd_device.hpp"
 
 namespace lbmd_impl {
+using lbmd_dev::CollideConsts;
+using lbmd_dev::Geom;
+
+constexpr int kBlock = 256;  // threads per block; site chunks of the LB kernels
+constexpr int kRedWidth = 16;
+
+// Per-replica constants of the LB kernels (run precision T).
+template <typename T>
+struct RepLB {
+  Geom g;
+  int site_off;  // first global site of the replica
+  int item_off;  // first 256-site work item of the replica
+  uint32_t key0, key1, tag0, tag1;
+  CollideConsts<T> k;
+};
+
+// Per-replica constants of the particle kernels (always FP64).
+struct RepMD {
+  Geom g;
+  int site_off;
+  int part_off, N;
+  int cell_off;  // first force cell of the replica
+  int variant, noise, split_kick, force_model, chain_len;
+  uint32_t key0, key1, tag;
+  double rho0, gamma, amp, tau, h;
+  double L[3];
+  double f_ext[3];
+  double k_bond, r0_bond, wca_eps, wca_sigma;
+  int nb[3];  // force-cell grid
+  double inv_edge[3];
+};
+
+// Device step clock: read by the kernels so that a captured cycle replays
+// unchanged; advanced by a one-thread kernel at the end of each LB step.
+struct Clock {
+  long long t_lb;  // LB steps done
+  long long t_md;  // MD steps done at the start of the current LB interval
+  int cur;         // population buffer holding the current state
+  int pad;
+};
 
 // Offsets (bytes) of the regions carved out of the caller's workspace.
 struct Layout {
-  size_t pop[2];     // [19][S] population deviations, pull storage
-  size_t transfer;   // [S] Vec4<T>: pending momentum transfer J (x, y, z, unused)
-  size_t mark;       // [ceil(S/64)] uint64: bit set <=> J may be non-zero at the site
-  size_t fcons;      // [3][N] double: conservative force at the current positions
-  size_t rec_cell;   // [3][N] int32: lower corner of the particle's cube (-1: skipped)
-  size_t rec_frac;   // [3][N] double: fractional position inside the cube
-  size_t rec_dp;     // [3][N] double: momentum change dP of the current MD step
-  size_t cc;         // [32][N] T: corner cache, per corner k: 1/rho, jx, jy, jz
-  size_t cc_cell;    // [N] int32: cube (linear index of its lower corner) cached
-  size_t cc_stamp;   // [N] int32: LB step + 1 at which the cache was filled
-  size_t fc_held;    // [3][N] double: coupling force of the MD step (split kick)
-  size_t bin_count;  // [ncell] int32: particles per force cell
-  size_t bin_start;  // [ncell + 1] int32: exclusive scan of bin_count
-  size_t bin_tiles;  // [ceil(ncell / 1024)] int32: scan tile totals
-  size_t bin_of;     // [N] int32: force cell of each particle (-1: none)
-  size_t bin_rank;   // [N] int32: slot inside the cell
-  size_t bin_sorted; // [N] int32: particles ordered by cell
+  size_t pop[2];     // [19][Stot] population deviations, pull storage
+  size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z, unused)
+  size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
+  size_t rep_lb;     // [R] RepLB<T>
+  size_t rep_md;     // [R] RepMD
+  size_t item_rep;   // [R + 1] int32: work-item offsets (prefix) for the LB kernels
+  size_t part_rep;   // [Ntot] int32: replica of each particle
+  size_t clock;      // Clock
+  size_t fcons;      // [3][Ntot] double: conservative force at the current positions
+  size_t rec_cell;   // [3][Ntot] int32: lower corner of the particle's cube (-1: skipped)
+  size_t rec_frac;   // [3][Ntot] double: fractional position inside the cube
+  size_t rec_dp;     // [3][Ntot] double: momentum change dP of the current MD step
+  size_t fc_held;    // [3][Ntot] double: coupling force of the MD step (split kick)
+  size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
+  size_t cc_cell;    // [Ntot] int32: cube (lower corner, replica-local) cached
+  size_t cc_stamp;   // [Ntot] int32: LB step + 1 at which the cache was filled
+  size_t bin_count;  // [Ctot] int32: particles per force cell
+  size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
+  size_t bin_tiles;  // [ceil(Ctot / 1024) + 1] int32: scan tile totals
+  size_t bin_of;     // [Ntot] int32: global force cell of each particle (-1: none)
+  size_t bin_rank;   // [Ntot] int32: slot inside the cell
+  size_t bin_sorted; // [Ntot] int32: particles ordered by cell
   size_t flags;      // int32[16]: [0] non-finite particle seen
-  size_t partials;   // double[kRedBlocks][kRedWidth]
-  size_t totals;     // double[kRedWidth]
+  size_t partials;   // double[nitems][kRedWidth]
+  size_t totals;     // double[R][kRedWidth]
   size_t total;      // bytes needed
 };
 
-constexpr int kRedBlocks = 512;
-constexpr int kRedWidth = 16;
-constexpr int kBlock = 256;
+// Launch shapes of the persistent kernels (blocks in flight; 0 = one block
+// per work item).
+struct Tune {
+  int lb_blocks;
+  int part_blocks;
+};
+
+struct Plan {
+  int R;
+  int prec;
+  int n_sub;
+  int64_t Stot;  // padded total sites
+  int64_t Ntot;  // particles
+  int64_t Ctot;  // force cells
+  int nitems;    // 256-site work items of the LB kernels
+  bool any_forces2;
+  std::vector<int64_t> site_off, part_off, cell_off, item_off;
+  Layout lay;
+};
 
 struct Context {
-  lbmd_params p;
-  Layout lay;
+  std::vector<lbmd_params> p;  // per replica
+  Plan plan;
   hipStream_t stream;
   char* ws;
-  lbmd_dev::Geom geom;
-  int64_t S;
-  int cur;  // index of the population buffer holding the current state
-  // bound particles
+  // bound particles (concatenated over replicas)
   void* x;
   void* v;
   int32_t* img;
   bool bound;
   int64_t t_lb, t_md;
   int32_t subs;
+  int cur;  // population buffer holding the current state (mirrors Clock::cur)
   int sticky;
-  // derived collision constants (double; cast per precision at launch)
-  double gs, gb, gg, mu, ns[15];
+  Tune tune;
+  bool graph_ok;
 };
 
 inline void* at(const Context* c, size_t off) { return c->ws + off; }
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_collide_stream(Context* c);
-hipError_t launch_moments(Context* c, void* d_rho, void* d_u, double* d_totals);
-hipError_t launch_get_populations(Context* c, void* dst);
-hipError_t launch_set_populations(Context* c, const void* src);
-hipError_t launch_get_transfer(Context* c, void* dst);
-hipError_t launch_couple(Context* c);
+hipError_t launch_clock_advance(Context* c);
+hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
+hipError_t launch_get_populations(Context* c, int rep, void* dst);
+hipError_t launch_set_populations(Context* c, int rep, const void* src);
+hipError_t launch_get_transfer(Context* c, int rep, void* dst);
+hipError_t launch_couple(Context* c, int substep);
+hipError_t launch_couple_refill_only(Context* c);
 hipError_t launch_init_forces(Context* c);
 hipError_t invalidate_corner_cache(Context* c);
 hipError_t launch_forces(Context* c);

@@ -71,9 +71,22 @@ def lib():
         L.lbmd_set_counters.argtypes = [P, C.c_int64, C.c_int64, C.c_int32]
         L.lbmd_strerror.argtypes = [C.c_int]
         L.lbmd_strerror.restype = C.c_char_p
+        L.lbmd_run_cycles.argtypes = [P, C.c_int32]
+        L.lbmd_batch_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int32]
+        L.lbmd_batch_workspace_bytes.restype = C.c_size_t
+        L.lb_create_batch.argtypes = [C.POINTER(Params), C.c_int32, P, C.c_size_t, P, C.POINTER(P)]
+        L.lbmd_replica_count.argtypes = [P]
+        L.lbmd_batch_moments.argtypes = [P, P]
+        L.lbmd_batch_get_populations.argtypes = [P, C.c_int32, P]
+        L.lbmd_batch_set_populations.argtypes = [P, C.c_int32, P]
+        L.lbmd_batch_get_transfer.argtypes = [P, C.c_int32, P]
+        L.lbmd_autotune.argtypes = [P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         for n in ("lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
                   "lb_step", "lb_moments", "lbmd_get_populations", "lbmd_set_populations",
-                  "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters"):
+                  "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters",
+                  "lbmd_run_cycles", "lb_create_batch", "lbmd_replica_count",
+                  "lbmd_batch_moments", "lbmd_batch_get_populations",
+                  "lbmd_batch_set_populations", "lbmd_batch_get_transfer", "lbmd_autotune"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -111,30 +124,27 @@ def _check(rc, what):
     return rc
 
 
-class Lattice:
-    """One LB/MD system on one GPU: a periodic lattice plus N particles.
+class _System:
+    """Common part of a single system and a batch of replicas."""
 
-    >>> sim = Lattice((64, 64, 64), precision=32, n_sub=5, kT=1e-4, ...)
-    >>> sim.bind_particles(x, v)          # torch tensors [3, N] on the device
-    >>> for _ in range(steps): sim.cycle()  # n_sub MD steps + one LB step
-    """
-
-    def __init__(self, shape, device="cuda", stream=None, **kw):
-        self.shape = tuple(int(v) for v in shape)
-        self.nsites = int(np.prod(self.shape))
-        self.params = make_params(self.shape, **kw)
-        self.kw = dict(DEFAULTS, **kw)
-        self.dtype = torch.float32 if self.params.precision == 32 else torch.float64
+    def _create(self, params_array, nrep, device, stream, batch):
         self.device = torch.device(device)
-        self.N = self.params.n_particles
-        nbytes = lib().lbmd_workspace_bytes(C.byref(self.params))
+        L = lib()
+        if batch:
+            nbytes = L.lbmd_batch_workspace_bytes(params_array, nrep)
+        else:
+            nbytes = L.lbmd_workspace_bytes(params_array)
         if nbytes == 0:
-            raise LbmdError(EINVAL, "lbmd_workspace_bytes")
+            raise LbmdError(EINVAL, "workspace_bytes")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        _check(lib().lb_create(C.byref(self.params), _ptr(self.ws), nbytes,
-                               C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lb_create")
+        sp = C.c_void_p(self.stream.cuda_stream)
+        if batch:
+            rc = L.lb_create_batch(params_array, nrep, _ptr(self.ws), nbytes, sp, C.byref(h))
+        else:
+            rc = L.lb_create(params_array, _ptr(self.ws), nbytes, sp, C.byref(h))
+        _check(rc, "lb_create")
         self._h = h
         self.x = self.v = self.img = None
 
@@ -149,7 +159,62 @@ class Lattice:
         except Exception:
             pass
 
-    # ---- state -----------------------------------------------------------
+    def counters(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().lbmd_get_counters(self._h, C.byref(a), C.byref(b), C.byref(c)), "counters")
+        return dict(t_lb=a.value, t_md=b.value, subs=c.value)
+
+    def set_counters(self, t_lb, t_md, subs):
+        _check(lib().lbmd_set_counters(self._h, t_lb, t_md, subs), "set_counters")
+
+    def md_couple_substep(self):
+        return _check(lib().md_couple_substep(self._h), "md_couple_substep")
+
+    def lb_step(self):
+        return _check(lib().lb_step(self._h), "lb_step")
+
+    def cycle(self, ncycles=1):
+        """Step-by-step cycles: n_sub MD steps, then one LB step."""
+        L = lib()
+        for _ in range(ncycles):
+            if self.N > 0:
+                for _ in range(self.n_sub):
+                    rc = L.md_couple_substep(self._h)
+                    if rc != OK:
+                        raise LbmdError(rc, "md_couple_substep")
+            rc = L.lb_step(self._h)
+            if rc != OK:
+                raise LbmdError(rc, "lb_step")
+
+    def run_cycles(self, ncycles=1):
+        """The same cycles replayed from one captured HIP graph."""
+        return _check(lib().lbmd_run_cycles(self._h, int(ncycles)), "lbmd_run_cycles")
+
+    def autotune(self, cache_path=None):
+        a, b = C.c_int32(), C.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().lbmd_autotune(self._h, path, C.byref(a), C.byref(b)), "lbmd_autotune")
+        return dict(lb_blocks=a.value, part_blocks=b.value)
+
+
+class Lattice(_System):
+    """One LB/MD system on one GPU: a periodic lattice plus N particles.
+
+    >>> sim = Lattice((64, 64, 64), precision=32, n_sub=5, kT=1e-4, ...)
+    >>> sim.bind_particles(x, v)          # [3, N] arrays (FP64 on the device)
+    >>> sim.run_cycles(100)               # 100 x (n_sub MD steps + one LB step)
+    """
+
+    def __init__(self, shape, device="cuda", stream=None, **kw):
+        self.shape = tuple(int(v) for v in shape)
+        self.nsites = int(np.prod(self.shape))
+        self.params = make_params(self.shape, **kw)
+        self.kw = dict(DEFAULTS, **kw)
+        self.dtype = torch.float32 if self.params.precision == 32 else torch.float64
+        self.N = self.params.n_particles
+        self.n_sub = self.params.n_sub
+        self._create(C.byref(self.params), 1, device, stream, batch=False)
+
     def bind_particles(self, x, v, img=None):
         N = self.N
         f64 = torch.float64  # particle state is FP64 in both lattice precisions
@@ -177,34 +242,6 @@ class Lattice:
         _check(lib().lbmd_get_transfer(self._h, _ptr(out)), "lbmd_get_transfer")
         return out
 
-    def counters(self):
-        a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
-        _check(lib().lbmd_get_counters(self._h, C.byref(a), C.byref(b), C.byref(c)), "counters")
-        return dict(t_lb=a.value, t_md=b.value, subs=c.value)
-
-    def set_counters(self, t_lb, t_md, subs):
-        _check(lib().lbmd_set_counters(self._h, t_lb, t_md, subs), "set_counters")
-
-    # ---- steps -----------------------------------------------------------
-    def md_couple_substep(self):
-        return _check(lib().md_couple_substep(self._h), "md_couple_substep")
-
-    def lb_step(self):
-        return _check(lib().lb_step(self._h), "lb_step")
-
-    def cycle(self, ncycles=1):
-        n = self.params.n_sub
-        L = lib()
-        for _ in range(ncycles):
-            if self.N > 0:
-                for _ in range(n):
-                    rc = L.md_couple_substep(self._h)
-                    if rc != OK:
-                        raise LbmdError(rc, "md_couple_substep")
-            rc = L.lb_step(self._h)
-            if rc != OK:
-                raise LbmdError(rc, "lb_step")
-
     def moments(self, fields=False, allow_nonfinite=False):
         tot = np.zeros(NTOTALS)
         rho = u = None
@@ -215,3 +252,51 @@ class Lattice:
         if rc != OK and not (allow_nonfinite and rc == ENONFINITE):
             raise LbmdError(rc, "lb_moments")
         return (tot, rho, u) if fields else tot
+
+
+class Batch(_System):
+    """Independent replicas of uneven box and particle counts advanced in
+    lockstep by one launch per phase.  per_rep: list of (shape, kwargs)."""
+
+    def __init__(self, per_rep, device="cuda", stream=None):
+        self.R = len(per_rep)
+        arr = (Params * self.R)()
+        self.shapes, self.Ns = [], []
+        for r, (shape, kw) in enumerate(per_rep):
+            arr[r] = make_params(shape, **kw)
+            self.shapes.append(tuple(int(v) for v in shape))
+            self.Ns.append(arr[r].n_particles)
+        self.params = arr
+        self.dtype = torch.float32 if arr[0].precision == 32 else torch.float64
+        self.N = int(sum(self.Ns))
+        self.n_sub = arr[0].n_sub
+        self.offsets = np.concatenate([[0], np.cumsum(self.Ns)]).astype(int)
+        self._create(arr, self.R, device, stream, batch=True)
+
+    def bind_particles(self, xs, vs):
+        """xs, vs: lists of [3, N_r] arrays (replica order)."""
+        f64 = torch.float64
+        x = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in xs], 1)
+        v = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in vs], 1)
+        self.x = torch.as_tensor(x, dtype=f64, device=self.device).contiguous()
+        self.v = torch.as_tensor(v, dtype=f64, device=self.device).contiguous()
+        self.img = torch.zeros((3, self.N), dtype=torch.int32, device=self.device)
+        _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
+               "lbmd_bind_particles")
+
+    def particles(self, rep):
+        a, b = self.offsets[rep], self.offsets[rep + 1]
+        return self.x[:, a:b], self.v[:, a:b], self.img[:, a:b]
+
+    def populations(self, rep):
+        S = int(np.prod(self.shapes[rep]))
+        out = torch.empty((19, S), dtype=self.dtype, device=self.device)
+        _check(lib().lbmd_batch_get_populations(self._h, rep, _ptr(out)), "batch_get_populations")
+        return out
+
+    def moments(self, allow_nonfinite=True):
+        tot = np.zeros((self.R, NTOTALS))
+        rc = lib().lbmd_batch_moments(self._h, tot.ctypes.data_as(C.c_void_p))
+        if rc != OK and not (allow_nonfinite and rc == ENONFINITE):
+            raise LbmdError(rc, "lbmd_batch_moments")
+        return tot

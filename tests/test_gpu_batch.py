@@ -1,0 +1,178 @@
+"""Batched replicas, captured cycles and the autotuner, through the C ABI.
+
+A replica of a batch must reproduce the single system with the same
+parameters (same seed and replica id, hence the same noise) up to the order
+of floating-point sums; captured cycles must reproduce step-by-step calls;
+autotuning must leave the state unchanged.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1610_02733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_02733_amd import lbmd
+    lbmd.lib()
+    return lbmd
+
+
+def rel_pop(a, b, w, rho0):
+    return float((np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64))
+                  / (w[:, None] * rho0)).max())
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_run_cycles_equals_stepwise(lb, orc, variant):
+    c, w, e, b = orc.tables()
+    shape = (16, 12, 10)
+    x, v = wl.free_particles(shape, 50, 1e-3, 1.0, 4)
+    kw = dict(precision=64, n_sub=5, variant=variant, kT=1e-3, seed=3, n_particles=50,
+              friction=1.0)
+    a = lb.Lattice(shape, **kw)
+    a.bind_particles(x, v)
+    a.cycle(12)
+    g = lb.Lattice(shape, **kw)
+    g.bind_particles(x, v)
+    g.run_cycles(5)
+    g.cycle(2)   # mixing both paths keeps the clock consistent
+    g.run_cycles(5)
+    assert g.counters() == a.counters()
+    assert rel_pop(a.populations().cpu(), g.populations().cpu(), w, 1.0) < 1e-13
+    assert np.abs(a.x.cpu().numpy() - g.x.cpu().numpy()).max() < 1e-12
+    assert np.abs(a.v.cpu().numpy() - g.v.cpu().numpy()).max() < 1e-14
+    # and against the oracle
+    o = orc.Oracle(*shape, **{k: v_ for k, v_ in kw.items() if k != "precision"})
+    o.set_particles(x, v)
+    o.cycle(12)
+    assert rel_pop(g.populations().cpu().numpy() + w[:, None], o.populations(), w, 1.0) < 1e-12
+
+
+def make_replicas(nrep, prec, variant, seed=11):
+    rng = np.random.default_rng(seed)
+    reps, xs, vs = [], [], []
+    for r in range(nrep):
+        e = int(rng.choice([6, 8, 10, 12]))
+        shape = (e, e + (r % 3), max(4, e - 2))
+        n = int(rng.integers(0, 40)) if r != 1 else 0  # one replica without particles
+        kw = dict(precision=prec, n_sub=4, variant=variant, kT=1e-3, seed=7 + r, replica=r,
+                  n_particles=n, friction=float(rng.uniform(0.5, 3.0)),
+                  nu=float(rng.uniform(0.1, 0.5)))
+        x, v = wl.free_particles(shape, n, 1e-3, 1.0, 100 + r)
+        reps.append((shape, kw))
+        xs.append(x)
+        vs.append(v)
+    return reps, xs, vs
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_batch_replicas_match_single_runs(lb, orc, prec, variant):
+    c, w, e, b = orc.tables()
+    reps, xs, vs = make_replicas(7, prec, variant)
+    B = lb.Batch(reps)
+    B.bind_particles(xs, vs)
+    B.run_cycles(6)
+    B.cycle(2)
+    tol = 1e-12 if prec == 64 else 2e-6
+    tot = B.moments()
+    for r, (shape, kw) in enumerate(reps):
+        s = lb.Lattice(shape, **kw)
+        if kw["n_particles"] > 0:
+            s.bind_particles(xs[r], vs[r])
+        s.cycle(8)
+        assert rel_pop(B.populations(r).cpu(), s.populations().cpu(), w, 1.0) < tol, r
+        if kw["n_particles"] > 0:
+            bx, bv, bi = B.particles(r)
+            ptol = 1e-10 if prec == 64 else 1e-6  # FP32 transfer sums reorder
+            assert np.abs(bx.cpu().numpy() - s.x.cpu().numpy()).max() < ptol
+            assert np.abs(bv.cpu().numpy() - s.v.cpu().numpy()).max() < ptol
+        ts = s.moments()
+        mtol = 1e-9 if prec == 64 else 1e-6
+        assert abs(tot[r, 0] - ts[0]) < mtol * ts[0]
+        assert np.allclose(tot[r, 7:11], ts[7:11], rtol=mtol, atol=1e-12)
+
+
+def test_batch_replicas_match_oracle(lb, orc):
+    c, w, e, b = orc.tables()
+    reps, xs, vs = make_replicas(4, 64, 2, seed=5)
+    B = lb.Batch(reps)
+    B.bind_particles(xs, vs)
+    B.run_cycles(5)
+    for r, (shape, kw) in enumerate(reps):
+        o = orc.Oracle(*shape, **{k: v for k, v in kw.items() if k != "precision"})
+        if kw["n_particles"] > 0:
+            o.set_particles(xs[r], vs[r])
+        o.cycle(5)
+        assert rel_pop(B.populations(r).cpu().numpy() + w[:, None], o.populations(), w, 1.0) < 1e-12
+        if kw["n_particles"] > 0:
+            assert np.abs(B.particles(r)[1].cpu().numpy() - o.particles()[1]).max() < 1e-12
+
+
+def test_batch_nonfinite_replica_is_isolated(lb, orc):
+    c, w, e, b = orc.tables()
+    reps, xs, vs = make_replicas(5, 64, 2, seed=9)
+    for r in range(5):
+        reps[r][1]["n_particles"] = 10
+        xs[r], vs[r] = wl.free_particles(reps[r][0], 10, 1e-3, 1.0, 50 + r)
+    xs[2] = xs[2].copy()
+    xs[2][0, 3] = np.nan
+    B = lb.Batch(reps)
+    B.bind_particles(xs, vs)
+    B.run_cycles(4)
+    tot = B.moments(allow_nonfinite=True)
+    assert np.isfinite(tot[:, :12]).all()
+    for r in (0, 4):
+        s = lb.Lattice(reps[r][0], **reps[r][1])
+        s.bind_particles(xs[r], vs[r])
+        s.cycle(4)
+        assert rel_pop(B.populations(r).cpu(), s.populations().cpu(), w, 1.0) < 1e-12
+
+
+def test_autotune_leaves_state_and_caches(lb, orc, tmp_path):
+    c, w, e, b = orc.tables()
+    shape = (24, 20, 16)
+    x, v = wl.free_particles(shape, 300, 1e-3, 1.0, 6)
+    kw = dict(precision=32, n_sub=5, variant=2, kT=1e-3, seed=2, n_particles=300, friction=1.0)
+    a = lb.Lattice(shape, **kw)
+    a.bind_particles(x, v)
+    a.run_cycles(3)
+    t = lb.Lattice(shape, **kw)
+    t.bind_particles(x, v)
+    t.run_cycles(3)
+    path = str(tmp_path / "tune.json")
+    first = t.autotune(path)
+    assert os.path.exists(path)
+    cache = json.load(open(path))
+    assert len(cache) == 1 and list(cache.values())[0] == [first["lb_blocks"], first["part_blocks"]]
+    assert t.autotune(path) == first  # served from the cache
+    a.run_cycles(4)
+    t.run_cycles(4)
+    # FP32 run: the two systems differ only by the order of transfer sums
+    assert rel_pop(a.populations().cpu(), t.populations().cpu(), w, 1.0) < 2e-6
+    assert np.abs(a.x.cpu().numpy() - t.x.cpu().numpy()).max() < 1e-6
+
+
+def test_run_cycles_requires_boundary(lb):
+    shape = (8, 8, 8)
+    x, v = wl.free_particles(shape, 4, 0.0, 1.0, 1)
+    g = lb.Lattice(shape, precision=64, n_sub=3, n_particles=4, friction=1.0)
+    with pytest.raises(lb.LbmdError):
+        g.run_cycles(1)  # particles not bound
+    g.bind_particles(x, v)
+    g.md_couple_substep()
+    assert lb.lib().lbmd_run_cycles(g._h, 1) == lb.ESTATE
+    g.md_couple_substep()
+    g.md_couple_substep()
+    g.lb_step()
+    g.run_cycles(2)
+    assert g.counters() == dict(t_lb=3, t_md=9, subs=0)
