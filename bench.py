@@ -214,6 +214,69 @@ def batch_measure(lbmd, torch, nrep=512, cycles=20, serial_cycles=2):
                 mean_T_over_kT_finite=round(float(np.mean(T[ok])), 4) if ok.any() else None)
 
 
+def adjoint_measure(lbmd, torch, reps=3):
+    """Reverse mode on the 64^3 adjoint case (1000 particles under a constant
+    force, gamma = 5, kT = 1e-4, n = 5, 50 LB steps, FP32 populations,
+    variant 2): wall time of the plain forward pass (captured cycles) against
+    the backward pass (re-run of each 10-cycle segment from its saved state
+    with recording, then the adjoint sweep), for the drift gradient."""
+    from paper_1610_02733_amd import workloads as wl
+    cfg = dict(wl.CONFIGS["c5"])
+    shape, N, T, K = cfg["shape"], cfg["n_particles"], cfg["lb_steps"], 10
+    rng = np.random.default_rng(cfg["seed"])
+    x0 = rng.random((3, N)) * np.asarray(shape, float)[:, None]
+    v0 = 1e-2 * rng.standard_normal((3, N))
+    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], seed=cfg["seed"], nu=cfg["nu"],
+              friction=cfg["friction"], particle_mass=cfg["particle_mass"], precision=32,
+              n_particles=N, force_model=1, f_ext=cfg["f_ext"])
+    sim = lbmd.Lattice(shape, **kw)
+    sim.bind_particles(x0, v0)
+    states = [sim.save_state() for _ in range(T // K)]
+    sim.adjoint_attach(K)
+    xbar = torch.zeros((3, N), dtype=torch.float64, device="cuda")
+    xbar[0] = 1.0 / N
+    fwd, fwd_ck, bwd = [], [], []
+    grads = None
+    for it in range(reps + 1):
+        sim.load_state(states[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run_cycles(T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.load_state(states[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for k in range(T // K):
+            if k > 0:
+                sim.save_state(states[k])
+            sim.run_cycles(K)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sim.adjoint_seed(xbar, None)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for k in reversed(range(T // K)):
+            sim.adjoint_record(states[k], K)
+            sim.adjoint_sweep(K)
+        xb, vb, g = sim.adjoint_result()
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        if it > 0:  # the first pass warms up graphs and allocations
+            fwd.append(t1 - t0)
+            fwd_ck.append(t3 - t2)
+            bwd.append(t5 - t4)
+            grads = g
+    sim.close()
+    f, fc, b = (float(np.median(a)) for a in (fwd, fwd_ck, bwd))
+    return dict(config="64^3, 1000 particles, n=5, 50 LB steps, checkpoint 10, FP32, variant 2",
+                forward_ms=round(f * 1e3, 3), forward_with_checkpoints_ms=round(fc * 1e3, 3),
+                backward_ms=round(b * 1e3, 3), backward_over_forward=round(b / f, 3),
+                forward_plus_backward_over_forward=round((fc + b) / f, 3),
+                drift_grad={"gamma": grads["gamma"], "nu": grads["nu"],
+                            "f_ext": [float(t) for t in grads["f_ext"]]})
+
+
 def cpu_baseline(cfg, x_density_seed=3, nz=32, cycles=4):
     """FP64 oracle, single thread, on a 256 x 256 x nz slab of the workload
     (same per-site work, same particle density and parameters)."""
@@ -250,6 +313,8 @@ def main():
                          "solution, 200 chains x 50 beads, bonds + WCA")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-replica batched-ensemble measurement")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the reverse-mode (adjoint) cost measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -327,6 +392,9 @@ def main():
     if not args.no_batch:
         log("batched ensemble: 512 replicas, batched vs serial")
         out["batch"] = batch_measure(lbmd, torch)
+    if not args.no_adjoint:
+        log("adjoint: 64^3 / 1000 particles, backward vs forward")
+        out["adjoint"] = adjoint_measure(lbmd, torch)
     if not args.no_parity:
         log("parity probe: one cycle vs the FP64 oracle (sampled sites, all particles)")
         out["parity"] = parity_probe(lbmd, cfg, x, v)

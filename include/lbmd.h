@@ -215,6 +215,62 @@ int lbmd_batch_get_transfer(lbmd *c, int32_t rep, void *d_dst);
  */
 int lbmd_autotune(lbmd *c, const char *cache_path, int32_t *lb_blocks, int32_t *part_blocks);
 
+/*
+ * Saved states (checkpoint / resume).  A state holds the step counters, the
+ * populations, and the particle positions, velocities and image counters:
+ * with the counter-based noise this fixes the future trajectory exactly.
+ * d_dst / d_src: caller-owned device buffers of lbmd_state_bytes() bytes,
+ * opaque layout.  Save only at an LB-step boundary (LBMD_ESTATE otherwise;
+ * the transfer field is empty there); asynchronous.  Load restores the
+ * state into the context and the bound particle arrays; synchronizes once
+ * to read the counters.
+ */
+size_t lbmd_state_bytes(lbmd *c);
+int lbmd_save_state(lbmd *c, void *d_dst);
+int lbmd_load_state(lbmd *c, const void *d_src);
+
+/*
+ * Reverse mode (adjoint) of the coupled cycles, for a single system with
+ * force_model 0 or 1 (LBMD_EINVAL otherwise).  The method of Sec. 2-3
+ * (Eq. 3-8) is differentiated exactly along one noise realisation: the
+ * gradients are those of the deterministic map from (gamma, nu, f_ext,
+ * initial particle state) to the particle state after T cycles, with the
+ * noise variates held fixed (regenerated from their counters, never
+ * stored).
+ *
+ * Protocol: save states every K cycles on the way forward; then
+ *   lbmd_adjoint_attach(c, ws, bytes, K)      adjoint workspace for segments of <= K cycles
+ *   lbmd_adjoint_seed(c, xbar, vbar)          dL/dx(T), dL/dv(T) (device [3][N] double, nullable = 0)
+ *   for each segment, last first:
+ *     lbmd_adjoint_record(c, state, k)        re-run the k cycles from the saved state, recording
+ *     k times: lb_step_adjoint(c), then n_sub times md_couple_substep_adjoint(c)
+ *   lbmd_adjoint_result(c, xbar0, vbar0, grads)
+ * Calls out of this order return LBMD_ESTATE.  The saved state passed to
+ * lbmd_adjoint_record() is read again by the reverse steps of its segment
+ * and must stay unchanged until they are done.  Recording advances the
+ * context like the same number of forward cycles (its state afterwards is
+ * the state after the segment).
+ *
+ * lbmd_adjoint_workspace_bytes: bytes of the adjoint workspace for segments
+ * of seg_cycles cycles (0 if unsupported); about (seg_cycles + 1) population
+ * sets plus per-MD-step particle records.  d_ws must be 256-byte aligned.
+ *
+ * lbmd_adjoint_result: dL/dx and dL/dv at the start of the swept cycles
+ * (device [3][N] double, nullable) and, in h_grads (host double[5],
+ * nullable, synchronizes): dL/dgamma (friction, Eq. 4), dL/dnu (shear
+ * viscosity; with nu_bulk < 0 the bulk rate follows it), dL/df_ext[3]
+ * (constant force on every particle).
+ */
+size_t lbmd_adjoint_workspace_bytes(lbmd *c, int32_t seg_cycles);
+int lbmd_adjoint_attach(lbmd *c, void *d_ws, size_t bytes, int32_t seg_cycles);
+int lbmd_adjoint_seed(lbmd *c, const double *d_xbar, const double *d_vbar);
+int lbmd_adjoint_record(lbmd *c, const void *d_state, int32_t ncycles);
+/* reverse of one lb_step() of the recorded segment (last first) */
+int lb_step_adjoint(lbmd *c);
+/* reverse of one md_couple_substep() (last first within the cycle) */
+int md_couple_substep_adjoint(lbmd *c);
+int lbmd_adjoint_result(lbmd *c, double *d_xbar, double *d_vbar, double *h_grads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -296,6 +296,11 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->tune.lb_blocks = 0;
   c->tune.part_blocks = 0;
   c->graph_ok = false;
+  c->popv[0] = at(c, pl.lay.pop[0]);
+  c->popv[1] = at(c, pl.lay.pop[1]);
+  c->rec_part = nullptr;
+  c->rec_J = nullptr;
+  c->rec_mark = nullptr;
   // fluid at rest (all deviations zero), nothing transferred yet
   hipError_t e = hipMemsetAsync(c->ws, 0, pl.lay.total, c->stream);
   if (e == hipSuccess) e = upload_tables(c);
@@ -525,6 +530,314 @@ int lbmd_set_counters(lbmd* c, int64_t t_lb, int64_t t_md, int32_t subs) {
   int rc = fail(c, write_clock(c));
   if (rc) return rc;
   return fail(c, invalidate_corner_cache(c));
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Saved states and the reverse sweep.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Saved state: counters, the stored populations (pull storage, as held by
+// the context), particle positions, velocities and image counts.  Taken at
+// an LB-step boundary, where the transfer field is empty.
+struct StateLayout {
+  size_t counters, pop, x, v, img, total;
+};
+
+StateLayout state_layout(const Context* c) {
+  StateLayout s;
+  const size_t S = (size_t)c->plan.Stot, N = (size_t)c->plan.Ntot;
+  const size_t t = c->plan.prec == 32 ? 4 : 8;
+  size_t o = 0;
+  s.counters = o; o = up(o + 16);
+  s.pop = o; o = up(o + 19 * S * t);
+  s.x = o; o = up(o + 3 * N * 8);
+  s.v = o; o = up(o + 3 * N * 8);
+  s.img = o; o = up(o + 3 * N * 4);
+  s.total = o;
+  return s;
+}
+
+AdjLayout adj_layout(const Context* c, int K) {
+  AdjLayout L;
+  const size_t S = (size_t)c->plan.Stot, N = (size_t)std::max<int64_t>(c->plan.Ntot, 1);
+  const size_t t = c->plan.prec == 32 ? 4 : 8, n = (size_t)c->plan.n_sub, k = (size_t)K;
+  size_t o = 0;
+  L.slots = o; o = up(o + (k - 1) * 19 * S * t);
+  L.jrec = o; o = up(o + k * S * 4 * t);
+  L.mrec = o; o = up(o + k * (S / 64) * 8);
+  L.prec = o; o = up(o + k * n * kAdjRec * N * 8);
+  L.pbar[0] = o; o = up(o + 19 * S * t);
+  L.pbar[1] = o; o = up(o + 19 * S * t);
+  L.jbar = o; o = up(o + S * 4 * t);
+  L.abar = o; o = up(o + S * 4 * t);
+  L.xbar = o; o = up(o + 3 * N * 8);
+  L.vbar = o; o = up(o + 3 * N * 8);
+  L.ubar = o; o = up(o + 3 * N * 8);
+  L.pacc = o; o = up(o + 4 * N * 8);
+  L.nuacc = o; o = up(o + (size_t)kAdjBlocks * 4 * 8);
+  L.total = o;
+  return L;
+}
+
+bool adjoint_supported(const Context* c) {
+  return c->plan.R == 1 && c->p[0].force_model <= 1;
+}
+
+// Particles, counters and an empty transfer field from a saved state (the
+// populations are handled by the caller).
+int load_common(lbmd* c, const char* src, const StateLayout& sl) {
+  const size_t N = (size_t)c->plan.Ntot, S = (size_t)c->plan.Stot;
+  long long cnt[2];
+  int rc = fail(c, hipMemcpyAsync(cnt, src + sl.counters, sizeof(cnt), hipMemcpyDeviceToHost,
+                                  c->stream));
+  if (!rc) rc = fail(c, hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  if (cnt[0] < 0 || cnt[1] < 0) return LBMD_EINVAL;
+  if (N > 0) {
+    rc = fail(c, hipMemcpyAsync(c->x, src + sl.x, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(c->v, src + sl.v, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(c->img, src + sl.img, 3 * N * 4, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    if (rc) return rc;
+  }
+  const size_t t = c->plan.prec == 32 ? 4 : 8;
+  rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.transfer), 0, S * 4 * t, c->stream));
+  if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.mark), 0, (S / 64) * 8, c->stream));
+  if (rc) return rc;
+  c->t_lb = cnt[0];
+  c->t_md = cnt[1];
+  c->subs = 0;
+  rc = fail(c, write_clock(c));
+  if (!rc) rc = fail(c, invalidate_corner_cache(c));
+  if (!rc && c->bound) rc = fail(c, launch_init_forces(c));
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbmd_state_bytes(lbmd* c) { return c ? state_layout(c).total : 0; }
+
+int lbmd_save_state(lbmd* c, void* d_dst) {
+  if (!c || !d_dst) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (c->subs != 0) return LBMD_ESTATE;
+  if (c->plan.Ntot > 0 && !c->bound) return LBMD_ESTATE;
+  const StateLayout sl = state_layout(c);
+  char* dst = (char*)d_dst;
+  const size_t N = (size_t)c->plan.Ntot;
+  const size_t t = c->plan.prec == 32 ? 4 : 8;
+  int rc = fail(c, launch_store_counters(c, dst + sl.counters, c->t_lb, c->t_md));
+  if (!rc)
+    rc = fail(c, hipMemcpyAsync(dst + sl.pop, c->popv[c->cur], 19 * (size_t)c->plan.Stot * t,
+                                hipMemcpyDeviceToDevice, c->stream));
+  if (!rc && N > 0) {
+    rc = fail(c, hipMemcpyAsync(dst + sl.x, c->x, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(dst + sl.v, c->v, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(dst + sl.img, c->img, 3 * N * 4, hipMemcpyDeviceToDevice,
+                                  c->stream));
+  }
+  return rc;
+}
+
+int lbmd_load_state(lbmd* c, const void* d_src) {
+  if (!c || !d_src) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (c->plan.Ntot > 0 && !c->bound) return LBMD_ESTATE;
+  const StateLayout sl = state_layout(c);
+  const char* src = (const char*)d_src;
+  const size_t t = c->plan.prec == 32 ? 4 : 8;
+  int rc = fail(c, hipMemcpyAsync(c->popv[c->cur], src + sl.pop, 19 * (size_t)c->plan.Stot * t,
+                                  hipMemcpyDeviceToDevice, c->stream));
+  if (rc) return rc;
+  return load_common(c, src, sl);
+}
+
+size_t lbmd_adjoint_workspace_bytes(lbmd* c, int32_t seg_cycles) {
+  if (!c || seg_cycles < 1 || !adjoint_supported(c)) return 0;
+  return adj_layout(c, seg_cycles).total;
+}
+
+int lbmd_adjoint_attach(lbmd* c, void* d_ws, size_t bytes, int32_t seg_cycles) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (seg_cycles < 1 || !adjoint_supported(c) || !d_ws || ((uintptr_t)d_ws % kAlign) != 0)
+    return LBMD_EINVAL;
+  const AdjLayout L = adj_layout(c, seg_cycles);
+  if (bytes < L.total) return LBMD_ENOSPACE;
+  AdjState& a = c->adj;
+  a.attached = true;
+  a.ws = (char*)d_ws;
+  a.K = seg_cycles;
+  a.lay = L;
+  a.ncyc = 0;
+  a.slot = -1;
+  a.sub = -1;
+  a.pbar_cur = 0;
+  return LBMD_OK;
+}
+
+int lbmd_adjoint_seed(lbmd* c, const double* d_xbar, const double* d_vbar) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  AdjState& a = c->adj;
+  if (!a.attached) return LBMD_ESTATE;
+  const AdjLayout& L = a.lay;
+  const size_t N3 = 3 * (size_t)c->plan.Ntot * 8;
+  // everything from the population adjoints to the per-block sums is zeroed
+  int rc = fail(c, hipMemsetAsync(a.ws + L.pbar[0], 0, L.total - L.pbar[0], c->stream));
+  if (!rc && N3 && d_xbar)
+    rc = fail(c, hipMemcpyAsync(a.ws + L.xbar, d_xbar, N3, hipMemcpyDeviceToDevice, c->stream));
+  if (!rc && N3 && d_vbar)
+    rc = fail(c, hipMemcpyAsync(a.ws + L.vbar, d_vbar, N3, hipMemcpyDeviceToDevice, c->stream));
+  if (rc) return rc;
+  a.pbar_cur = 0;
+  a.ncyc = 0;
+  a.slot = -1;
+  a.sub = -1;
+  return LBMD_OK;
+}
+
+int lbmd_adjoint_record(lbmd* c, const void* d_state, int32_t ncycles) {
+  if (!c || !d_state) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  AdjState& a = c->adj;
+  if (!a.attached) return LBMD_ESTATE;
+  if (ncycles < 1 || ncycles > a.K) return LBMD_EINVAL;
+  if (c->plan.Ntot > 0 && !c->bound) return LBMD_ESTATE;
+  const StateLayout sl = state_layout(c);
+  const char* st = (const char*)d_state;
+  int rc = load_common(c, st, sl);
+  if (rc) return rc;
+  const AdjLayout& L = a.lay;
+  const size_t S = (size_t)c->plan.Stot, N = (size_t)c->plan.Ntot;
+  const size_t t = c->plan.prec == 32 ? 4 : 8;
+  const int n = c->plan.Ntot > 0 ? c->plan.n_sub : 0;
+  void* base[2] = {at(c, c->plan.lay.pop[0]), at(c, c->plan.lay.pop[1])};
+  auto slot_ptr = [&](int j) { return (void*)(a.ws + L.slots + (size_t)(j - 1) * 19 * S * t); };
+  a.src.assign(ncycles, nullptr);
+  a.t_lb.assign(ncycles, 0);
+  a.t_md.assign(ncycles, 0);
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < ncycles && e == hipSuccess; ++j) {
+    void* src = j == 0 ? (void*)(st + sl.pop) : slot_ptr(j);
+    void* dst = j == ncycles - 1 ? base[1 - c->cur] : slot_ptr(j + 1);
+    c->popv[c->cur] = src;
+    c->popv[1 - c->cur] = dst;
+    c->rec_part = (double*)(a.ws + L.prec) + (size_t)j * c->plan.n_sub * kAdjRec * N;
+    c->rec_J = a.ws + L.jrec + (size_t)j * S * 4 * t;
+    c->rec_mark = (unsigned long long*)(a.ws + L.mrec) + (size_t)j * (S / 64);
+    a.src[j] = src;
+    a.t_lb[j] = c->t_lb;
+    a.t_md[j] = c->t_md;
+    for (int s = 0; s < n && e == hipSuccess; ++s) e = substep_launches(c, s);
+    c->subs = n;
+    if (e == hipSuccess) e = launch_collide_stream(c);
+    if (e == hipSuccess) e = launch_clock_advance(c);
+    c->subs = 0;
+    c->cur = 1 - c->cur;
+    c->t_lb += 1;
+    c->t_md += n;
+  }
+  c->popv[0] = base[0];
+  c->popv[1] = base[1];
+  c->rec_part = nullptr;
+  c->rec_J = nullptr;
+  c->rec_mark = nullptr;
+  rc = fail(c, e);
+  if (rc) return rc;
+  a.ncyc = ncycles;
+  a.slot = ncycles - 1;
+  a.sub = -1;
+  return LBMD_OK;
+}
+
+static void adjoint_end_cycle(AdjState& a) {
+  a.pbar_cur = 1 - a.pbar_cur;
+  a.slot -= 1;
+  a.sub = -1;
+}
+
+int lb_step_adjoint(lbmd* c) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  AdjState& a = c->adj;
+  if (!a.attached || a.slot < 0 || a.sub != -1) return LBMD_ESTATE;
+  int rc = fail(c, launch_collide_stream_adjoint(c));
+  if (rc) return rc;
+  if (c->plan.Ntot > 0)
+    a.sub = c->plan.n_sub - 1;
+  else
+    adjoint_end_cycle(a);
+  return LBMD_OK;
+}
+
+int md_couple_substep_adjoint(lbmd* c) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  AdjState& a = c->adj;
+  if (!a.attached || a.slot < 0 || a.sub < 0) return LBMD_ESTATE;
+  int rc = fail(c, launch_couple_adjoint(c));
+  if (rc) return rc;
+  if (a.sub == 0) {
+    rc = fail(c, launch_adjoint_fold(c));
+    if (rc) return rc;
+    adjoint_end_cycle(a);
+  } else {
+    a.sub -= 1;
+  }
+  return LBMD_OK;
+}
+
+int lbmd_adjoint_result(lbmd* c, double* d_xbar, double* d_vbar, double* h_grads) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  AdjState& a = c->adj;
+  if (!a.attached) return LBMD_ESTATE;
+  const AdjLayout& L = a.lay;
+  const size_t N = (size_t)c->plan.Ntot;
+  int rc = LBMD_OK;
+  if (N && d_xbar)
+    rc = fail(c, hipMemcpyAsync(d_xbar, a.ws + L.xbar, 3 * N * 8, hipMemcpyDeviceToDevice,
+                                c->stream));
+  if (!rc && N && d_vbar)
+    rc = fail(c, hipMemcpyAsync(d_vbar, a.ws + L.vbar, 3 * N * 8, hipMemcpyDeviceToDevice,
+                                c->stream));
+  if (rc || !h_grads) return rc;
+  std::vector<double> pacc(4 * N), nuacc((size_t)kAdjBlocks * 4);
+  if (N)
+    rc = fail(c, hipMemcpyAsync(pacc.data(), a.ws + L.pacc, 4 * N * 8, hipMemcpyDeviceToHost,
+                                c->stream));
+  if (!rc)
+    rc = fail(c, hipMemcpyAsync(nuacc.data(), a.ws + L.nuacc, nuacc.size() * 8,
+                                hipMemcpyDeviceToHost, c->stream));
+  if (!rc) rc = fail(c, hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < 4; ++k)
+    for (size_t p = 0; p < N; ++p) g[k] += pacc[k * N + p];
+  double gb = 0.0, gs = 0.0;
+  for (int b = 0; b < kAdjBlocks; ++b) {
+    gb += nuacc[(size_t)b * 4 + 0];
+    gs += nuacc[(size_t)b * 4 + 1];
+  }
+  const lbmd_params& p = c->p[0];
+  const double dgs_dnu = 12.0 / ((6.0 * p.nu + 1.0) * (6.0 * p.nu + 1.0));
+  h_grads[0] = g[0];
+  h_grads[1] = (gs + (p.nu_bulk < 0.0 ? gb : 0.0)) * dgs_dnu;
+  h_grads[2] = g[1];
+  h_grads[3] = g[2];
+  h_grads[4] = g[3];
+  return LBMD_OK;
 }
 
 }  // extern "C"

@@ -5,7 +5,7 @@
 // reads its replica's constants.
 #include <algorithm>
 
-#include "lbmd_internal.hpp"
+#include "particle_geom.hpp"
 
 namespace lbmd_impl {
 using namespace lbmd_dev;
@@ -32,72 +32,13 @@ struct CoupleArgs {
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
   const Clock* __restrict__ clock;
+  double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
   size_t P;     // population stride
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
   int variant;
   int single;   // one replica: its constants are uniform across the grid
 };
-
-// Periodic wrap into [0, L) with image counting for any displacement
-// (x -= k L, k = floor(x / L)); a value that rounds to exactly L after the
-// shift moves to 0 in the next image.
-__device__ __forceinline__ void wrap_coord(double& x, int32_t& im, double L) {
-  if (x >= 0.0 && x < L) return;
-  double k = floor(x / L);
-  if (fabs(k) > 1e9) k = copysign(1e9, k);  // keep the image count in range
-  x -= k * L;
-  im += (int32_t)k;
-  if (x >= L) {
-    x -= L;
-    im += 1;
-  } else if (x < 0.0) {
-    x += L;
-    im -= 1;
-  }
-}
-
-// Integer cube corner from a coordinate, kept inside [0, n) whatever the
-// input (the coupling always addresses valid sites).
-__device__ __forceinline__ int cell_of(int c, int n) {
-  c %= n;
-  return c < 0 ? c + n : c;
-}
-
-// D3Q19 velocities in the library's order (opposite pairs adjacent).
-__device__ const int8_t kVel[19][3] = {
-    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
-    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-    {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-
-struct Cube {
-  int base[3];
-  double s[3];
-};
-
-__device__ __forceinline__ void cube_of(const double X[3], const Geom& g, Cube& q) {
-  const int n3[3] = {g.nx, g.ny, g.nz};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double fl = floor(X[d]);
-    q.s[d] = X[d] - fl;
-    q.base[d] = cell_of((int)fl, n3[d]);
-  }
-}
-
-// Site (replica-local) and trilinear weight (Eq. 5) of corner k of the cube.
-__device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, int& cx, int& cy,
-                                          int& cz, int& site, double& w) {
-  cx = q.base[0] + (k & 1);
-  cy = q.base[1] + ((k >> 1) & 1);
-  cz = q.base[2] + ((k >> 2) & 1);
-  cx = cx == g.nx ? 0 : cx;
-  cy = cy == g.ny ? 0 : cy;
-  cz = cz == g.nz ? 0 : cz;
-  site = cx + g.nx * (cy + g.ny * cz);
-  w = ((k & 1) ? q.s[0] : 1.0 - q.s[0]) * ((k & 2) ? q.s[1] : 1.0 - q.s[1]) *
-      ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
-}
 
 // Corner cache entry k of particle p: (jx, jy, jz, 1/rho) of the corner.
 template <typename T>
@@ -199,7 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
 // spreading kernel, because every particle must first read the velocities as
 // of the end of the previous MD step.
 // ---------------------------------------------------------------------------
-template <typename T>
+//
+// With Rec, the particle's position and velocity before the step and the
+// corner velocities (j [+ J]) and inverse densities it interpolated are
+// recorded for the reverse sweep (position NaN: particle skipped).
+template <typename T, bool Rec>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   __shared__ int sh_rep[kBlock];
   __shared__ int sh_base[3][kBlock];
@@ -227,6 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       if (!live) {
         a.flags[0] = 1;
         if (a.variant == 2) a.rec_cell[p] = -1;
+        if (Rec) a.rec[p] = __builtin_nan("");
       }
     }
     Cube q;
@@ -279,6 +225,19 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         u[0] += wi * jx;
         u[1] += wi * jy;
         u[2] += wi * jz;
+        if (Rec) {
+          a.rec[(6 + 3 * k) * N + p] = jx;
+          a.rec[(7 + 3 * k) * N + p] = jy;
+          a.rec[(8 + 3 * k) * N + p] = jz;
+          a.rec[(30 + k) * N + p] = (double)cv[k].w;
+        }
+      }
+      if (Rec) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.rec[d * N + p] = X[d];
+          a.rec[(3 + d) * N + p] = V[d];
+        }
       }
       // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
       double xi[3] = {0.0, 0.0, 0.0};
@@ -383,8 +342,8 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.v = (double*)c->v;
   a.img = c->img;
   a.fcons = (const double*)at(c, L.fcons);
-  a.pop[0] = (T*)at(c, L.pop[0]);
-  a.pop[1] = (T*)at(c, L.pop[1]);
+  a.pop[0] = (T*)c->popv[0];
+  a.pop[1] = (T*)c->popv[1];
   a.J = (Vec4<T>*)at(c, L.transfer);
   a.mark = (unsigned long long*)at(c, L.mark);
   a.rec_cell = (int32_t*)at(c, L.rec_cell);
@@ -398,6 +357,7 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
   a.clock = (const Clock*)at(c, L.clock);
+  a.rec = c->rec_part ? c->rec_part + (size_t)substep * kAdjRec * (size_t)c->plan.Ntot : nullptr;
   a.P = (size_t)c->plan.Stot;
   a.N = c->plan.Ntot;
   a.substep = substep;
@@ -422,8 +382,11 @@ static hipError_t couple_t(Context* c, int substep) {
                        dim3(kBlock), 0, c->stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_couple<T>, dim3(grid_for((N + kBlock - 1) / kBlock, c->tune.part_blocks)),
-                     dim3(kBlock), 0, c->stream, a);
+  const dim3 cgrid(grid_for((N + kBlock - 1) / kBlock, c->tune.part_blocks));
+  if (a.rec)
+    hipLaunchKernelGGL((k_couple<T, true>), cgrid, dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_couple<T, false>), cgrid, dim3(kBlock), 0, c->stream, a);
   if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
   hipLaunchKernelGGL(k_spread<T>, dim3(grid_for((N * 24 + kBlock - 1) / kBlock, c->tune.part_blocks)),
                      dim3(kBlock), 0, c->stream, a);

@@ -46,11 +46,16 @@ struct StreamArgs {
   const RepLB<T>* __restrict__ rep;
   const int32_t* __restrict__ item_off;
   const Clock* __restrict__ clock;
+  Vec4<T>* __restrict__ jrec;                 // recording: J consumed at marked sites
+  unsigned long long* __restrict__ mrec;      // recording: mark words
   size_t P;  // population stride (padded total sites)
   int R, nitems;
 };
 
-template <typename T>
+// With Rec, the transfer field and the mark words the step consumes are also
+// copied out for the reverse sweep (the adjoint needs the force density of
+// the step and the set of sites the MD steps touched).
+template <typename T, bool Rec>
 __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   const int cur = a.clock->cur;
   const long long t = a.clock->t_lb;
@@ -83,7 +88,9 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
       Fy += jv.y;
       Fz += jv.z;
       a.J[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
+      if (Rec) a.jrec[gsite] = jv;
     }
+    if (Rec && (gsite & 63) == 0) a.mrec[gsite >> 6] = word;
     uint32_t hw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (q.k.noise) {
       const Words4 o0 = philox10(Words4{(uint32_t)local, step_lo, q.tag0, step_hi}, q.key0, q.key1);
@@ -103,9 +110,11 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
 template <typename T>
 static StreamArgs<T> stream_args(Context* c) {
   StreamArgs<T> a;
-  a.pop[0] = (T*)at(c, c->plan.lay.pop[0]);
-  a.pop[1] = (T*)at(c, c->plan.lay.pop[1]);
+  a.pop[0] = (T*)c->popv[0];
+  a.pop[1] = (T*)c->popv[1];
   a.J = (Vec4<T>*)at(c, c->plan.lay.transfer);
+  a.jrec = (Vec4<T>*)c->rec_J;
+  a.mrec = c->rec_mark;
   a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
@@ -120,7 +129,10 @@ template <typename T>
 static hipError_t collide_stream_t(Context* c) {
   StreamArgs<T> a = stream_args<T>(c);
   const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
-  hipLaunchKernelGGL(k_collide_stream<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
+  if (a.jrec)
+    hipLaunchKernelGGL((k_collide_stream<T, true>), dim3(blocks), dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_collide_stream<T, false>), dim3(blocks), dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }
 
@@ -314,7 +326,7 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
                        (const Vec4<T>*)at(c, c->plan.lay.transfer), site_off, g.S, (T*)plain);
     return hipGetLastError();
   }
-  T* pop = (T*)at(c, c->plan.lay.pop[c->cur]);
+  T* pop = (T*)c->popv[c->cur];
   hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
                      (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0);
   return hipGetLastError();

@@ -220,6 +220,195 @@ __host__ __device__ __forceinline__ void collide_deviation(T d[19], T Fx, T Fy, 
   d[18] = (Ehi - Ohi) * w2;
 }
 
+// All 19 modes m_k = sum_i e_k(c_i) d_i of a population vector.
+template <typename T>
+__host__ __device__ __forceinline__ void modes19(const T d[19], T m[19]) {
+  const T s12 = d[1] + d[2], a12 = d[1] - d[2];
+  const T s34 = d[3] + d[4], a34 = d[3] - d[4];
+  const T s56 = d[5] + d[6], a56 = d[5] - d[6];
+  const T s78 = d[7] + d[8], a78 = d[7] - d[8];
+  const T s9a = d[9] + d[10], a9a = d[9] - d[10];
+  const T sbc = d[11] + d[12], abc = d[11] - d[12];
+  const T sde = d[13] + d[14], ade = d[13] - d[14];
+  const T sfg = d[15] + d[16], afg = d[15] - d[16];
+  const T shi = d[17] + d[18], ahi = d[17] - d[18];
+  const T sxy = s78 + s9a, sxz = sbc + sde, syz = sfg + shi;
+  const T sdiag = sxy + sxz + syz, saxis = s12 + s34 + s56;
+  m[0] = d[0] + saxis + sdiag;
+  m[1] = a12 + a78 + a9a + abc + ade;
+  m[2] = a34 + a78 - a9a + afg + ahi;
+  m[3] = a56 + abc - ade + afg - ahi;
+  m[4] = sdiag - d[0];
+  m[5] = T(2) * s12 - s34 - s56 + sxy + sxz - T(2) * syz;
+  m[6] = s34 - s56 + sxy - sxz;
+  m[7] = s78 - s9a;
+  m[8] = sfg - shi;
+  m[9] = sbc - sde;
+  m[10] = a78 + a9a + abc + ade - T(2) * a12;
+  m[11] = a78 - a9a + afg + ahi - T(2) * a34;
+  m[12] = abc - ade + afg - ahi - T(2) * a56;
+  m[13] = a78 + a9a - abc - ade;
+  m[14] = a9a - a78 + afg + ahi;
+  m[15] = abc - ade - afg + ahi;
+  m[16] = d[0] - T(2) * saxis + sdiag;
+  m[17] = s34 + s56 - T(2) * s12 + sxy + sxz - T(2) * syz;
+  m[18] = s56 - s34 + sxy - sxz;
+}
+
+// Transpose of the mode map: d_i = sum_k e_k(c_i) m_k.
+template <typename T>
+__host__ __device__ __forceinline__ void modes19_transpose(const T m[19], T d[19]) {
+  d[0] = m[0] - m[4] + m[16];
+  const T Eax = m[0] - T(2) * m[16] + m[17];
+  const T Ex = m[0] + T(2) * m[5] - T(2) * m[16] - T(2) * m[17], Ox = m[1] - T(2) * m[10];
+  const T Ey = Eax - m[5] + m[6] - m[18], Oy = m[2] - T(2) * m[11];
+  const T Ez = Eax - m[5] - m[6] + m[18], Oz = m[3] - T(2) * m[12];
+  d[1] = Ex + Ox;
+  d[2] = Ex - Ox;
+  d[3] = Ey + Oy;
+  d[4] = Ey - Oy;
+  d[5] = Ez + Oz;
+  d[6] = Ez - Oz;
+  const T D = m[0] + m[4] + m[16];
+  const T Dxy = D + m[5] + m[6] + m[17] + m[18];
+  const T Dxz = D + m[5] - m[6] + m[17] - m[18];
+  const T Dyz = D - T(2) * m[5] - T(2) * m[17];
+  const T E78 = Dxy + m[7], O78 = m[1] + m[2] + m[10] + m[11] + m[13] - m[14];
+  const T E9a = Dxy - m[7], O9a = m[1] - m[2] + m[10] - m[11] + m[13] + m[14];
+  const T Ebc = Dxz + m[9], Obc = m[1] + m[3] + m[10] + m[12] - m[13] + m[15];
+  const T Ede = Dxz - m[9], Ode = m[1] - m[3] + m[10] - m[12] - m[13] - m[15];
+  const T Efg = Dyz + m[8], Ofg = m[2] + m[3] + m[11] + m[12] + m[14] - m[15];
+  const T Ehi = Dyz - m[8], Ohi = m[2] - m[3] + m[11] - m[12] + m[14] + m[15];
+  d[7] = E78 + O78;
+  d[8] = E78 - O78;
+  d[9] = E9a + O9a;
+  d[10] = E9a - O9a;
+  d[11] = Ebc + Obc;
+  d[12] = Ebc - Obc;
+  d[13] = Ede + Ode;
+  d[14] = Ede - Ode;
+  d[15] = Efg + Ofg;
+  d[16] = Efg - Ofg;
+  d[17] = Ehi + Ohi;
+  d[18] = Ehi - Ohi;
+}
+
+// Reverse mode of collide_deviation.  Inputs: the collision's inputs (d, F,
+// noise words) and the adjoint of its outputs (dbar_out).  Outputs: the
+// adjoint of the input deviations (dbar_in), of the force density (Fb), and
+// the derivatives of the result with respect to the relaxation factors of
+// the bulk, shear and kinetic modes (gbar[0..2]).  The noise enters through
+// its amplitude sqrt(mu rho b_k (1 - g_k^2)); the variates themselves are
+// fixed numbers of the counter-based stream.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_deviation_adjoint(
+    const T d[19], T Fx, T Fy, T Fz, const uint32_t hw[8], const CollideConsts<T>& k,
+    const T dbar_out[19], T dbar_in[19], T& Fbx, T& Fby, T& Fbz, T gbar[3]) {
+  // forward intermediates
+  T m[19];
+  modes19<T>(d, m);
+  const T rho = k.rho0 + m[0];
+  const T irho = T(1) / rho;
+  const T ux = (m[1] + T(0.5) * Fx) * irho;
+  const T uy = (m[2] + T(0.5) * Fy) * irho;
+  const T uz = (m[3] + T(0.5) * Fz) * irho;
+  const T xx = ux * ux, yy = uy * uy, zz = uz * uz;
+  const T e[6] = {rho * (xx + yy + zz), rho * (T(2) * xx - yy - zz), rho * (yy - zz),
+                  rho * ux * uy,        rho * uy * uz,                rho * ux * uz};
+  const T fx = ux * Fx, fy = uy * Fy, fz = uz * Fz;
+  const T q[6] = {T(2) * (fx + fy + fz), T(2) * (T(2) * fx - fy - fz), T(2) * (fy - fz),
+                  ux * Fy + uy * Fx,     uy * Fz + uz * Fy,            ux * Fz + uz * Fx};
+  // back transform: d_out = W E^T (m* / b)  ->  Mbar = E (W dbar_out)
+  const T w0 = T(1) / T(3), w1 = T(1) / T(18), w2 = T(1) / T(36);
+  T y[19];
+  y[0] = w0 * dbar_out[0];
+#pragma unroll
+  for (int i = 1; i < 7; ++i) y[i] = w1 * dbar_out[i];
+#pragma unroll
+  for (int i = 7; i < 19; ++i) y[i] = w2 * dbar_out[i];
+  T Mb[19];
+  modes19<T>(y, Mb);
+  // m*_k = b_k M_k: the adjoint of m*_k is Mbar_k / b_k
+  const T ib[19] = {T(1),   T(3),   T(3),   T(3),   T(1.5), T(0.75), T(2.25),
+                    T(9),   T(9),   T(9),   T(1.5), T(1.5), T(1.5),  T(4.5),
+                    T(4.5), T(4.5), T(0.5), T(0.75), T(2.25)};
+  T ps[19];
+#pragma unroll
+  for (int kk = 0; kk < 19; ++kk) ps[kk] = Mb[kk] * ib[kk];
+  // m*_0 = rho - rho0 (deviation), m*_{1..3} = j + F
+  T mb[19];
+  T rhob = T(0);
+  mb[0] = ps[0];
+  mb[1] = ps[1];
+  mb[2] = ps[2];
+  mb[3] = ps[3];
+  Fbx = ps[1];
+  Fby = ps[2];
+  Fbz = ps[3];
+  gbar[0] = gbar[1] = gbar[2] = T(0);
+  // noise on modes 4..18
+  if (k.noise) {
+    const T amp = tsqrt<T>(k.mu * rho);
+    const T damp = amp > T(0) ? T(0.5) * k.mu / amp : T(0);
+#pragma unroll
+    for (int v = 0; v < 15; ++v) {
+      const uint32_t w = hw[v >> 1];
+      const uint32_t h = (v & 1) ? (w >> 16) : (w & 0xFFFFu);
+      const T cv = (T)(int)h - T(32767.5);
+      const T pb = ps[v + 4];
+      rhob += pb * k.ns[v] * cv * damp;
+      // ns = K sqrt(1 - g^2): d ns / d g = -ns g / (1 - g^2)
+      const int cls = v == 0 ? 0 : (v <= 5 ? 1 : 2);
+      const T g = cls == 0 ? k.gb : (cls == 1 ? k.gs : k.gg);
+      gbar[cls] += pb * amp * cv * (-k.ns[v] * g / (T(1) - g * g));
+    }
+  }
+  // relaxation of the stress modes (k = 4..9) and Guo source
+  T eb[6], qb[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const T g = s == 0 ? k.gb : k.gs;
+    const T h = s == 0 ? k.hb : k.hs;
+    const T pb = ps[4 + s];
+    eb[s] = (T(1) - g) * pb;
+    mb[4 + s] = g * pb;
+    qb[s] = h * pb;
+    gbar[s == 0 ? 0 : 1] += pb * (m[4 + s] - e[s]) + T(0.5) * pb * q[s];
+  }
+  // kinetic modes relax to zero
+#pragma unroll
+  for (int kk = 10; kk < 19; ++kk) {
+    mb[kk] = k.gg * ps[kk];
+    gbar[2] += ps[kk] * m[kk];
+  }
+  // equilibrium e(rho, u)
+  rhob += eb[0] * (xx + yy + zz) + eb[1] * (T(2) * xx - yy - zz) + eb[2] * (yy - zz) +
+          eb[3] * ux * uy + eb[4] * uy * uz + eb[5] * ux * uz;
+  T ubx = rho * (eb[0] * T(2) * ux + eb[1] * T(4) * ux + eb[3] * uy + eb[5] * uz);
+  T uby = rho * (eb[0] * T(2) * uy - eb[1] * T(2) * uy + eb[2] * T(2) * uy + eb[3] * ux +
+                 eb[4] * uz);
+  T ubz = rho * (eb[0] * T(2) * uz - eb[1] * T(2) * uz - eb[2] * T(2) * uz + eb[4] * uy +
+                 eb[5] * ux);
+  // Guo source q(u, F)
+  ubx += T(2) * qb[0] * Fx + T(4) * qb[1] * Fx + qb[3] * Fy + qb[5] * Fz;
+  uby += T(2) * qb[0] * Fy - T(2) * qb[1] * Fy + T(2) * qb[2] * Fy + qb[3] * Fx + qb[4] * Fz;
+  ubz += T(2) * qb[0] * Fz - T(2) * qb[1] * Fz - T(2) * qb[2] * Fz + qb[4] * Fy + qb[5] * Fx;
+  Fbx += T(2) * qb[0] * ux + T(4) * qb[1] * ux + qb[3] * uy + qb[5] * uz;
+  Fby += T(2) * qb[0] * uy - T(2) * qb[1] * uy + T(2) * qb[2] * uy + qb[3] * ux + qb[4] * uz;
+  Fbz += T(2) * qb[0] * uz - T(2) * qb[1] * uz - T(2) * qb[2] * uz + qb[4] * uy + qb[5] * ux;
+  // u = (j + F/2) / rho
+  mb[1] += ubx * irho;
+  mb[2] += uby * irho;
+  mb[3] += ubz * irho;
+  Fbx += T(0.5) * ubx * irho;
+  Fby += T(0.5) * uby * irho;
+  Fbz += T(0.5) * ubz * irho;
+  rhob -= (ubx * ux + uby * uy + ubz * uz) * irho;
+  // rho = rho0 + m_0
+  mb[0] += rhob;
+  modes19_transpose<T>(mb, dbar_in);
+}
+
 // Density deviation and momentum of 19 population deviations.
 template <typename T>
 __host__ __device__ __forceinline__ void moments_deviation(const T d[19], T& drho, T& jx, T& jy,

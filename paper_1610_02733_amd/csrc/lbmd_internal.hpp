@@ -109,11 +109,56 @@ struct Plan {
   Layout lay;
 };
 
+// Reverse-mode state (one system, force models 0 and 1).  A segment of up
+// to K cycles is re-run forward with recording: cycle j reads populations
+// from slot j (slot 0 is the caller's saved state, slots 1..K-1 live in the
+// adjoint workspace) and records the transfer field and mark words its LB
+// step consumed and, per MD step, the particle state and the corner
+// velocities it interpolated.  The reverse sweep then walks the recorded
+// cycles backwards.
+struct AdjLayout {
+  size_t slots;    // [K-1][19][Stot] T: populations read by cycles 1..K-1
+  size_t jrec;     // [K][Stot] Vec4<T>: transfer field at the LB step (valid at marked sites)
+  size_t mrec;     // [K][Stot/64] uint64: mark words at the LB step
+  size_t prec;     // [K][n_sub][kAdjRec][Ntot] double: particle records
+  size_t pbar[2];  // [19][Stot] T: adjoint of the stored (post-collision) populations
+  size_t jbar;     // [Stot] Vec4<T>: adjoint of the transfer field
+  size_t abar;     // [Stot] Vec4<T>: adjoint of (j, rho) read by the MD steps
+  size_t xbar, vbar, ubar;  // [3][Ntot] double
+  size_t pacc;     // [4][Ntot] double: per particle d/dgamma, d/df_ext
+  size_t nuacc;    // [kAdjBlocks][4] double: per block d/dgamma_{bulk, shear, ghost}
+  size_t total;
+};
+
+constexpr int kAdjRec = 38;       // X[3], V[3], U[8][3], 1/rho[8]
+constexpr int kAdjBlocks = 2048;  // persistent grid of the adjoint LB kernel
+
+struct AdjState {
+  bool attached = false;
+  char* ws = nullptr;
+  int K = 0;
+  AdjLayout lay;
+  int ncyc = 0;     // cycles recorded
+  int slot = -1;    // cycle the reverse sweep is in
+  int sub = -1;     // next MD step to reverse (-1: the LB step is next)
+  int pbar_cur = 0; // pbar buffer holding the adjoint of the current slot's output
+  std::vector<const void*> src;  // populations read by each recorded cycle
+  std::vector<int64_t> t_lb, t_md;
+};
+
 struct Context {
   std::vector<lbmd_params> p;  // per replica
   Plan plan;
   hipStream_t stream;
   char* ws;
+  // population buffers the kernels read and write (pull storage); the
+  // workspace pair, except while a segment is re-run for the adjoint
+  void* popv[2];
+  // recording targets of the forward kernels (null when not recording)
+  double* rec_part;
+  void* rec_J;
+  unsigned long long* rec_mark;
+  AdjState adj;
   // bound particles (concatenated over replicas)
   void* x;
   void* v;
@@ -131,6 +176,10 @@ inline void* at(const Context* c, size_t off) { return c->ws + off; }
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_collide_stream(Context* c);
+hipError_t launch_collide_stream_adjoint(Context* c);
+hipError_t launch_couple_adjoint(Context* c);
+hipError_t launch_adjoint_fold(Context* c);
+hipError_t launch_store_counters(Context* c, void* dst, int64_t t_lb, int64_t t_md);
 hipError_t launch_clock_advance(Context* c);
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
 hipError_t launch_get_populations(Context* c, int rep, void* dst);

@@ -1,0 +1,71 @@
+// Device helpers shared by the particle kernels and their adjoints: periodic
+// wrap with image counting, the cube of lattice sites around a particle and
+// the trilinear weights of its corners (Eq. 5).
+#pragma once
+
+#include "lbmd_internal.hpp"
+
+namespace lbmd_impl {
+using namespace lbmd_dev;
+
+// Periodic wrap into [0, L) with image counting for any displacement
+// (x -= k L, k = floor(x / L)); a value that rounds to exactly L after the
+// shift moves to 0 in the next image.
+__device__ __forceinline__ void wrap_coord(double& x, int32_t& im, double L) {
+  if (x >= 0.0 && x < L) return;
+  double k = floor(x / L);
+  if (fabs(k) > 1e9) k = copysign(1e9, k);  // keep the image count in range
+  x -= k * L;
+  im += (int32_t)k;
+  if (x >= L) {
+    x -= L;
+    im += 1;
+  } else if (x < 0.0) {
+    x += L;
+    im -= 1;
+  }
+}
+
+// Integer cube corner from a coordinate, kept inside [0, n) whatever the
+// input (the coupling always addresses valid sites).
+__device__ __forceinline__ int cell_of(int c, int n) {
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+// D3Q19 velocities in the library's order (opposite pairs adjacent).
+static __device__ const int8_t kVel[19][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+struct Cube {
+  int base[3];
+  double s[3];
+};
+
+__device__ __forceinline__ void cube_of(const double X[3], const Geom& g, Cube& q) {
+  const int n3[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double fl = floor(X[d]);
+    q.s[d] = X[d] - fl;
+    q.base[d] = cell_of((int)fl, n3[d]);
+  }
+}
+
+// Site (replica-local) and trilinear weight (Eq. 5) of corner k of the cube.
+__device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, int& cx, int& cy,
+                                          int& cz, int& site, double& w) {
+  cx = q.base[0] + (k & 1);
+  cy = q.base[1] + ((k >> 1) & 1);
+  cz = q.base[2] + ((k >> 2) & 1);
+  cx = cx == g.nx ? 0 : cx;
+  cy = cy == g.ny ? 0 : cy;
+  cz = cz == g.nz ? 0 : cz;
+  site = cx + g.nx * (cy + g.ny * cz);
+  w = ((k & 1) ? q.s[0] : 1.0 - q.s[0]) * ((k & 2) ? q.s[1] : 1.0 - q.s[1]) *
+      ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
+}
+
+}  // namespace lbmd_impl

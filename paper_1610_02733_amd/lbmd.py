@@ -81,12 +81,27 @@ def lib():
         L.lbmd_batch_set_populations.argtypes = [P, C.c_int32, P]
         L.lbmd_batch_get_transfer.argtypes = [P, C.c_int32, P]
         L.lbmd_autotune.argtypes = [P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.lbmd_state_bytes.argtypes = [P]
+        L.lbmd_state_bytes.restype = C.c_size_t
+        L.lbmd_save_state.argtypes = [P, P]
+        L.lbmd_load_state.argtypes = [P, P]
+        L.lbmd_adjoint_workspace_bytes.argtypes = [P, C.c_int32]
+        L.lbmd_adjoint_workspace_bytes.restype = C.c_size_t
+        L.lbmd_adjoint_attach.argtypes = [P, P, C.c_size_t, C.c_int32]
+        L.lbmd_adjoint_seed.argtypes = [P, P, P]
+        L.lbmd_adjoint_record.argtypes = [P, P, C.c_int32]
+        L.lb_step_adjoint.argtypes = [P]
+        L.md_couple_substep_adjoint.argtypes = [P]
+        L.lbmd_adjoint_result.argtypes = [P, P, P, P]
         for n in ("lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
                   "lb_step", "lb_moments", "lbmd_get_populations", "lbmd_set_populations",
                   "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters",
                   "lbmd_run_cycles", "lb_create_batch", "lbmd_replica_count",
                   "lbmd_batch_moments", "lbmd_batch_get_populations",
-                  "lbmd_batch_set_populations", "lbmd_batch_get_transfer", "lbmd_autotune"):
+                  "lbmd_batch_set_populations", "lbmd_batch_get_transfer", "lbmd_autotune",
+                  "lbmd_save_state", "lbmd_load_state", "lbmd_adjoint_attach",
+                  "lbmd_adjoint_seed", "lbmd_adjoint_record", "lb_step_adjoint",
+                  "md_couple_substep_adjoint", "lbmd_adjoint_result"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -190,6 +205,19 @@ class _System:
         """The same cycles replayed from one captured HIP graph."""
         return _check(lib().lbmd_run_cycles(self._h, int(ncycles)), "lbmd_run_cycles")
 
+    def save_state(self, out=None):
+        """Checkpoint at an LB-step boundary into a device byte tensor."""
+        n = lib().lbmd_state_bytes(self._h)
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        elif out.numel() < n:
+            raise LbmdError(ENOSPACE, "lbmd_save_state")
+        _check(lib().lbmd_save_state(self._h, _ptr(out)), "lbmd_save_state")
+        return out
+
+    def load_state(self, state):
+        _check(lib().lbmd_load_state(self._h, _ptr(state)), "lbmd_load_state")
+
     def autotune(self, cache_path=None):
         a, b = C.c_int32(), C.c_int32()
         path = cache_path.encode() if cache_path else None
@@ -216,14 +244,16 @@ class Lattice(_System):
         self._create(C.byref(self.params), 1, device, stream, batch=False)
 
     def bind_particles(self, x, v, img=None):
+        """Copies x, v (and img) into arrays owned by this object, which the
+        library then advances in place (self.x, self.v, self.img)."""
         N = self.N
         f64 = torch.float64  # particle state is FP64 in both lattice precisions
-        self.x = torch.as_tensor(x, dtype=f64, device=self.device).reshape(3, N).contiguous()
-        self.v = torch.as_tensor(v, dtype=f64, device=self.device).reshape(3, N).contiguous()
+        self.x = torch.as_tensor(x, dtype=f64, device=self.device).reshape(3, N).clone()
+        self.v = torch.as_tensor(v, dtype=f64, device=self.device).reshape(3, N).clone()
         if img is None:
             self.img = torch.zeros((3, N), dtype=torch.int32, device=self.device)
         else:
-            self.img = torch.as_tensor(img, dtype=torch.int32, device=self.device).reshape(3, N).contiguous()
+            self.img = torch.as_tensor(img, dtype=torch.int32, device=self.device).reshape(3, N).clone()
         _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
                "lbmd_bind_particles")
 
@@ -254,6 +284,54 @@ class Lattice(_System):
         return (tot, rho, u) if fields else tot
 
 
+    # -- reverse mode ---------------------------------------------------------
+    def adjoint_attach(self, seg_cycles):
+        n = lib().lbmd_adjoint_workspace_bytes(self._h, int(seg_cycles))
+        if n == 0:
+            raise LbmdError(EINVAL, "lbmd_adjoint_workspace_bytes")
+        self.adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().lbmd_adjoint_attach(self._h, _ptr(self.adj_ws), n, int(seg_cycles)),
+               "lbmd_adjoint_attach")
+
+    def adjoint_seed(self, xbar=None, vbar=None):
+        f64 = torch.float64
+        xb = None if xbar is None else torch.as_tensor(xbar, dtype=f64, device=self.device).reshape(3, self.N).contiguous()
+        vb = None if vbar is None else torch.as_tensor(vbar, dtype=f64, device=self.device).reshape(3, self.N).contiguous()
+        _check(lib().lbmd_adjoint_seed(self._h, _ptr(xb), _ptr(vb)), "lbmd_adjoint_seed")
+        torch.cuda.current_stream(self.device).synchronize()  # xb, vb may be freed
+
+    def adjoint_record(self, state, ncycles):
+        _check(lib().lbmd_adjoint_record(self._h, _ptr(state), int(ncycles)), "lbmd_adjoint_record")
+
+    def lb_step_adjoint(self):
+        return _check(lib().lb_step_adjoint(self._h), "lb_step_adjoint")
+
+    def md_couple_substep_adjoint(self):
+        return _check(lib().md_couple_substep_adjoint(self._h), "md_couple_substep_adjoint")
+
+    def adjoint_sweep(self, ncycles):
+        """Reverse of the last `ncycles` recorded cycles."""
+        L = lib()
+        for _ in range(ncycles):
+            rc = L.lb_step_adjoint(self._h)
+            if rc != OK:
+                raise LbmdError(rc, "lb_step_adjoint")
+            if self.N > 0:
+                for _ in range(self.n_sub):
+                    rc = L.md_couple_substep_adjoint(self._h)
+                    if rc != OK:
+                        raise LbmdError(rc, "md_couple_substep_adjoint")
+
+    def adjoint_result(self):
+        """(dL/dx0 [3, N], dL/dv0 [3, N], grads) with grads = dict(gamma, nu, f_ext[3])."""
+        xb = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        vb = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        g = np.zeros(5)
+        _check(lib().lbmd_adjoint_result(self._h, _ptr(xb), _ptr(vb), g.ctypes.data_as(C.c_void_p)),
+               "lbmd_adjoint_result")
+        return xb, vb, dict(gamma=g[0], nu=g[1], f_ext=g[2:5].copy())
+
+
 class Batch(_System):
     """Independent replicas of uneven box and particle counts advanced in
     lockstep by one launch per phase.  per_rep: list of (shape, kwargs)."""
@@ -278,8 +356,8 @@ class Batch(_System):
         f64 = torch.float64
         x = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in xs], 1)
         v = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in vs], 1)
-        self.x = torch.as_tensor(x, dtype=f64, device=self.device).contiguous()
-        self.v = torch.as_tensor(v, dtype=f64, device=self.device).contiguous()
+        self.x = torch.as_tensor(x, dtype=f64, device=self.device).clone()
+        self.v = torch.as_tensor(v, dtype=f64, device=self.device).clone()
         self.img = torch.zeros((3, self.N), dtype=torch.int32, device=self.device)
         _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
                "lbmd_bind_particles")

@@ -1,0 +1,271 @@
+"""Reverse mode through the C ABI: saved states, the recorded re-run and the
+adjoint sweep.
+
+Gradients of particle observables with respect to gamma, nu, f_ext and the
+initial particle state are compared with torch.autograd through the FP64
+reference (``oracle/torch_oracle.py``) on small systems, and with central
+finite differences of the library's own forward runs (FP64, h = 1e-4) on
+the 64^3 / 1000-particle adjoint case, all along one noise realisation.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1610_02733_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_02733_amd import lbmd
+    lbmd.lib()
+    return lbmd
+
+
+def scalar(v):
+    return torch.tensor(float(v), dtype=torch.float64, device="cuda", requires_grad=True)
+
+
+def run_gpu(shape, x0, v0, gamma, nu, fext, cycles, checkpoint, pops=None, **kw):
+    from paper_1610_02733_amd.adjoint import coupled_run
+    g, n = scalar(gamma), scalar(nu)
+    fe = torch.tensor(fext, dtype=torch.float64, device="cuda", requires_grad=True)
+    x0t = torch.tensor(x0, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0t = torch.tensor(v0, dtype=torch.float64, device="cuda", requires_grad=True)
+    x, v = coupled_run(g, n, fe, x0t, v0t, shape=shape, cycles=cycles, checkpoint=checkpoint,
+                       populations=pops, **kw)
+    return (g, n, fe, x0t, v0t), x, v
+
+
+def loss_of(x, v, x0, a):
+    d = x - x0
+    return d[0].mean() + (a * v).sum() + (d * d).sum(0).mean()
+
+
+@pytest.mark.parametrize("variant,kT", [(1, 1e-3), (2, 1e-3), (2, 0.0)])
+def test_adjoint_matches_oracle_autograd(lb, orc, variant, kT):
+    from oracle.torch_oracle import TorchOracle
+    c, w, e, b = orc.tables()
+    shape, N, cycles = (8, 6, 5), 7, 7
+    S = int(np.prod(shape))
+    rng = np.random.default_rng(21 + variant)
+    dev = 0.02 * w[:, None] * rng.standard_normal((19, S))
+    x0 = rng.random((3, N)) * np.asarray(shape, float)[:, None]
+    v0 = 0.02 * rng.standard_normal((3, N))
+    a = rng.standard_normal((3, N))
+    gamma, nu, fext = 1.7, 0.23, [2e-3, -1e-3, 4e-4]
+    kw = dict(n_sub=3, variant=variant, kT=kT, seed=6, particle_mass=1.2, precision=64)
+    leaves, x, v = run_gpu(shape, x0, v0, gamma, nu, fext, cycles, 3,
+                           pops=torch.tensor(dev, device="cuda"), **kw)
+    x0c = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    loss_of(x, v, x0c, torch.tensor(a, device="cuda")).backward()
+    gg = [t.grad.detach().cpu().numpy() for t in leaves]
+
+    td = torch.float64
+    T = TorchOracle(shape, 3, variant, kT, seed=6, particle_mass=1.2)
+    rl = [torch.tensor(gamma, dtype=td, requires_grad=True), torch.tensor(nu, dtype=td, requires_grad=True),
+          torch.tensor(fext, dtype=td, requires_grad=True), torch.tensor(x0, dtype=td, requires_grad=True),
+          torch.tensor(v0, dtype=td, requires_grad=True)]
+    xr, vr, _ = T.run(torch.tensor(w[:, None] + dev, dtype=td), rl[3], rl[4], rl[0], rl[1], rl[2], cycles)
+    assert np.abs(xr.detach().numpy() - x.detach().cpu().numpy()).max() < 1e-12
+    loss_of(xr, vr, torch.tensor(x0, dtype=td), torch.tensor(a)).backward()
+    for k, (gpu, ref) in enumerate(zip(gg, [t.grad.numpy() for t in rl])):
+        err = np.abs(gpu - ref).max() / max(np.abs(ref).max(), 1e-12)
+        assert err < 1e-10, (k, err, gpu, ref)
+
+
+def c5_setup(precision):
+    cfg = dict(wl.CONFIGS["c5"])
+    shape = cfg["shape"]
+    N = cfg["n_particles"]
+    rng = np.random.default_rng(cfg["seed"])
+    x0 = rng.random((3, N)) * np.asarray(shape, float)[:, None]
+    v0 = 1e-2 * rng.standard_normal((3, N))  # v ~ N(0, 1e-4)
+    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], seed=cfg["seed"],
+              particle_mass=cfg["particle_mass"], precision=precision)
+    return shape, x0, v0, cfg, kw
+
+
+def drift(x, x0):
+    return (x - x0)[0].mean()
+
+
+def c5_directions(lb, kT):
+    """Adjoint drift gradients on the 64^3 case and a loss function for
+    central differences along the same directions (FP64, same noise)."""
+    from paper_1610_02733_amd.adjoint import coupled_run
+    shape, x0, v0, cfg, kw = c5_setup(64)
+    kw["kT"] = kT
+    gamma, nu, fext = cfg["friction"], cfg["nu"], list(cfg["f_ext"])
+    cycles = cfg["lb_steps"]
+    leaves, x, v = run_gpu(shape, x0, v0, gamma, nu, fext, cycles, 10, **kw)
+    x0c = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    drift(x, x0c).backward()
+    g_gamma, g_nu = leaves[0].grad.item(), leaves[1].grad.item()
+    g_f, g_v0 = leaves[2].grad.cpu().numpy(), leaves[4].grad.cpu().numpy()
+
+    def L(dgamma=0.0, dnu=0.0, df=(0.0, 0.0, 0.0), dv0=0.0):
+        with torch.no_grad():
+            xx, _ = coupled_run(scalar(gamma + dgamma), scalar(nu + dnu),
+                                torch.tensor(np.add(fext, df), dtype=torch.float64, device="cuda"),
+                                x0c, torch.tensor(v0 + dv0, dtype=torch.float64, device="cuda"),
+                                shape=shape, cycles=cycles, checkpoint=10, **kw)
+            return drift(xx, x0c).item()
+
+    dirs = [("gamma", g_gamma, lambda h: L(dgamma=h)), ("nu", g_nu, lambda h: L(dnu=h))]
+    for d in range(3):
+        e = np.eye(3)[d]
+        dirs.append((f"f{d}", g_f[d], lambda h, e=e: L(df=h * e)))
+    rng = np.random.default_rng(55)
+    for q in range(10):  # 10 random components of v0 and one random direction
+        d, p = int(rng.integers(0, 3)), int(rng.integers(0, x0.shape[1]))
+        e = np.zeros_like(v0)
+        e[d, p] = 1.0
+        dirs.append((f"v0[{d},{p}]", g_v0[d, p], lambda h, e=e: L(dv0=h * e)))
+    u = rng.standard_normal(v0.shape)
+    u /= np.linalg.norm(u)
+    dirs.append(("v0.u", float((g_v0 * u).sum()), lambda h, u=u: L(dv0=h * u)))
+    return dirs
+
+
+def central(Lh, h):
+    return (Lh(h) - Lh(-h)) / (2 * h)
+
+
+@pytest.mark.parametrize("kT", [0.0, 1e-4])
+def test_c5_adjoint_matches_central_differences(lb, kT):
+    """64^3, 1000 particles under f = 1e-3 x, n = 5, 50 LB steps, checkpoints
+    every 10, FP64, along gamma, nu, f (3 components), 10 random components
+    of v0 and one random direction.
+
+    The drift is only piecewise smooth in every parameter: the trilinear
+    weights change slope where a particle crosses a lattice plane, and a
+    perturbed run whose trajectories cross such a kink differs from the
+    linearisation at first order in h.  Central differences are therefore
+    taken on a ladder of steps starting at h = 1e-4; a step counts once
+    dividing it by ten changes the estimate by less than 1e-6 of the
+    gradient's scale (no kink inside the stencil: crossing one shifts the
+    estimate far more).
+    The error bound is 1e-6 relative per gradient: for gamma and nu, for the
+    3-vector f and for the sampled v0 gradient, the largest deviation over
+    the group's components against the group's largest component.  Without
+    noise the along-force directions (gamma, nu, f_x) resolve at h = 1e-4
+    itself."""
+    dirs = c5_directions(lb, kT)
+    ladder = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9]
+    groups = {}
+    gscale = {}  # scale of each gradient, from the adjoint
+    for name, ad, _ in dirs:
+        group = name[0] if name[0] in "fv" else name
+        gscale[group] = max(gscale.get(group, 0.0), abs(ad))
+    for name, ad, Lh in dirs:
+        group = name[0] if name[0] in "fv" else name
+        prev = central(Lh, ladder[0])
+        used = None
+        for h in ladder[1:]:
+            cur = central(Lh, h)
+            if abs(cur - prev) <= 1e-6 * max(abs(cur), gscale[group]):
+                used = (h * 10, prev)
+                break
+            prev = cur
+        if used is None:  # a tiny component: the last, smallest-step estimate
+            used = (ladder[-1], prev)
+        h, f = used
+        print(f"kT={kT:g} {name}: adjoint {ad:.10e} fd {f:.10e} (h = {h:g})")
+        groups.setdefault(group, []).append((name, ad, f, h))
+        if kT == 0.0 and name in ("gamma", "nu", "f0"):
+            assert h == 1e-4, (name, h)
+    # relative error of each gradient (scalar, 3-vector f, sampled v0)
+    for group, rows in groups.items():
+        scale = max(abs(r[2]) for r in rows)
+        err = max(abs(r[1] - r[2]) for r in rows)
+        print(f"kT={kT:g} group {group}: max |adjoint - fd| / max |fd| = {err / scale:.2e}")
+        assert err <= 1e-6 * scale, (group, rows)
+
+
+def test_c5_fp32_adjoint_error_vs_fp64(lb):
+    """FP32 populations: the gradients against the FP64 run (error stated)."""
+    res = {}
+    for prec in (64, 32):
+        shape, x0, v0, cfg, kw = c5_setup(prec)
+        leaves, x, v = run_gpu(shape, x0, v0, cfg["friction"], cfg["nu"], list(cfg["f_ext"]),
+                               cfg["lb_steps"], 10, **kw)
+        drift(x, torch.tensor(x0, dtype=torch.float64, device="cuda")).backward()
+        res[prec] = [leaves[0].grad.item(), leaves[1].grad.item(),
+                     *leaves[2].grad.cpu().numpy(), *leaves[4].grad.cpu().numpy().ravel()]
+    a, b = np.asarray(res[32]), np.asarray(res[64])
+    rel = np.abs(a[:5] - b[:5]) / np.abs(b[:5]).max()
+    print("fp32 adjoint rel err (gamma, nu, f):", rel)
+    assert rel.max() < 1e-3
+    assert np.abs(a[5:] - b[5:]).max() < 1e-3 * np.abs(b[5:]).max()
+
+
+def test_save_load_state_resumes_exactly(lb):
+    """Resuming from a saved state reproduces the trajectory (counter-based
+    noise); FP64 transfer sums are atomic, so equal up to their rounding."""
+    shape = (12, 10, 8)
+    x, v = wl.free_particles(shape, 30, 1e-3, 1.0, 8)
+    kw = dict(precision=64, n_sub=4, variant=2, kT=1e-3, seed=9, n_particles=30, friction=1.5)
+    a = lb.Lattice(shape, **kw)
+    a.bind_particles(x, v)
+    a.run_cycles(3)
+    st = a.save_state()
+    a.run_cycles(4)
+    ref = (a.populations().cpu(), a.x.cpu().clone(), a.v.cpu().clone(), a.counters())
+
+    def same(sim):
+        assert (sim.populations().cpu() - ref[0]).abs().max().item() < 1e-15
+        assert (sim.x.cpu() - ref[1]).abs().max().item() < 1e-13
+        assert (sim.v.cpu() - ref[2]).abs().max().item() < 1e-15
+        assert sim.counters() == ref[3]
+
+    a.load_state(st)
+    assert a.counters() == dict(t_lb=3, t_md=12, subs=0)
+    a.cycle(4)
+    same(a)
+    # a second context of the same system resumes from the same state
+    b = lb.Lattice(shape, **kw)
+    b.bind_particles(x, v)
+    b.load_state(st)
+    b.run_cycles(4)
+    same(b)
+    a.md_couple_substep()
+    with pytest.raises(lb.LbmdError):
+        a.save_state()  # mid-interval
+
+
+def test_adjoint_call_order_and_support(lb):
+    shape = (8, 8, 8)
+    x, v = wl.free_particles(shape, 5, 0.0, 1.0, 2)
+    s = lb.Lattice(shape, precision=64, n_sub=2, n_particles=5, friction=1.0, force_model=1)
+    s.bind_particles(x, v)
+    with pytest.raises(lb.LbmdError):
+        s.lb_step_adjoint()  # nothing attached
+    st = s.save_state()
+    s.adjoint_attach(2)
+    s.adjoint_seed()
+    with pytest.raises(lb.LbmdError):
+        s.md_couple_substep_adjoint()  # nothing recorded
+    with pytest.raises(lb.LbmdError):
+        s.adjoint_record(st, 3)  # longer than the segment size
+    s.adjoint_record(st, 2)
+    assert s.counters() == dict(t_lb=2, t_md=4, subs=0)
+    with pytest.raises(lb.LbmdError):
+        s.md_couple_substep_adjoint()  # the LB step comes first
+    s.lb_step_adjoint()
+    with pytest.raises(lb.LbmdError):
+        s.lb_step_adjoint()
+    s.md_couple_substep_adjoint()
+    s.md_couple_substep_adjoint()
+    s.adjoint_sweep(1)
+    with pytest.raises(lb.LbmdError):
+        s.lb_step_adjoint()  # segment exhausted
+    xb, vb, g = s.adjoint_result()
+    assert np.isfinite(g["gamma"]) and torch.isfinite(vb).all()
+    # unsupported: batches, position-dependent forces
+    assert lb.lib().lbmd_adjoint_workspace_bytes(
+        lb.Lattice(shape, precision=64, n_particles=4, force_model=2, chain_len=2,
+                   wca_sigma=1.0, particle_mass=1.0)._h, 2) == 0
