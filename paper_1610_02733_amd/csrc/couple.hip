@@ -50,6 +50,12 @@ __device__ __forceinline__ int cache_stamp(const Clock* clk) {
   return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
 }
 
+// Mark a site as a receiver of momentum transfer in this LB interval.
+template <typename T>
+__device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
+  atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
+}
+
 // ---------------------------------------------------------------------------
 // Corner-cache refill, once per LB interval (before its first MD step):
 // (j, 1/rho) of the post-stream state at the 8 corners of every particle's
@@ -122,195 +128,187 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
       a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
       a.cc_stamp[p] = stamp;
     }
-    const int gs = m.site_off + site;
-    if (c == 0) atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
+    if (c == 0) claim_site(a, m.site_off + site);
   }
 }
 
 // ---------------------------------------------------------------------------
-// One MD step (Sec. 3, Eq. 4-8), one lane per particle.
+// One MD step (Sec. 3, Eq. 4-8), eight lanes per particle, one per corner of
+// its cube.
 //
-// Fluid velocity at the particle from the cached corner moments (a particle
-// that left its cube since the refill gathers the new corners itself),
-// friction + noise, velocity Verlet.  Variant 1 then transfers the momentum
-// right away: the block stages (replica, cube, dP) of its 256 particles in
-// LDS and re-issues the 24 adds of each particle from 24 consecutive lanes,
-// so one atomic instruction covers ~3 particles and a handful of cache lines
-// rather than 64 unrelated lines.  Variant 2 stores (cube, dP) for the
-// spreading kernel, because every particle must first read the velocities as
-// of the end of the previous MD step.
-// ---------------------------------------------------------------------------
+// Each lane fetches its corner's cached moments (a particle that left its
+// cube since the refill gathers the new corners itself, one corner per lane)
+// and, in variant 2, the corner's pending transfer; the interpolated fluid
+// velocity (Eq. 5) is the sum over the eight lanes (butterfly shuffles, the
+// same order on every lane).  Friction + noise (Eq. 4, 6) and velocity
+// Verlet are evaluated on all eight lanes alike; lane 0 stores the particle.
+// Variant 1 then transfers the momentum right away (Eq. 7-8): the 24
+// (corner, component) adds of a particle are spread over its 8 lanes in
+// three rounds, so the lanes of one atomic instruction share a few sites
+// rather than touching 64 unrelated cache lines.  Variant 2 stores (cube,
+// dP) for the spreading kernel instead, because every particle must first
+// read the velocities as of the end of the previous MD step.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
 // recorded for the reverse sweep (position NaN: particle skipped).
+// ---------------------------------------------------------------------------
+constexpr int kCornerLanes = 8;
+
+__device__ __forceinline__ double oct_sum(double v) {  // over the 8 lanes of a particle
+  v += __shfl_xor(v, 1, kCornerLanes);
+  v += __shfl_xor(v, 2, kCornerLanes);
+  v += __shfl_xor(v, 4, kCornerLanes);
+  return v;
+}
+
+__device__ __forceinline__ double pick3(const double v[3], int c) {
+  return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
+}
+
+// Transfer -w_k dP of one particle (Eq. 7-8) from its 8 lanes: pair
+// index 8 r + lane = 3 corner + component, rounds r = 0, 1, 2.
+template <typename T>
+__device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, const RepMD& m,
+                                                    const Cube& q, int lane, const double dp[3]) {
+#pragma unroll
+  for (int rnd = 0; rnd < 3; ++rnd) {
+    const int pair = rnd * kCornerLanes + lane;
+    const int kc = pair / 3, c = pair - 3 * kc;
+    int cx, cy, cz, site;
+    double w;
+    corner_of(q, m.g, kc, cx, cy, cz, site, w);
+    atomicAdd(((T*)(J + m.site_off + site)) + c, (T)(-w * pick3(dp, c)));
+  }
+}
+
 template <typename T, bool Rec>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
-  __shared__ int sh_rep[kBlock];
-  __shared__ int sh_base[3][kBlock];
-  __shared__ double sh_s[3][kBlock];
-  __shared__ double sh_dp[3][kBlock];
   const T* __restrict__ pop = a.pop[a.clock->cur];
   const int stamp = cache_stamp(a.clock);
   const unsigned long long t_md = (unsigned long long)(a.clock->t_md + a.substep);
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
-  const int64_t rounds = (N + kBlock - 1) / kBlock;
-  for (int64_t blk = blockIdx.x; blk < rounds; blk += gridDim.x) {
-    const int64_t p = blk * kBlock + threadIdx.x;
-    bool live = p < N;
-    int rr = 0;
-    double X[3] = {0.0, 0.0, 0.0}, V[3] = {0.0, 0.0, 0.0};
-    if (live) {
-      rr = a.single ? 0 : a.part_rep[p];
+  const int64_t lanes = N * kCornerLanes;
+  // lanes come in whole particles (8 | kBlock): the 8 lanes of a particle
+  // are always active together, as the shuffles require
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / kCornerLanes;
+    const int k = (int)(t & (kCornerLanes - 1));
+    const int rr = a.single ? 0 : a.part_rep[p];
+    double X[3], V[3];
+    bool live = true;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        X[d] = a.x[d * N + p];
-        V[d] = a.v[d * N + p];
-        live = live && isfinite(X[d]) && isfinite(V[d]);
-      }
-      if (!live) {
+    for (int d = 0; d < 3; ++d) {
+      X[d] = a.x[d * N + p];
+      V[d] = a.v[d * N + p];
+      live = live && isfinite(X[d]) && isfinite(V[d]);
+    }
+    if (!live) {
+      if (k == 0) {
         a.flags[0] = 1;
         if (a.variant == 2) a.rec_cell[p] = -1;
         if (Rec) a.rec[p] = __builtin_nan("");
       }
+      continue;
     }
+    const RepMD& m = a.md[rr];
     Cube q;
-    double dp[3] = {0.0, 0.0, 0.0};
-    if (live) {
-      const RepMD& m = a.md[rr];
-      cube_of(X, m.g, q);
-      const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-      Vec4<T> cv[8];
-      if (a.cc_stamp[p] == stamp && a.cc_cell[p] == cell) {
+    cube_of(X, m.g, q);
+    const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+    int cx, cy, cz, site;
+    double w;
+    corner_of(q, m.g, k, cx, cy, cz, site, w);
+    Vec4<T> cv;
+    const bool hit = a.cc_stamp[p] == stamp && a.cc_cell[p] == cell;
+    if (hit) {
+      cv = *cache_entry(a, p, k);
+    } else {
+      // left the cube of the refill: this lane gathers its corner
+      int sidx[19];
+      pull_sources(m.g, cx, cy, cz, sidx);
+      T d[19];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) cv[k] = *cache_entry(a, p, k);
-      } else {
-        // left the cube of the refill: gather the new corners here
-#pragma unroll 1
-        for (int k = 0; k < 8; ++k) {
-          int cx, cy, cz, site;
-          double w;
-          corner_of(q, m.g, k, cx, cy, cz, site, w);
-          int sidx[19];
-          pull_sources(m.g, cx, cy, cz, sidx);
-          T d[19];
-#pragma unroll
-          for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
-          T drho, jx, jy, jz;
-          moments_deviation<T>(d, drho, jx, jy, jz);
-          cv[k] = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-          *cache_entry(a, p, k) = cv[k];
-          const int gs = m.site_off + site;
-          atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
-        }
+      for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
+      T drho, jx, jy, jz;
+      moments_deviation<T>(d, drho, jx, jy, jz);
+      cv = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
+      *cache_entry(a, p, k) = cv;
+      claim_site(a, m.site_off + site);
+      if (k == 0) {
         a.cc_cell[p] = cell;
         a.cc_stamp[p] = stamp;
       }
-      // fluid velocity at the particle (Eq. 5)
-      double u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        int cx, cy, cz, site;
-        double w;
-        corner_of(q, m.g, k, cx, cy, cz, site, w);
-        double jx = (double)cv[k].x, jy = (double)cv[k].y, jz = (double)cv[k].z;
-        if (a.variant == 2) {
-          const Vec4<T> jv = a.J[m.site_off + site];
-          jx += (double)jv.x;
-          jy += (double)jv.y;
-          jz += (double)jv.z;
-        }
-        const double wi = w * (double)cv[k].w;
-        u[0] += wi * jx;
-        u[1] += wi * jy;
-        u[2] += wi * jz;
-        if (Rec) {
-          a.rec[(6 + 3 * k) * N + p] = jx;
-          a.rec[(7 + 3 * k) * N + p] = jy;
-          a.rec[(8 + 3 * k) * N + p] = jz;
-          a.rec[(30 + k) * N + p] = (double)cv[k].w;
-        }
-      }
-      if (Rec) {
+    }
+    // fluid velocity at the particle (Eq. 5)
+    double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
+    if (a.variant == 2) {
+      const Vec4<T> jv = a.J[m.site_off + site];
+      jx += (double)jv.x;
+      jy += (double)jv.y;
+      jz += (double)jv.z;
+    }
+    if (Rec) {
+      a.rec[(6 + 3 * k) * N + p] = jx;
+      a.rec[(7 + 3 * k) * N + p] = jy;
+      a.rec[(8 + 3 * k) * N + p] = jz;
+      a.rec[(30 + k) * N + p] = (double)cv.w;
+      if (k == 0) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           a.rec[d * N + p] = X[d];
           a.rec[(3 + d) * N + p] = V[d];
         }
       }
-      // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
-      double xi[3] = {0.0, 0.0, 0.0};
-      if (m.noise) {
-        const uint32_t lp = (uint32_t)(p - m.part_off);
-        const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
-        const uint32_t ws[3] = {o.w0, o.w1, o.w2};
+    }
+    const double wi = w * (double)cv.w;
+    const double u[3] = {oct_sum(wi * jx), oct_sum(wi * jy), oct_sum(wi * jz)};
+    // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (m.noise) {
+      const uint32_t lp = (uint32_t)(p - m.part_off);
+      const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
+      const uint32_t ws[3] = {o.w0, o.w1, o.w2};
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
-      }
-      // velocity Verlet with the coupling force held over the step; with
-      // position-dependent conservative forces the second half-kick waits
-      // for the forces at the new positions (k_kick)
+      for (int d = 0; d < 3; ++d)
+        xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
+    }
+    // velocity Verlet with the coupling force held over the step; with
+    // position-dependent conservative forces the second half-kick waits
+    // for the forces at the new positions (k_kick)
+    double dp[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
-        dp[d] = m.tau * Fc;
+    for (int d = 0; d < 3; ++d) {
+      const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
+      dp[d] = m.tau * Fc;
+      if (k == 0) {
         const double fc = a.fcons[d * N + p];
         int32_t im = a.img[d * N + p];
-        V[d] += m.h * (fc + Fc);
-        X[d] += m.tau * V[d];
-        wrap_coord(X[d], im, m.L[d]);
+        double v1 = V[d] + m.h * (fc + Fc);
+        double x1 = X[d] + m.tau * v1;
+        wrap_coord(x1, im, m.L[d]);
         if (m.split_kick)
           a.fc_held[d * N + p] = Fc;
         else
-          V[d] += m.h * (fc + Fc);
-        a.x[d * N + p] = X[d];
-        a.v[d * N + p] = V[d];
+          v1 += m.h * (fc + Fc);
+        a.x[d * N + p] = x1;
+        a.v[d * N + p] = v1;
         a.img[d * N + p] = im;
-      }
-      if (a.variant == 2) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
+        if (a.variant == 2) {
           a.rec_cell[d * N + p] = q.base[d];
           a.rec_frac[d * N + p] = q.s[d];
           a.rec_dp[d * N + p] = dp[d];
         }
       }
     }
-    if (a.variant != 1) continue;  // uniform over the grid
-
-    // momentum transfer to the fluid (Eq. 7-8), 24 consecutive lanes per particle
-    sh_rep[threadIdx.x] = rr;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      sh_base[d][threadIdx.x] = live ? q.base[d] : -1;
-      sh_s[d][threadIdx.x] = live ? q.s[d] : 0.0;
-      sh_dp[d][threadIdx.x] = dp[d];
-    }
-    __syncthreads();
-    for (int g = threadIdx.x; g < 24 * kBlock; g += kBlock) {
-      const int pp = g / 24, r = g - 24 * pp;
-      if (sh_base[0][pp] < 0) continue;
-      const int k = r / 3, c = r - 3 * k;
-      const RepMD& m = a.md[a.single ? 0 : sh_rep[pp]];
-      Cube qq;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        qq.base[d] = sh_base[d][pp];
-        qq.s[d] = sh_s[d][pp];
-      }
-      int cx, cy, cz, site;
-      double w;
-      corner_of(qq, m.g, k, cx, cy, cz, site, w);
-      atomicAdd(((T*)(a.J + m.site_off + site)) + c, (T)(-w * sh_dp[c][pp]));
-    }
-    __syncthreads();
+    if (a.variant == 1) transfer_from_lanes<T>(a.J, m, q, k, dp);
   }
 }
 
-// Variant-2 momentum transfer of the MD step just taken, 24 lanes per
-// particle (one per corner and component).
+// Variant-2 momentum transfer of the MD step just taken, 24 consecutive lanes
+// per particle (one per corner and component): the lanes of one atomic
+// instruction then share the few cache lines of ~3 particles' cubes.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
   const int64_t N = a.N;
@@ -382,7 +380,7 @@ static hipError_t couple_t(Context* c, int substep) {
                        dim3(kBlock), 0, c->stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const dim3 cgrid(grid_for((N + kBlock - 1) / kBlock, c->tune.part_blocks));
+  const dim3 cgrid(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
   if (a.rec)
     hipLaunchKernelGGL((k_couple<T, true>), cgrid, dim3(kBlock), 0, c->stream, a);
   else
