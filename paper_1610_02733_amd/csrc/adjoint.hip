@@ -140,43 +140,37 @@ struct AdjMDArgs {
   long long t_md;                  // MD step being reversed
 };
 
-// Trilinear weights of the 8 corners and their derivatives with respect to
-// the fractional position s (d w_k / d s_e).
-__device__ __forceinline__ void weights_and_slopes(const double s[3], double w[8],
-                                                   double dw[8][3]) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const double a0 = (k & 1) ? s[0] : 1.0 - s[0], e0 = (k & 1) ? 1.0 : -1.0;
-    const double a1 = (k & 2) ? s[1] : 1.0 - s[1], e1 = (k & 2) ? 1.0 : -1.0;
-    const double a2 = (k & 4) ? s[2] : 1.0 - s[2], e2 = (k & 4) ? 1.0 : -1.0;
-    w[k] = a0 * a1 * a2;
-    dw[k][0] = e0 * a1 * a2;
-    dw[k][1] = a0 * e1 * a2;
-    dw[k][2] = a0 * a1 * e2;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Adjoint of one MD step, one lane per particle (Eq. 4-8 with velocity
-// Verlet).  Forward, with s = X - floor(X) and w_k(s) the corner weights:
+// Adjoint of one MD step (Eq. 4-8 with velocity Verlet), eight lanes per
+// particle, one per corner k of its cube.  Forward, with s = X - floor(X)
+// and w_k(s) the corner weights:
 //   u   = sum_k w_k U_k / rho_k          (U_k = j_k [+ J_k in variant 2])
 //   Fc  = -gamma (V - u) + A xi,         A = sqrt(2 gamma kT / tau)
 //   J_k += -w_k tau Fc                   (transfer, Eq. 7-8)
 //   V1  = V + h (f + Fc);  X' = X + tau V1;  V' = V1 + h (f + Fc)
 // Reverse: from X'-bar, V'-bar and J-bar at the corners, the adjoints of X,
-// V, Fc, u, gamma and f; u-bar is left for the scatter kernel.  The weights
-// are piecewise linear in X, so their derivative enters through both the
-// interpolation and the transfer.
+// V, Fc, u, gamma and f.  Sums over corners are butterfly sums over the
+// lanes; the weights are piecewise linear in X, so their slopes enter
+// through both the interpolation and the transfer.  The reads of the
+// interpolation then have adjoints
+//   j-bar_k += w_k / rho_k u-bar,   rho-bar_k -= w_k / rho_k^2 (U_k . u-bar),
+// which Fused adds right here (variant 1: J-bar is not read again in this
+// step); in variant 2 the read includes J, so J-bar gains the same j-bar,
+// and the adds wait for k_scatter_adjoint until every particle of the step
+// has read J-bar.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool Fused>
 __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
-                                                           const Vec4<T>* __restrict__ jbar) {
+                                                           const Vec4<T>* __restrict__ jbar,
+                                                           Vec4<T>* __restrict__ abar) {
   const RepMD& m = a.md[0];
   const int64_t N = a.N;
   const unsigned long long t_md = (unsigned long long)a.t_md;
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
-  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < N;
-       p += (int64_t)gridDim.x * kBlock) {
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kCornerLanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / kCornerLanes;
+    const int k = (int)(t & (kCornerLanes - 1));
     const double* r = a.rec;
     double X[3], V[3];
 #pragma unroll
@@ -184,21 +178,24 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
       X[d] = r[d * N + p];
       V[d] = r[(3 + d) * N + p];
     }
-    if (!isfinite(X[0])) continue;  // skipped by the forward step
+    if (!isfinite(X[0])) continue;  // skipped by the forward step (all 8 lanes)
     Cube q;
     cube_of(X, m.g, q);
-    double w[8], dw[8][3];
-    weights_and_slopes(q.s, w, dw);
-    double U[8][3], ir[8], u[3] = {0.0, 0.0, 0.0};
+    int cx, cy, cz, site;
+    double w;
+    corner_of(q, m.g, k, cx, cy, cz, site, w);
+    // d w_k / d s_e
+    const double a0 = (k & 1) ? q.s[0] : 1.0 - q.s[0], e0 = (k & 1) ? 1.0 : -1.0;
+    const double a1 = (k & 2) ? q.s[1] : 1.0 - q.s[1], e1 = (k & 2) ? 1.0 : -1.0;
+    const double a2 = (k & 4) ? q.s[2] : 1.0 - q.s[2], e2 = (k & 4) ? 1.0 : -1.0;
+    const double dw[3] = {e0 * a1 * a2, a0 * e1 * a2, a0 * a1 * e2};
+    const double ir = r[(30 + k) * N + p];
+    const double U[3] = {r[(6 + 3 * k) * N + p], r[(7 + 3 * k) * N + p], r[(8 + 3 * k) * N + p]};
+    const Vec4<T> jb = jbar[site];
+    const double jbv[3] = {(double)jb.x, (double)jb.y, (double)jb.z};
+    double u[3];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      ir[k] = r[(30 + k) * N + p];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        U[k][d] = r[(6 + 3 * k + d) * N + p];
-        u[d] += w[k] * ir[k] * U[k][d];
-      }
-    }
+    for (int d = 0; d < 3; ++d) u[d] = oct_sum(w * ir * U[d]);
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
       const Words4 o = philox10(Words4{(uint32_t)p, step_lo, m.tag, step_hi}, m.key0, m.key1);
@@ -207,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
       for (int d = 0; d < 3; ++d)
         xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
     }
-    double Fc[3], xb[3], vb[3], Fcb[3];
+    double Fc[3], xb[3], vb[3], Fcb[3], fb[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       Fc[d] = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
@@ -215,24 +212,16 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
       vb[d] = a.vbar[d * N + p];
       const double v1b = vb[d] + m.tau * xb[d];
       Fcb[d] = m.h * (vb[d] + v1b);
-      a.pacc[(1 + d) * N + p] += Fcb[d];  // f enters exactly where Fc does
+      fb[d] = Fcb[d];  // f enters exactly where Fc does
       vb[d] = v1b;
     }
     // transfer J_k += -w_k tau Fc
-    double xs[3] = {0.0, 0.0, 0.0};
+    const double gk = jbv[0] * Fc[0] + jbv[1] * Fc[1] + jbv[2] * Fc[2];
+    double xs[3];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int cx, cy, cz, site;
-      double wk;
-      corner_of(q, m.g, k, cx, cy, cz, site, wk);
-      const Vec4<T> jb = jbar[site];
-      const double jbv[3] = {(double)jb.x, (double)jb.y, (double)jb.z};
-      const double gk = jbv[0] * Fc[0] + jbv[1] * Fc[1] + jbv[2] * Fc[2];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        Fcb[d] -= m.tau * w[k] * jbv[d];
-        xs[d] -= m.tau * gk * dw[k][d];
-      }
+    for (int d = 0; d < 3; ++d) {
+      Fcb[d] += oct_sum(-m.tau * w * jbv[d]);
+      xs[d] = -m.tau * gk * dw[d];
     }
     // friction and noise
     double ub[3], gbar = 0.0;
@@ -243,33 +232,37 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
       ub[d] = m.gamma * Fcb[d];
       gbar += Fcb[d] * (-(V[d] - u[d]) + half_amp_over_gamma * xi[d]);
     }
-    a.pacc[p] += gbar;
     // interpolation weights
+    const double uk = ir * (U[0] * ub[0] + U[1] * ub[1] + U[2] * ub[2]);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double uk = ir[k] * (U[k][0] * ub[0] + U[k][1] * ub[1] + U[k][2] * ub[2]);
+    for (int d = 0; d < 3; ++d) xs[d] = oct_sum(xs[d] + uk * dw[d]);
+    if (k == 0) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) xs[d] += uk * dw[k][d];
+      for (int d = 0; d < 3; ++d) {
+        a.xbar[d * N + p] = xb[d] + xs[d];
+        a.vbar[d * N + p] = vb[d];
+        a.ubar[d * N + p] = ub[d];
+        a.pacc[(1 + d) * N + p] += fb[d];
+      }
+      a.pacc[p] += gbar;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      a.xbar[d * N + p] = xb[d] + xs[d];
-      a.vbar[d * N + p] = vb[d];
-      a.ubar[d * N + p] = ub[d];
+    if (Fused) {
+      T* dst = (T*)(abar + site);
+      atomicAdd(dst + 0, (T)(w * ir * ub[0]));
+      atomicAdd(dst + 1, (T)(w * ir * ub[1]));
+      atomicAdd(dst + 2, (T)(w * ir * ub[2]));
+      atomicAdd(dst + 3, (T)(-w * ir * uk));
     }
   }
 }
 
-// Adjoint of the interpolation's reads, 32 lanes per particle (corner k =
-// lane / 4; lanes 0-2 of a corner carry j-bar components, lane 3 rho-bar):
-//   j-bar_k += w_k / rho_k u-bar,   rho-bar_k -= w_k / rho_k^2 (U_k . u-bar).
-// In variant 2 the read includes the transfer field J as of the start of the
-// step, so J-bar gains the same j-bar (after every particle of the step has
-// read J-bar in k_couple_adjoint).
+// Variant 2: the adds of k_couple_adjoint's reads, after every particle of
+// the step has read J-bar; 32 lanes per particle (corner k = lane / 4; lanes
+// 0-2 of a corner carry j-bar components, lane 3 rho-bar).  The read
+// included the transfer field, so J-bar gains the same j-bar.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter_adjoint(AdjMDArgs a, Vec4<T>* __restrict__ abar,
-                                                            Vec4<T>* __restrict__ jbar,
-                                                            int variant) {
+                                                            Vec4<T>* __restrict__ jbar) {
   const RepMD& m = a.md[0];
   const int64_t N = a.N;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * 32;
@@ -296,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_adjoint(AdjMDArgs a, Vec4<T>
     } else {
       const T val = (T)(w * ir * a.ubar[c * N + p]);
       atomicAdd(dst + c, val);
-      if (variant == 2) atomicAdd(((T*)(jbar + site)) + c, val);
+      atomicAdd(((T*)(jbar + site)) + c, val);
     }
   }
 }
@@ -354,12 +347,18 @@ static hipError_t couple_adjoint_t(Context* c) {
   Vec4<T>* jbar = (Vec4<T>*)(c->adj.ws + c->adj.lay.jbar);
   Vec4<T>* abar = (Vec4<T>*)(c->adj.ws + c->adj.lay.abar);
   const int64_t N = a.N;
-  hipLaunchKernelGGL(k_couple_adjoint<T>, dim3((unsigned)((N + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, c->stream, a, (const Vec4<T>*)jbar);
+  const dim3 grid((unsigned)((N * kCornerLanes + kBlock - 1) / kBlock));
+  if (c->p[0].variant == 1) {
+    hipLaunchKernelGGL((k_couple_adjoint<T, true>), grid, dim3(kBlock), 0, c->stream, a,
+                       (const Vec4<T>*)jbar, abar);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_couple_adjoint<T, false>), grid, dim3(kBlock), 0, c->stream, a,
+                     (const Vec4<T>*)jbar, abar);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter_adjoint<T>, dim3((unsigned)((N * 32 + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, c->stream, a, abar, jbar, c->p[0].variant);
+                     dim3(kBlock), 0, c->stream, a, abar, jbar);
   return hipGetLastError();
 }
 

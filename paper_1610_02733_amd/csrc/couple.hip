@@ -153,15 +153,6 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
 // corner velocities (j [+ J]) and inverse densities it interpolated are
 // recorded for the reverse sweep (position NaN: particle skipped).
 // ---------------------------------------------------------------------------
-constexpr int kCornerLanes = 8;
-
-__device__ __forceinline__ double oct_sum(double v) {  // over the 8 lanes of a particle
-  v += __shfl_xor(v, 1, kCornerLanes);
-  v += __shfl_xor(v, 2, kCornerLanes);
-  v += __shfl_xor(v, 4, kCornerLanes);
-  return v;
-}
-
 __device__ __forceinline__ double pick3(const double v[3], int c) {
   return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
 }

@@ -68,4 +68,15 @@ __device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, i
       ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
 }
 
+// Kernels that give a particle one lane per corner of its cube (8 | kBlock,
+// so the lanes of a particle are always active together).
+constexpr int kCornerLanes = 8;
+
+__device__ __forceinline__ double oct_sum(double v) {  // over the 8 lanes of a particle
+  v += __shfl_xor(v, 1, kCornerLanes);
+  v += __shfl_xor(v, 2, kCornerLanes);
+  v += __shfl_xor(v, 4, kCornerLanes);
+  return v;
+}
+
 }  // namespace lbmd_impl
