@@ -28,6 +28,7 @@ struct CoupleArgs {
   T* __restrict__ cc;
   int32_t* __restrict__ cc_cell;
   int32_t* __restrict__ cc_stamp;
+  unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
@@ -50,10 +51,13 @@ __device__ __forceinline__ int cache_stamp(const Clock* clk) {
   return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
 }
 
-// Mark a site as a receiver of momentum transfer in this LB interval.
+// Mark a site as a receiver of momentum transfer in this LB interval; a site
+// claimed again (by another particle, or by one that changed cubes) is
+// flagged as shared.
 template <typename T>
 __device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
-  atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
+  const unsigned long long bit = 1ull << (gs & 63);
+  if (atomicOr(a.mark + (gs >> 6), bit) & bit) atomicOr(a.shared_site + (gs >> 6), bit);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,29 +301,48 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   }
 }
 
-// Variant-2 momentum transfer of the MD step just taken, 24 consecutive lanes
-// per particle (one per corner and component): the lanes of one atomic
-// instruction then share the few cache lines of ~3 particles' cubes.
+// Variant-2 momentum transfer of the MD step just taken, eight lanes per
+// particle (one per corner).  Every site a particle transfers to was claimed
+// by it in this interval before this kernel runs (refill or cube change in
+// k_couple), so a site without the shared flag has exactly one writer here:
+// it is updated with a plain read-modify-write of its vector.  Shared sites
+// take atomic adds.  Either way the site receives the same rounded values.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
   const int64_t N = a.N;
-  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < 24 * N;
-       g += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = g / 24;
-    const int r = (int)(g - 24 * p);
-    const int k = r / 3, c = r - 3 * k;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kCornerLanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / kCornerLanes;
+    const int k = (int)(t & (kCornerLanes - 1));
     Cube q;
     q.base[0] = a.rec_cell[p];
     if (q.base[0] < 0) continue;
     const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
     q.base[1] = a.rec_cell[N + p];
     q.base[2] = a.rec_cell[2 * N + p];
+    double dp[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) q.s[d] = a.rec_frac[d * N + p];
+    for (int d = 0; d < 3; ++d) {
+      q.s[d] = a.rec_frac[d * N + p];
+      dp[d] = a.rec_dp[d * N + p];
+    }
     int cx, cy, cz, site;
     double w;
     corner_of(q, m.g, k, cx, cy, cz, site, w);
-    atomicAdd(((T*)(a.J + m.site_off + site)) + c, (T)(-w * a.rec_dp[c * N + p]));
+    const int gs = m.site_off + site;
+    const T ax = (T)(-w * dp[0]), ay = (T)(-w * dp[1]), az = (T)(-w * dp[2]);
+    if ((a.shared_site[gs >> 6] >> (gs & 63)) & 1ull) {
+      T* dst = (T*)(a.J + gs);
+      atomicAdd(dst + 0, ax);
+      atomicAdd(dst + 1, ay);
+      atomicAdd(dst + 2, az);
+    } else {
+      Vec4<T> v = a.J[gs];
+      v.x += ax;
+      v.y += ay;
+      v.z += az;
+      a.J[gs] = v;
+    }
   }
 }
 
@@ -342,6 +365,7 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.cc = (T*)at(c, L.cc);
   a.cc_cell = (int32_t*)at(c, L.cc_cell);
   a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
+  a.shared_site = (unsigned long long*)at(c, L.shared_site);
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
@@ -377,7 +401,7 @@ static hipError_t couple_t(Context* c, int substep) {
   else
     hipLaunchKernelGGL((k_couple<T, false>), cgrid, dim3(kBlock), 0, c->stream, a);
   if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
-  hipLaunchKernelGGL(k_spread<T>, dim3(grid_for((N * 24 + kBlock - 1) / kBlock, c->tune.part_blocks)),
+  hipLaunchKernelGGL(k_spread<T>, dim3(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
                      dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }

@@ -43,6 +43,7 @@ struct StreamArgs {
   T* pop[2];
   Vec4<T>* __restrict__ J;
   unsigned long long* __restrict__ mark;
+  unsigned long long* __restrict__ shared_site;
   const RepLB<T>* __restrict__ rep;
   const int32_t* __restrict__ item_off;
   const Clock* __restrict__ clock;
@@ -103,7 +104,10 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
     // caches (non-temporal hint)
 #pragma unroll
     for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], dst + (size_t)i * a.P + gsite);
-    if ((gsite & 63) == 0 && word) a.mark[gsite >> 6] = 0ull;
+    if ((gsite & 63) == 0 && word) {
+      a.mark[gsite >> 6] = 0ull;
+      a.shared_site[gsite >> 6] = 0ull;  // shared bits are a subset of the mark bits
+    }
   }
 }
 
@@ -116,6 +120,7 @@ static StreamArgs<T> stream_args(Context* c) {
   a.jrec = (Vec4<T>*)c->rec_J;
   a.mrec = c->rec_mark;
   a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
+  a.shared_site = (unsigned long long*)at(c, c->plan.lay.shared_site);
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
   a.clock = (const Clock*)at(c, c->plan.lay.clock);

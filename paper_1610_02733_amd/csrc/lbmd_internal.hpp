@@ -77,6 +77,7 @@ struct Layout {
   size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
   size_t cc_cell;    // [Ntot] int32: cube (lower corner, replica-local) cached
   size_t cc_stamp;   // [Ntot] int32: LB step + 1 at which the cache was filled
+  size_t shared_site; // [Stot/64] uint64: site claimed more than once in this LB interval
   size_t bin_count;  // [Ctot] int32: particles per force cell
   size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
   size_t bin_tiles;  // [ceil(Ctot / 1024) + 1] int32: scan tile totals
