@@ -11,6 +11,7 @@ not reproducible, so these stand in for it):
 
 * ``c1``: 16^3, FP64, 32 free particles, n = 5, 100 LB steps (parity case).
 * ``c2``: 128^3, FP32, 200 chains x 50 beads, harmonic bonds + WCA, n = 10.
+* ``c2p``: the same shapes at stable dimensionless parameters (companion of c2).
 * ``c3``: 256^3, FP32, 1e5 free particles, n = 10 (bandwidth-roofline case).
 * ``c4``: 512 replicas, edges in {24,32,40,48}, 20..400 particles each.
 * ``c5``: 64^3, 1000 particles under a constant force, n = 5 (adjoint case).
@@ -29,6 +30,13 @@ CONFIGS = {
                kT=1.0, n_particles=10_000, chain_len=50, particle_mass=1.0, friction=20.0,
                n_sub=10, lb_steps=1000, seed=2, precision=32, variant=2, force_model=2,
                k_bond=30.0, r0_bond=1.0, wca_eps=1.0, wca_sigma=1.0),
+    # the same shapes as c2 at stable dimensionless parameters: energies in
+    # units of kT (eps = kT, k = 30 kT / sigma^2), gamma tau_MD / m = 0.2,
+    # chains grown without overlaps closer than 0.9 sigma
+    "c2p": dict(shape=(128, 128, 128), rho0=1.0, nu=NU_1_6, nu_bulk=-1.0, gamma_ghost=0.0,
+                kT=1e-4, n_particles=10_000, chain_len=50, particle_mass=1.0, friction=2.0,
+                n_sub=10, lb_steps=1000, seed=2, precision=32, variant=2, force_model=2,
+                k_bond=3e-3, r0_bond=1.0, wca_eps=1e-4, wca_sigma=1.0, min_dist=0.9),
     "c3": dict(shape=(256, 256, 256), rho0=1.0, nu=NU_1_6, nu_bulk=-1.0, gamma_ghost=0.0,
                kT=1e-4, n_particles=100_000, particle_mass=1.0, friction=10.0, n_sub=10,
                lb_steps=200, seed=3, precision=32),
