@@ -201,11 +201,9 @@ RepMD rep_md(const Context* c, int r) {
   m.r0_bond = p.r0_bond;
   m.wca_eps = p.wca_eps;
   m.wca_sigma = p.wca_sigma;
-  const double rc = pow(2.0, 1.0 / 6.0) * p.wca_sigma;
   const int Ls[3] = {p.nx, p.ny, p.nz};
   for (int d = 0; d < 3; ++d) {
-    int n = (int)floor((double)Ls[d] / rc);
-    n = n < 1 ? 1 : n;
+    const int n = cells_per_axis(&p, d);
     m.nb[d] = n;
     m.inv_edge[d] = (double)n / (double)Ls[d];
   }

@@ -302,11 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
 }
 
 // Variant-2 momentum transfer of the MD step just taken, eight lanes per
-// particle (one per corner).  Every site a particle transfers to was claimed
-// by it in this interval before this kernel runs (refill or cube change in
-// k_couple), so a site without the shared flag has exactly one writer here:
-// it is updated with a plain read-modify-write of its vector.  Shared sites
-// take atomic adds.  Either way the site receives the same rounded values.
+// particle (one per corner; see spread_corner).  With position-dependent
+// forces the same transfer runs inside the force kernel instead.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
   const int64_t N = a.N;
@@ -326,23 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
       q.s[d] = a.rec_frac[d * N + p];
       dp[d] = a.rec_dp[d * N + p];
     }
-    int cx, cy, cz, site;
-    double w;
-    corner_of(q, m.g, k, cx, cy, cz, site, w);
-    const int gs = m.site_off + site;
-    const T ax = (T)(-w * dp[0]), ay = (T)(-w * dp[1]), az = (T)(-w * dp[2]);
-    if ((a.shared_site[gs >> 6] >> (gs & 63)) & 1ull) {
-      T* dst = (T*)(a.J + gs);
-      atomicAdd(dst + 0, ax);
-      atomicAdd(dst + 1, ay);
-      atomicAdd(dst + 2, az);
-    } else {
-      Vec4<T> v = a.J[gs];
-      v.x += ax;
-      v.y += ay;
-      v.z += az;
-      a.J[gs] = v;
-    }
+    spread_corner<T>(a.J, a.shared_site, m, q, k, dp);
   }
 }
 
@@ -400,7 +381,9 @@ static hipError_t couple_t(Context* c, int substep) {
     hipLaunchKernelGGL((k_couple<T, true>), cgrid, dim3(kBlock), 0, c->stream, a);
   else
     hipLaunchKernelGGL((k_couple<T, false>), cgrid, dim3(kBlock), 0, c->stream, a);
-  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
+  // variant 2: the transfer waits until every particle has read J; with
+  // position-dependent forces it runs inside the force kernel
+  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1 || c->plan.any_forces2) return e;
   hipLaunchKernelGGL(k_spread<T>, dim3(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
                      dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();

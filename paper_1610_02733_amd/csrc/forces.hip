@@ -3,7 +3,10 @@
 // beads of a chain and the purely repulsive WCA potential between all pairs,
 // found through a cell list.  Also the counting-sort binning of particles
 // into cells (histogram, three-level exclusive scan, scatter).
-#include "lbmd_internal.hpp"
+#include <algorithm>
+#include <cmath>
+
+#include "particle_geom.hpp"
 
 namespace lbmd_impl {
 
@@ -22,11 +25,6 @@ __device__ __forceinline__ int local_cell(const double X[3], const RepMD& m) {
     c[d] = q;
   }
   return c[0] + m.nb[0] * (c[1] + m.nb[1] * c[2]);
-}
-
-__global__ __launch_bounds__(kBlock) void k_fill_int(int32_t* __restrict__ a, int64_t n, int v) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) a[i] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__ x, int64_t N,
@@ -48,9 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__
   rank[p] = atomicAdd(count + c, 1);
 }
 
-// Exclusive scan of n ints in three launches: per-block scans (kScanTile
-// elements per block), a single-block scan of the tile totals, and the
-// add-back.
+// Exclusive scan of the n cell counts in two launches: per-block scans
+// (kScanTile cells per block, which also reset the counts) and a single-block
+// scan of the tile totals.  The start of cell c is then the in-tile scan plus
+// its tile's offset (bin_begin); the total sits at index n.
 constexpr int kScanTile = 1024;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh) {
@@ -67,14 +66,17 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh) {
   return incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(int32_t* __restrict__ in, int64_t n,
                                                        int32_t* __restrict__ out,
                                                        int32_t* __restrict__ tile_sum) {
   __shared__ int sh[kBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
   int v[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = base + q < n ? in[base + q] : 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    if (base + q < n) in[base + q] = 0;  // counts start from zero at the next binning
+  }
   const int tsum = v[0] + v[1] + v[2] + v[3];
   int run = block_exclusive_scan(tsum, sh);
 #pragma unroll
@@ -102,179 +104,255 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(int32_t* __restrict__ tile_
   if (threadIdx.x == kBlock - 1) *total = run;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, int64_t n,
-                                                     const int32_t* __restrict__ tile_sum) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) out[i] += tile_sum[i / kScanTile];
+__device__ __forceinline__ int bin_begin(const int32_t* __restrict__ start,
+                                         const int32_t* __restrict__ tiles, int64_t n, int c) {
+  return c == n ? start[n] : start[c] + tiles[c / kScanTile];
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restrict__ bin,
                                                         const int32_t* __restrict__ rank,
                                                         const int32_t* __restrict__ start,
-                                                        int64_t N, int32_t* __restrict__ sorted) {
+                                                        const int32_t* __restrict__ tiles,
+                                                        int64_t n, int64_t N,
+                                                        int32_t* __restrict__ sorted) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= N) return;
   const int c = bin[p];
-  if (c >= 0) sorted[start[c] + rank[p]] = (int32_t)p;
+  if (c >= 0) sorted[bin_begin(start, tiles, n, c) + rank[p]] = (int32_t)p;
 }
 
 // ---------------------------------------------------------------------------
 // Forces: each particle sums its own bond and WCA forces (no atomics; every
 // pair is evaluated from both sides, so the pair forces cancel up to
-// rounding).  Minimum-image separations.  Force models 0 and 1 give zero or
-// the constant f_ext.
+// rounding), with minimum-image separations.  Force models 0 and 1 give zero
+// or the constant f_ext.
+//
+// 32 lanes per particle: lanes 0-26 scan one neighbouring cell each (offsets
+// -1, 0, +1 per axis; on an axis with fewer than 3 cells, cells 0, 1, 2 of
+// that axis instead, so every distinct cell is scanned once), lane 27 adds
+// the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
+// stores the force and, after an MD step, applies the second half-kick of
+// velocity Verlet (new conservative force + the coupling force held over the
+// step).  In variant 2 lanes 0-7 also transfer the step's momentum to the 8
+// cube corners (the spreading of k_spread): this kernel runs after every
+// particle of the step has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
-__global__ __launch_bounds__(kBlock) void k_forces(const double* __restrict__ x,
-                                                   double* __restrict__ f, int64_t N,
-                                                   const RepMD* __restrict__ md,
-                                                   const int32_t* __restrict__ part_rep,
-                                                   const int32_t* __restrict__ bin,
-                                                   const int32_t* __restrict__ start,
-                                                   const int32_t* __restrict__ sorted) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  const RepMD& m = md[part_rep[p]];
-  double F[3] = {0.0, 0.0, 0.0};
-  if (m.force_model == 1) {
-    F[0] = m.f_ext[0];
-    F[1] = m.f_ext[1];
-    F[2] = m.f_ext[2];
-  }
-  const int c = bin[p];
-  if (m.force_model != 2 || c < 0) {
-    f[p] = F[0];
-    f[N + p] = F[1];
-    f[2 * N + p] = F[2];
-    return;
-  }
-  const double X[3] = {x[p], x[N + p], x[2 * N + p]};
-  const double rc2 = 1.2599210498948732 * m.wca_sigma * m.wca_sigma;  // (2^(1/6) sigma)^2
-  const double sig2 = m.wca_sigma * m.wca_sigma;
-  // harmonic bonds to the chain neighbours
-  const int pos = (int)((p - m.part_off) % m.chain_len);
+constexpr int kForceLanes = 32;
+
+__device__ __forceinline__ double lane32_sum(double v) {
+  v += __shfl_xor(v, 16, kForceLanes);
+  v += __shfl_xor(v, 8, kForceLanes);
+  v += __shfl_xor(v, 4, kForceLanes);
+  v += __shfl_xor(v, 2, kForceLanes);
+  v += __shfl_xor(v, 1, kForceLanes);
+  return v;
+}
+
+template <typename T>
+struct ForceArgs {
+  const double* __restrict__ x;
+  double* __restrict__ v;
+  double* __restrict__ f;
+  const double* __restrict__ fc_held;
+  const RepMD* __restrict__ md;
+  const int32_t* __restrict__ part_rep;
+  const int32_t* __restrict__ bin;
+  const int32_t* __restrict__ start;
+  const int32_t* __restrict__ tiles;
+  const int32_t* __restrict__ sorted;
+  // variant-2 transfer of the MD step
+  const int32_t* __restrict__ rec_cell;
+  const double* __restrict__ rec_frac;
+  const double* __restrict__ rec_dp;
+  const unsigned long long* __restrict__ shared_site;
+  Vec4<T>* __restrict__ J;
+  int64_t N;
+  int64_t ncells;
+};
+
+template <typename T, bool Kick, bool Spread>
+__global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
+  const int64_t N = a.N;
+  // lanes come in whole particles (32 | kBlock), as the shuffles require
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kForceLanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / kForceLanes;
+    const int lane = (int)(t & (kForceLanes - 1));
+    const RepMD& m = a.md[a.part_rep[p]];
+    double F[3] = {0.0, 0.0, 0.0};
+    const int c = m.force_model == 2 ? a.bin[p] : -1;
+    if (c >= 0) {
+      const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
+      const double rc2 = 1.2599210498948732 * m.wca_sigma * m.wca_sigma;  // (2^(1/6) sigma)^2
+      const double sig2 = m.wca_sigma * m.wca_sigma;
+      if (lane < 27) {
+        const int o[3] = {lane % 3, (lane / 3) % 3, lane / 9};
+        const int lc = c - m.cell_off;
+        const int cc[3] = {lc % m.nb[0], (lc / m.nb[0]) % m.nb[1], lc / (m.nb[0] * m.nb[1])};
+        int q3[3];
+        bool use = true;
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    if ((side == 0 && pos == 0) || (side == 1 && pos == m.chain_len - 1)) continue;
-    const int64_t q = side == 0 ? p - 1 : p + 1;
-    double dx[3], r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          if (m.nb[d] < 3) {
+            q3[d] = o[d];
+            use = use && o[d] < m.nb[d];
+          } else {
+            const int qq = cc[d] + o[d] - 1;
+            q3[d] = qq < 0 ? qq + m.nb[d] : (qq >= m.nb[d] ? qq - m.nb[d] : qq);
+          }
+        }
+        if (use) {
+          const int cell = m.cell_off + q3[0] + m.nb[0] * (q3[1] + m.nb[1] * q3[2]);
+          const int s1 = bin_begin(a.start, a.tiles, a.ncells, cell + 1);
+          for (int s = bin_begin(a.start, a.tiles, a.ncells, cell); s < s1; ++s) {
+            const int q = a.sorted[s];
+            if (q == p) continue;
+            double dx[3], r2 = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      dx[d] = min_image(X[d] - x[d * N + q], m.L[d]);
-      r2 += dx[d] * dx[d];
-    }
-    const double r = sqrt(r2);
-    const double fm = -m.k_bond * (r - m.r0_bond) / r;
+            for (int d = 0; d < 3; ++d) {
+              dx[d] = min_image(X[d] - a.x[d * N + q], m.L[d]);
+              r2 += dx[d] * dx[d];
+            }
+            if (r2 >= rc2) continue;
+            const double sr2 = sig2 / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double fm = 24.0 * m.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
-  }
-  // WCA over the 27 neighbouring cells (distinct cells only on grids < 3 wide)
-  const int lc = c - m.cell_off;
-  const int cz = lc / (m.nb[0] * m.nb[1]);
-  const int cy = (lc / m.nb[0]) % m.nb[1];
-  const int cx = lc % m.nb[0];
-  const int wz = m.nb[2] < 3 ? m.nb[2] : 3, wy = m.nb[1] < 3 ? m.nb[1] : 3,
-            wx = m.nb[0] < 3 ? m.nb[0] : 3;
-  for (int oz = 0; oz < wz; ++oz) {
-    int zz = m.nb[2] < 3 ? oz : cz + oz - 1;
-    zz = zz < 0 ? zz + m.nb[2] : (zz >= m.nb[2] ? zz - m.nb[2] : zz);
-    for (int oy = 0; oy < wy; ++oy) {
-      int yy = m.nb[1] < 3 ? oy : cy + oy - 1;
-      yy = yy < 0 ? yy + m.nb[1] : (yy >= m.nb[1] ? yy - m.nb[1] : yy);
-      for (int ox = 0; ox < wx; ++ox) {
-        int xx = m.nb[0] < 3 ? ox : cx + ox - 1;
-        xx = xx < 0 ? xx + m.nb[0] : (xx >= m.nb[0] ? xx - m.nb[0] : xx);
-        const int cell = m.cell_off + xx + m.nb[0] * (yy + m.nb[1] * zz);
-        for (int s = start[cell]; s < start[cell + 1]; ++s) {
-          const int q = sorted[s];
-          if (q == p) continue;
+            for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
+          }
+        }
+      } else if (lane == 27) {
+        // harmonic bonds to the chain neighbours
+        const int pos = (int)((p - m.part_off) % m.chain_len);
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if ((side == 0 && pos == 0) || (side == 1 && pos == m.chain_len - 1)) continue;
+          const int64_t q = side == 0 ? p - 1 : p + 1;
           double dx[3], r2 = 0.0;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            dx[d] = min_image(X[d] - x[d * N + q], m.L[d]);
+            dx[d] = min_image(X[d] - a.x[d * N + q], m.L[d]);
             r2 += dx[d] * dx[d];
           }
-          if (r2 >= rc2) continue;
-          const double sr2 = sig2 / r2;
-          const double sr6 = sr2 * sr2 * sr2;
-          const double fm = 24.0 * m.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+          const double r = sqrt(r2);
+          const double fm = -m.k_bond * (r - m.r0_bond) / r;
 #pragma unroll
           for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
         }
       }
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = lane32_sum(F[d]);
+    if (lane == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (m.force_model == 1) F[d] = m.f_ext[d];
+        a.f[d * N + p] = F[d];
+        if (Kick && m.split_kick) {
+          const double vv = a.v[d * N + p];
+          if (isfinite(vv)) a.v[d * N + p] = vv + m.h * (F[d] + a.fc_held[d * N + p]);
+        }
+      }
+    }
+    if (Spread && lane < 8) {
+      Cube q;
+      q.base[0] = a.rec_cell[p];
+      if (q.base[0] >= 0) {
+        q.base[1] = a.rec_cell[N + p];
+        q.base[2] = a.rec_cell[2 * N + p];
+        double dp[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          q.s[d] = a.rec_frac[d * N + p];
+          dp[d] = a.rec_dp[d * N + p];
+        }
+        spread_corner<T>(a.J, a.shared_site, m, q, lane, dp);
+      }
+    }
   }
-  f[p] = F[0];
-  f[N + p] = F[1];
-  f[2 * N + p] = F[2];
 }
 
-// Second half-kick of velocity Verlet with the new conservative force and
-// the coupling force held over the step (replicas with force model 2).
-__global__ __launch_bounds__(kBlock) void k_kick(double* __restrict__ v, const double* __restrict__ f,
-                                                 const double* __restrict__ fc, int64_t N,
-                                                 const RepMD* __restrict__ md,
-                                                 const int32_t* __restrict__ part_rep) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  const RepMD& m = md[part_rep[p]];
-  if (!m.split_kick) return;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double vv = v[d * N + p];
-    if (isfinite(vv)) v[d * N + p] = vv + m.h * (f[d * N + p] + fc[d * N + p]);
-  }
+// Force cells per axis: edge just above the WCA cut-off 2^(1/6) sigma, so the
+// 27 neighbouring cells hold every interacting pair.  Larger cells (about one
+// particle per cell on average) were measured slower on chains: a chain's
+// beads then crowd a few cells and the per-lane cell loops serialise.
+int cells_per_axis(const lbmd_params* p, int d) {
+  const double rc = std::pow(2.0, 1.0 / 6.0) * p->wca_sigma;
+  const int L[3] = {p->nx, p->ny, p->nz};
+  const int q = (int)std::floor((double)L[d] / rc);
+  return q < 1 ? 1 : q;
 }
 
 int64_t force_cells(const lbmd_params* p) {
   if (p->force_model != 2) return 0;
-  const double rc = std::pow(2.0, 1.0 / 6.0) * p->wca_sigma;
-  const int L[3] = {p->nx, p->ny, p->nz};
   int64_t n = 1;
-  for (int d = 0; d < 3; ++d) {
-    int q = (int)std::floor((double)L[d] / rc);
-    n *= q < 1 ? 1 : q;
-  }
+  for (int d = 0; d < 3; ++d) n *= cells_per_axis(p, d);
   return n;
+}
+
+template <typename T>
+static ForceArgs<T> force_args(Context* c) {
+  const Layout& L = c->plan.lay;
+  ForceArgs<T> a;
+  a.x = (const double*)c->x;
+  a.v = (double*)c->v;
+  a.f = (double*)at(c, L.fcons);
+  a.fc_held = (const double*)at(c, L.fc_held);
+  a.md = (const RepMD*)at(c, L.rep_md);
+  a.part_rep = (const int32_t*)at(c, L.part_rep);
+  a.bin = (const int32_t*)at(c, L.bin_of);
+  a.start = (const int32_t*)at(c, L.bin_start);
+  a.tiles = (const int32_t*)at(c, L.bin_tiles);
+  a.sorted = (const int32_t*)at(c, L.bin_sorted);
+  a.rec_cell = (const int32_t*)at(c, L.rec_cell);
+  a.rec_frac = (const double*)at(c, L.rec_frac);
+  a.rec_dp = (const double*)at(c, L.rec_dp);
+  a.shared_site = (const unsigned long long*)at(c, L.shared_site);
+  a.J = (Vec4<T>*)at(c, L.transfer);
+  a.N = c->plan.Ntot;
+  a.ncells = c->plan.Ctot;
+  return a;
+}
+
+// Bin the particles of force-model-2 replicas into their cells.
+static hipError_t launch_binning(Context* c) {
+  const int64_t N = c->plan.Ntot;
+  const Layout& L = c->plan.lay;
+  const int pb = (int)((N + kBlock - 1) / kBlock);
+  int32_t* count = (int32_t*)at(c, L.bin_count);
+  int32_t* tiles = (int32_t*)at(c, L.bin_tiles);
+  int32_t* rank = (int32_t*)at(c, L.bin_rank);
+  int32_t* bin = (int32_t*)at(c, L.bin_of);
+  int32_t* start = (int32_t*)at(c, L.bin_start);
+  const int64_t n = c->plan.Ctot;
+  hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x, N,
+                     (const RepMD*)at(c, L.rep_md), (const int32_t*)at(c, L.part_rep), count, bin,
+                     rank);
+  const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, c->stream, count, n, start,
+                     tiles);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, c->stream, tiles, ntiles, start + n);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(kBlock), 0, c->stream, bin, rank, start, tiles,
+                     n, N, (int32_t*)at(c, L.bin_sorted));
+  return hipGetLastError();
+}
+
+template <typename T, bool Kick, bool Spread>
+static hipError_t forces_t(Context* c) {
+  const ForceArgs<T> a = force_args<T>(c);
+  const dim3 grid((unsigned)((a.N * kForceLanes + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL((k_forces<T, Kick, Spread>), grid, dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError();
 }
 
 // Conservative forces at the current positions (all force models).
 hipError_t launch_forces(Context* c) {
-  const int64_t N = c->plan.Ntot;
-  if (N == 0) return hipSuccess;
-  const Layout& L = c->plan.lay;
-  const int pb = (int)((N + kBlock - 1) / kBlock);
-  const RepMD* md = (const RepMD*)at(c, L.rep_md);
-  const int32_t* prep = (const int32_t*)at(c, L.part_rep);
-  int32_t* bin = (int32_t*)at(c, L.bin_of);
-  int32_t* start = (int32_t*)at(c, L.bin_start);
-  int32_t* sorted = (int32_t*)at(c, L.bin_sorted);
+  if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e;
-  if (c->plan.any_forces2) {
-    int32_t* count = (int32_t*)at(c, L.bin_count);
-    int32_t* tiles = (int32_t*)at(c, L.bin_tiles);
-    int32_t* rank = (int32_t*)at(c, L.bin_rank);
-    const int64_t n = c->plan.Ctot;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       c->stream, count, n, 0);
-    hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x, N,
-                       md, prep, count, bin, rank);
-    const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, c->stream, count, n, start,
-                       tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, c->stream, tiles, ntiles, start + n);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       c->stream, start, n, tiles);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(kBlock), 0, c->stream, bin, rank, start, N,
-                       sorted);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  } else {
-    hipLaunchKernelGGL(k_fill_int, dim3(pb), dim3(kBlock), 0, c->stream, bin, N, -1);
-  }
-  hipLaunchKernelGGL(k_forces, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x,
-                     (double*)at(c, L.fcons), N, md, prep, bin, start, sorted);
-  return hipGetLastError();
+  if (c->plan.any_forces2 && (e = launch_binning(c)) != hipSuccess) return e;
+  return c->plan.prec == 32 ? forces_t<float, false, false>(c) : forces_t<double, false, false>(c);
 }
 
 // Forces at the bound positions; the corner cache is stale from here on.
@@ -284,17 +362,18 @@ hipError_t launch_init_forces(Context* c) {
   return invalidate_corner_cache(c);
 }
 
-// Forces at the new positions, then the second half-kick.
+// After an MD step of replicas with position-dependent forces: binning,
+// forces at the new positions, the second half-kick and, in variant 2, the
+// step's momentum transfer (so the coupling step launches no spreading
+// kernel of its own).
 hipError_t launch_forces_and_kick(Context* c) {
-  hipError_t e = launch_forces(c);
+  if (c->plan.Ntot == 0) return hipSuccess;
+  hipError_t e = launch_binning(c);
   if (e != hipSuccess) return e;
-  const int64_t N = c->plan.Ntot;
-  const Layout& L = c->plan.lay;
-  hipLaunchKernelGGL(k_kick, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     c->stream, (double*)c->v, (const double*)at(c, L.fcons),
-                     (const double*)at(c, L.fc_held), N, (const RepMD*)at(c, L.rep_md),
-                     (const int32_t*)at(c, L.part_rep));
-  return hipGetLastError();
+  const bool v2 = c->p[0].variant == 2;
+  if (c->plan.prec == 32)
+    return v2 ? forces_t<float, true, true>(c) : forces_t<float, true, false>(c);
+  return v2 ? forces_t<double, true, true>(c) : forces_t<double, true, false>(c);
 }
 
 }  // namespace lbmd_impl

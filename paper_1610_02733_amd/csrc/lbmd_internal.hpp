@@ -193,5 +193,6 @@ hipError_t invalidate_corner_cache(Context* c);
 hipError_t launch_forces(Context* c);
 hipError_t launch_forces_and_kick(Context* c);
 int64_t force_cells(const lbmd_params* p);
+int cells_per_axis(const lbmd_params* p, int d);
 
 }  // namespace lbmd_impl
