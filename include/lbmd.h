@@ -168,6 +168,17 @@ int lbmd_get_transfer(lbmd *c, void *d_dst);
 int lbmd_get_counters(lbmd *c, int64_t *t_lb, int64_t *t_md, int32_t *subs);
 int lbmd_set_counters(lbmd *c, int64_t t_lb, int64_t t_md, int32_t subs);
 
+/*
+ * Bandwidth calibration (not part of the method): copy `bytes` bytes from
+ * d_src to d_dst (device, 16-byte aligned, bytes a multiple of 16) with
+ * 16-byte non-temporal loads and stores on a persistent grid, asynchronously
+ * on hip_stream.  This is the read+write streaming ceiling that the
+ * collide-stream kernel's roofline is compared with, and the known-size
+ * dispatch that HBM byte counters are calibrated against.  LBMD_EINVAL for
+ * misaligned or null arguments.
+ */
+int lbmd_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
+
 /* Message for a status code. */
 const char *lbmd_strerror(int code);
 

@@ -977,6 +977,16 @@ int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
   return LBMD_OK;
 }
 
+int lbmd_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* hip_stream) {
+  if (!d_dst || !d_src || bytes % 16 != 0 || ((uintptr_t)d_dst % 16) != 0 ||
+      ((uintptr_t)d_src % 16) != 0)
+    return LBMD_EINVAL;
+  if (bytes == 0) return LBMD_OK;
+  return launch_stream_copy(d_dst, d_src, bytes, (hipStream_t)hip_stream) == hipSuccess
+             ? LBMD_OK
+             : LBMD_EHIP;
+}
+
 const char* lbmd_strerror(int code) {
   switch (code) {
     case LBMD_OK: return "ok";

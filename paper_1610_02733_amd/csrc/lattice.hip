@@ -348,4 +348,32 @@ hipError_t launch_get_transfer(Context* c, int rep, void* dst) {
   return c->plan.prec == 32 ? copy_t<float>(c, rep, dst, 2) : copy_t<double>(c, rep, dst, 2);
 }
 
+// ---------------------------------------------------------------------------
+// Plain device copy with 16-byte non-temporal loads and stores on a
+// persistent grid: the read+write streaming ceiling the roofline of the
+// collide-stream kernel is set against (and the known-size dispatch the HBM
+// byte counters are calibrated with).
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const v4f* __restrict__ src,
+                                                        v4f* __restrict__ dst, size_t n4) {
+  for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < n4;
+       t += (size_t)gridDim.x * kBlock)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + t), dst + t);
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  int dev = 0, cu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cu = 256;
+  const size_t n4 = bytes / 16;
+  const size_t want = (n4 + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)4 * cu));
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, stream, (const v4f*)src,
+                     (v4f*)dst, n4);
+  return hipGetLastError();
+}
+
 }  // namespace lbmd_impl

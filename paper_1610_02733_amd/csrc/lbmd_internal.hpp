@@ -182,6 +182,7 @@ hipError_t launch_couple_adjoint(Context* c);
 hipError_t launch_adjoint_fold(Context* c);
 hipError_t launch_store_counters(Context* c, void* dst, int64_t t_lb, int64_t t_md);
 hipError_t launch_clock_advance(Context* c);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
 hipError_t launch_get_populations(Context* c, int rep, void* dst);
 hipError_t launch_set_populations(Context* c, int rep, const void* src);

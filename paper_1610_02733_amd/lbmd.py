@@ -20,6 +20,9 @@ OK, EINVAL, ESTATE, EHIP, ENOSPACE, ENONFINITE = 0, -1, -2, -3, -4, -5
 NTOTALS = 14
 TOT = dict(mass=0, pfluid=slice(1, 4), pseen=slice(4, 7), ppart=slice(7, 10), ke=10,
            u2=11, t_lb=12, t_md=13)
+# D3Q19 weights in the library's velocity order (include/lbmd.h): rest,
+# the 6 axis directions, the 12 face diagonals.
+WEIGHTS = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
 
 
 class Params(C.Structure):
@@ -81,6 +84,8 @@ def lib():
         L.lbmd_batch_set_populations.argtypes = [P, C.c_int32, P]
         L.lbmd_batch_get_transfer.argtypes = [P, C.c_int32, P]
         L.lbmd_autotune.argtypes = [P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.lbmd_stream_copy.argtypes = [P, P, C.c_size_t, P]
+        L.lbmd_stream_copy.restype = C.c_int
         L.lbmd_state_bytes.argtypes = [P]
         L.lbmd_state_bytes.restype = C.c_size_t
         L.lbmd_save_state.argtypes = [P, P]
@@ -111,6 +116,17 @@ DEFAULTS = dict(n_sub=1, variant=2, precision=32, n_particles=0, force_model=0, 
                 replica=0, seed=0, rho0=1.0, nu=1.0 / 6.0, nu_bulk=-1.0, gamma_ghost=0.0,
                 kT=0.0, friction=0.0, particle_mass=1.0, body_force=(0.0, 0.0, 0.0),
                 f_ext=(0.0, 0.0, 0.0), k_bond=0.0, r0_bond=1.0, wca_eps=0.0, wca_sigma=1.0)
+
+
+def stream_copy(dst, src, stream=None):
+    """Device copy of src into dst (same byte size, 16-byte multiple) with the
+    library's non-temporal streaming kernel (bandwidth calibration)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(lib().lbmd_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                                  nbytes, C.c_void_p(s.cuda_stream)), "lbmd_stream_copy")
 
 
 def make_params(shape, **kw) -> Params:
@@ -371,6 +387,16 @@ class Batch(_System):
         out = torch.empty((19, S), dtype=self.dtype, device=self.device)
         _check(lib().lbmd_batch_get_populations(self._h, rep, _ptr(out)), "batch_get_populations")
         return out
+
+    def temperatures(self):
+        """Particle temperature over kT per replica, 2 KE / (3 N kT) (NaN for a
+        replica without particles or whose particles went non-finite)."""
+        tot = self.moments()
+        kT = np.array([self.params[r].kT for r in range(self.R)])
+        n = np.maximum(np.asarray(self.Ns, float), 1.0)
+        T = 2.0 * tot[:, TOT["ke"]] / (3.0 * n * np.where(kT > 0, kT, np.nan))
+        T[np.asarray(self.Ns) == 0] = np.nan
+        return T
 
     def moments(self, allow_nonfinite=True):
         tot = np.zeros((self.R, NTOTALS))

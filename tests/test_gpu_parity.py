@@ -109,7 +109,8 @@ def test_c1_coupled(lb, orc, prec, variant):
     gd, fo = g.populations().cpu().numpy(), o.populations()
     err = pop_err(gd, fo, w, rho0)
     inst = (np.abs(full_pops(gd, w, rho0) - fo) / np.abs(fo)).max()
-    print(f"c1 variant {variant} fp{prec}: max err / (w rho0) {err:.3e}, "
+    rms = float(np.sqrt(np.mean(((full_pops(gd, w, rho0) - fo) / (w[:, None] * rho0)) ** 2)))
+    print(f"c1 variant {variant} fp{prec}: max err / (w rho0) {err:.3e}, rms {rms:.3e}, "
           f"max err / |f| {inst:.3e}, min f / (w rho0) {(fo / w[:, None]).min():.3f}")
     assert err < TOL[prec]
     check_particles(g, o, cfg["shape"], TOL[prec], cfg["kT"])
@@ -249,3 +250,37 @@ def test_fast_particles_wrap(lb, orc):
     check_particles(g, o, shape, 1e-12, 1.0)
     err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
     assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_full_size_sampled_parity(lb, orc, prec):
+    """The 256^3 workload as bench.py times it (1e5 free particles, n = 10,
+    gamma = 10, kT = 1e-4, variant 2, default launch shapes): one coupled
+    cycle from the seeded start, every particle and 2048 random sites against
+    the FP64 oracle (which evaluates the sampled sites one by one)."""
+    cfg = wl.CONFIGS["c3"]
+    shape = cfg["shape"]
+    x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
+                             cfg["seed"])
+    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
+              friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
+              particle_mass=cfg["particle_mass"])
+    g = lb.Lattice(shape, precision=prec, **kw)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    for _ in range(cfg["n_sub"]):
+        g.md_couple_substep()
+        o.md_couple_substep()
+    g.lb_step()
+    sites = np.random.default_rng(0).choice(int(np.prod(shape)), 2048, replace=False)
+    ref = o.lb_step_sampled(sites)  # [nsample, 19] full populations
+    c, w, e, b = orc.tables()
+    dev = g.populations()[:, sites].double().cpu().numpy().T
+    rel = np.abs(dev + w * cfg["rho0"] - ref) / (w * cfg["rho0"])
+    print(f"256^3 fp{prec} one cycle, sampled sites: max {rel.max():.3e}, "
+          f"rms {np.sqrt(np.mean(rel ** 2)):.3e}")
+    assert rel.max() < TOL[prec]
+    check_particles(g, o, shape, TOL[prec], cfg["kT"], cfg["particle_mass"])
+    g.close()
+    o.close()
