@@ -350,7 +350,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-statement", action="store_true",
                     help="skip the FP32-vs-FP64 comparison on the workload")
-    ap.add_argument("--variants", default="1,2")
+    ap.add_argument("--variants", default="1,2,3",
+                    help="coupling variants to time (1 = A, 2 = B, 3 = C); the JSON value is variant 2")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c2p"],
                     help="c3: 256^3, 1e5 free particles (default); c2: 128^3 polymer "
                          "solution, 200 chains x 50 beads, bonds + WCA, as specified "
@@ -437,6 +438,9 @@ def main():
     if 1 in res and 2 in res:
         out["variant1_ms_per_step"] = round(res[1][0] / args.steps * 1e3, 4)
         out["variant2_over_variant1"] = round(res[2][0] / res[1][0], 4)
+    if 1 in res and 3 in res:
+        out["variant3_ms_per_step"] = round(res[3][0] / args.steps * 1e3, 4)
+        out["variant3_over_variant1"] = round(res[3][0] / res[1][0], 4)
     if not args.no_batch:
         log("batched ensemble: 512 replicas, batched vs serial")
         out["batch"] = batch_measure(lbmd, torch)

@@ -51,10 +51,10 @@ enum {
   LBMD_TOT_MASS = 0,     /* sum_r rho(r)                                      */
   LBMD_TOT_PFLUID = 1,   /* [3] sum_r j(r) + sum_r J(r)                       */
   LBMD_TOT_PSEEN = 4,    /* [3] momentum the coupling sees: variant 1 sum j,
-                            variant 2 sum j + sum J                           */
+                            variants 2 and 3 sum j + sum J                    */
   LBMD_TOT_PPART = 7,    /* [3] sum_p m v_p                                   */
   LBMD_TOT_KEPART = 10,  /* sum_p m |v_p|^2 / 2                               */
-  LBMD_TOT_U2FLUID = 11, /* mean over sites of |j/rho|^2                      */
+  LBMD_TOT_U2FLUID = 11, /* mean over sites of |j/rho|^2 (variant 3: |(j+J)/rho|^2) */
   LBMD_TOT_TLB = 12,     /* LB steps done                                     */
   LBMD_TOT_TMD = 13,     /* MD steps done                                     */
   LBMD_NTOTALS = 14
@@ -63,14 +63,19 @@ enum {
 /*
  * Parameters: the paper's statement of the problem (Sec. 2-3): lattice size,
  * n = tau_LB/tau_MD, viscosity, friction (the paper's zeta, Eq. 4), kT and
- * the coupling variant (1 = variant A, 2 = variant B).
+ * the coupling variant (1 = variant A, 2 = variant B, 3 = variant C).
  */
 typedef struct {
   int32_t nx, ny, nz;     /* sites per axis, periodic, each >= 2               */
   int32_t n_sub;          /* n = tau_LB / tau_MD, integer >= 1 (Sec. 3)        */
   int32_t variant;        /* 1: fluid velocity frozen over the LB interval;
                              2: the sites around each particle see its momentum
-                             transfer at the next MD step (Sec. 3)             */
+                             transfer at the next MD step (Sec. 3);
+                             3: each MD step's transfer is applied to the
+                             populations of the receiving sites through the
+                             forcing part of the collision (Guo, no relaxation,
+                             no noise, no streaming), and the LB step then
+                             applies only the body force (Sec. 3, variant C)   */
   int32_t precision;      /* 32: float populations stored as deviations from
                              w_i rho0; 64: double (also deviations)            */
   int32_t n_particles;    /* N >= 0                                            */
@@ -125,7 +130,12 @@ int lbmd_bind_particles(lbmd *c, void *d_x, void *d_v, int32_t *d_img);
  * (Eq. 4), dP = tau_MD F (Eq. 6), transfer -delta_k dP to the 8 sites
  * (Eq. 7-8) and advance the particle by velocity Verlet.  In variant 2 the
  * transfer is seen by the velocity interpolation of the next MD step; in
- * variant 1 only by the next lb_step().  At most n_sub calls per LB interval
+ * variant 1 only by the next lb_step(); in variant 3 it changes the
+ * state of the receiving sites before the next MD step (momentum + dJ,
+ * stress modes + (1+gamma)/2 times the image of u dJ + dJ u with
+ * u = (j + dJ/2)/rho; the library keeps these increments per site and adds
+ * them to the stored populations at the next lb_step(), which is the same
+ * state in exact arithmetic).  At most n_sub calls per LB interval
  * (LBMD_ESTATE otherwise).
  */
 int md_couple_substep(lbmd *c);
@@ -133,7 +143,9 @@ int md_couple_substep(lbmd *c);
 /*
  * One LB step (Eq. 3): MRT collision with the force density J/tau_LB of the
  * accumulated momentum transfer (Guo forcing) plus body_force, thermal noise
- * on the 15 non-conserved modes, then streaming.  Requires exactly n_sub
+ * on the 15 non-conserved modes, then streaming.  Variant 3: the interval's
+ * site increments join the populations first and the force density is
+ * body_force alone.  Requires exactly n_sub
  * md_couple_substep() calls since the previous lb_step() when N > 0
  * (LBMD_ESTATE otherwise).
  */
@@ -141,7 +153,8 @@ int lb_step(lbmd *c);
 
 /*
  * Moments of the current (post-stream) state (Eq. 1-2).  d_rho: nullable
- * device [nsites] density; d_u: nullable device [3][nsites] velocity j/rho;
+ * device [nsites] density; d_u: nullable device [3][nsites] velocity j/rho
+ * (variant 3: (j + J)/rho, the momentum of the state after the MD steps);
  * both in the context precision.  h_totals: nullable host double[LBMD_NTOTALS]
  * (FP64 reductions, see the LBMD_TOT_* layout); when given, the call
  * synchronizes the stream and returns LBMD_ENONFINITE if any particle became
@@ -155,7 +168,10 @@ int lb_moments(lbmd *c, void *d_rho, void *d_u, double *h_totals);
  * site index r = x + nx*(y + ny*z), velocity order: 0, +x, -x, +y, -y, +z,
  * -z, (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1),
  * (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  Get copies out, set
- * replaces the state (pending momentum transfer is kept).
+ * replaces the state (variants 1, 2: pending momentum transfer is kept).
+ * Variant 3: get includes the increments the MD steps of the current LB
+ * interval applied (the populations of the paper's variant C), and set
+ * replaces them too (the replica's J is cleared).
  */
 int lbmd_get_populations(lbmd *c, void *d_dst);
 int lbmd_set_populations(lbmd *c, const void *d_src);

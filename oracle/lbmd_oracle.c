@@ -1,8 +1,8 @@
 /*
  * lbmd_oracle.c -- plain, slow FP64 CPU reference of the fluctuating D3Q19
  * lattice-Boltzmann fluid with dissipative (Ahlrichs-Duenweg) point-particle
- * coupling, in the two coupling variants of Tretyakov & Duenweg,
- * arXiv:1610.02733 (variant A = 1, variant B = 2).
+ * coupling, in the coupling variants of Tretyakov & Duenweg,
+ * arXiv:1610.02733 (variant A = 1, variant B = 2, variant C = 3).
  *
  * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark may load this library.  It shares no code,
@@ -193,7 +193,7 @@ void orc_particle_variates(uint64_t seed, uint32_t replica, uint64_t particle,
 typedef struct {
   int32_t nx, ny, nz;
   int32_t n_sub;       /* n = tau_LB / tau_MD, integer >= 1 (Sec. 3)      */
-  int32_t variant;     /* 1 = variant A, 2 = variant B                      */
+  int32_t variant;     /* 1 = variant A, 2 = variant B, 3 = variant C       */
   int32_t n_particles;
   int32_t force_model; /* 0 none, 1 constant f_ext, 2 harmonic bonds + WCA */
   int32_t chain_len;   /* beads per chain for force model 2                 */
@@ -210,7 +210,9 @@ typedef struct {
   int64_t nsites;
   double *f;    /* [Q][nsites] post-stream populations (the physical state)  */
   double *J;    /* [3][nsites] momentum transferred by the particles since
-                   the last LB step (Eq. 8 summed over the MD steps)         */
+                   the last LB step (Eq. 8 summed over the MD steps);
+                   variants A and B only                                     */
+  double *dJ;   /* [3][nsites] transfer of the current MD step (variant C)   */
   double *x, *v, *fcons; /* [3][N]                                          */
   int32_t *img;          /* [3][N] periodic image counters                   */
   int64_t t_lb, t_md;
@@ -258,7 +260,7 @@ int orc_create(const orc_params *p, orc_ctx **out) {
   tables_init();
   *out = NULL;
   if (p->nx < 2 || p->ny < 2 || p->nz < 2) return ORC_EINVAL;
-  if (p->n_sub < 1 || (p->variant != 1 && p->variant != 2)) return ORC_EINVAL;
+  if (p->n_sub < 1 || p->variant < 1 || p->variant > 3) return ORC_EINVAL;
   if (!(p->nu > 0.0) || !(p->kT >= 0.0) || !(p->friction >= 0.0)) return ORC_EINVAL;
   if (!(p->rho0 > 0.0) || p->n_particles < 0) return ORC_EINVAL;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return ORC_EINVAL;
@@ -269,6 +271,7 @@ int orc_create(const orc_params *p, orc_ctx **out) {
   c->nsites = (int64_t)p->nx * p->ny * p->nz;
   c->f = (double *)malloc(sizeof(double) * Q * c->nsites);
   c->J = (double *)calloc(3 * c->nsites, sizeof(double));
+  c->dJ = (double *)calloc(3 * c->nsites, sizeof(double));
   int64_t n = p->n_particles > 0 ? p->n_particles : 1;
   c->x = (double *)calloc(3 * n, sizeof(double));
   c->v = (double *)calloc(3 * n, sizeof(double));
@@ -284,7 +287,7 @@ int orc_create(const orc_params *p, orc_ctx **out) {
 
 void orc_destroy(orc_ctx *c) {
   if (!c) return;
-  free(c->f); free(c->J); free(c->x); free(c->v); free(c->fcons); free(c->img);
+  free(c->f); free(c->J); free(c->dJ); free(c->x); free(c->v); free(c->fcons); free(c->img);
   free(c);
 }
 
@@ -547,7 +550,9 @@ void orc_cube_weights(const orc_ctx *c, const double R[3], int64_t sites[8],
 /* fluid velocity seen by the coupling at a site: u = j/rho of the
  * post-stream state (variant A), plus the momentum already transferred in
  * this LB interval, (j + J)/rho (variant B: "update the lattice velocities
- * on the surrounding sites"; the populations themselves are not touched). */
+ * on the surrounding sites"; the populations themselves are not touched).
+ * In variant C the transfers are applied to the populations at every MD
+ * step, so u = j/rho of the current populations (J stays zero). */
 static void site_velocity(const orc_ctx *c, int64_t r, double u[3]) {
   int64_t S = c->nsites;
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -580,6 +585,56 @@ static void wrap_position(double *x, int32_t *img, double L) {
   }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Variant C (Sec. 3, the refined variant): at every MD step the momentum     */
+/* transfer dJ of the step is applied to the populations of each receiving    */
+/* site through the forcing part of the collision operator alone -- no        */
+/* relaxation, no noise, no streaming.  Reading: the same mode-space forcing  */
+/* as in the LB step (Guo), with the site's current velocity                  */
+/*   u = (j + dJ/2) / rho,                                                    */
+/*   G_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . dJ,    g_k = sum_i e_k(c_i) G_i  */
+/*   dm_0 = 0,  dm_{1,2,3} = dJ (= g_{1,2,3}),                                */
+/*   dm_k = (1 + gamma_k)/2 g_k  (stress modes, k = 4..9),  dm_k = 0 (k >= 10) */
+/*   f_i += w_i sum_k e_k(c_i) dm_k / b_k.                                    */
+/* Mass and the kinetic modes are unchanged, the momentum changes by exactly  */
+/* dJ (momentum is conserved at every MD step, as in variant B), and the     */
+/* next MD step reads its velocities from the changed populations.           */
+/* ------------------------------------------------------------------------- */
+static void forcing_update(const orc_ctx *c, int64_t r, const double dJ[3]) {
+  int64_t S = c->nsites;
+  double f[Q], rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < Q; ++i) {
+    f[i] = c->f[i * S + r];
+    rho += f[i];
+    for (int d = 0; d < 3; ++d) j[d] += CV[i][d] * f[i];
+  }
+  double u[3];
+  for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * dJ[d]) / rho;
+  double G[Q];
+  for (int i = 0; i < Q; ++i) {
+    double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+    double g = 0.0;
+    for (int d = 0; d < 3; ++d) g += (3.0 * (CV[i][d] - u[d]) + 9.0 * cu * CV[i][d]) * dJ[d];
+    G[i] = Wt[i] * g;
+  }
+  double dm[Q];
+  for (int k = 0; k < Q; ++k) {
+    double gk = 0.0;
+    for (int i = 0; i < Q; ++i) gk += Emat[k][i] * G[i];
+    if (k == 0 || k >= 10)
+      dm[k] = 0.0;
+    else if (k <= 3)
+      dm[k] = dJ[k - 1];
+    else
+      dm[k] = 0.5 * (1.0 + mode_rate(c, k)) * gk;
+  }
+  for (int i = 0; i < Q; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < Q; ++k) s += Emat[k][i] * dm[k] / Bn[k];
+    c->f[i * S + r] = f[i] + Wt[i] * s;
+  }
+}
+
 /* One MD step of the coupled system (Sec. 3, Eq. 4-8 and the variant-B
  * schedule):
  *  1. for every particle, from start-of-step R, v and a fresh F_rand:
@@ -590,7 +645,9 @@ static void wrap_position(double *x, int32_t *img, double L) {
  *     (the discrete fluctuation-dissipation balance of the friction).
  *  2. every particle transfers -delta_k dP to J(r_k)          (Eq. 7-8)
  *     -- all particles read the velocities of step 1 first, so within one
- *     MD step no particle sees another's transfer of the same step.
+ *     MD step no particle sees another's transfer of the same step.  In
+ *     variant C the step's transfers are collected per site and applied to
+ *     the populations (forcing_update).
  *  3. velocity Verlet with F_c held over the step:
  *       v += tau/(2m) (F_cons(R) + F_c);  R += tau v;  wrap;
  *       F_cons(R_new);  v += tau/(2m) (F_cons(R_new) + F_c).
@@ -631,11 +688,27 @@ int orc_md_couple_substep(orc_ctx *c) {
     for (int d = 0; d < 3; ++d)
       Fc[d * N + a] = -p->friction * (v[d] - uR[d]) + amp * xi[d];
   }
+  double *target = p->variant == 3 ? c->dJ : c->J;
   for (int64_t a = 0; a < N; ++a) {
     if (!ok[a]) continue;
     for (int k = 0; k < 8; ++k)
       for (int d = 0; d < 3; ++d)
-        c->J[d * S + sites[a][k]] -= wts[a][k] * tau * Fc[d * N + a];
+        target[d * S + sites[a][k]] -= wts[a][k] * tau * Fc[d * N + a];
+  }
+  if (p->variant == 3) {
+    /* variant C: apply each receiving site's total transfer of this step to
+       its populations, once (every site reads the state as of the step
+       start: the updates touch disjoint sites) */
+    for (int64_t a = 0; a < N; ++a) {
+      if (!ok[a]) continue;
+      for (int k = 0; k < 8; ++k) {
+        int64_t r = sites[a][k];
+        double dJ[3] = {c->dJ[r], c->dJ[S + r], c->dJ[2 * S + r]};
+        if (dJ[0] == 0.0 && dJ[1] == 0.0 && dJ[2] == 0.0) continue; /* done or empty */
+        forcing_update(c, r, dJ);
+        c->dJ[r] = c->dJ[S + r] = c->dJ[2 * S + r] = 0.0;
+      }
+    }
   }
   double L[3] = {p->nx, p->ny, p->nz};
   double h = tau / (2.0 * p->particle_mass);

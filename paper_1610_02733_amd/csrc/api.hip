@@ -31,7 +31,7 @@ bool valid_one(const lbmd_params* p) {
   const int64_t S = (int64_t)p->nx * p->ny * p->nz;
   if (S > (int64_t)0x3FFFFFFF) return false;
   if (p->n_sub < 1) return false;
-  if (p->variant != 1 && p->variant != 2) return false;
+  if (p->variant < 1 || p->variant > 3) return false;
   if (p->precision != 32 && p->precision != 64) return false;
   if (p->n_particles < 0) return false;
   if (!(p->rho0 > 0.0) || !(p->nu > 0.0) || !(p->kT >= 0.0) || !(p->friction >= 0.0)) return false;
@@ -96,6 +96,10 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.pop[0] = o; o = up(o + 19 * S * t);
   L.pop[1] = o; o = up(o + 19 * S * t);
   L.transfer = o; o = up(o + 4 * S * t);
+  const size_t S3 = p[0].variant == 3 ? S : 0;  // variant-3 per-site fields
+  L.jstep = o; o = up(o + 4 * S3 * t);
+  L.vc_stress = o; o = up(o + 8 * S3 * t);
+  L.vc_moments = o; o = up(o + 4 * S3 * t);
   L.mark = o; o = up(o + (S / 64) * 8);
   L.rep_lb = o; o = up(o + (size_t)R * (pl.prec == 32 ? sizeof(RepLB<float>) : sizeof(RepLB<double>)));
   L.rep_md = o; o = up(o + (size_t)R * sizeof(RepMD));
@@ -466,7 +470,7 @@ static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* 
     h[LBMD_TOT_MASS] = p.rho0 * S + t[0];
     for (int d = 0; d < 3; ++d) {
       h[LBMD_TOT_PFLUID + d] = t[1 + d] + t[4 + d];
-      h[LBMD_TOT_PSEEN + d] = t[1 + d] + (p.variant == 2 ? t[4 + d] : 0.0);
+      h[LBMD_TOT_PSEEN + d] = t[1 + d] + (p.variant >= 2 ? t[4 + d] : 0.0);
       h[LBMD_TOT_PPART + d] = m * t[8 + d];
     }
     h[LBMD_TOT_KEPART] = 0.5 * m * t[11];
@@ -497,6 +501,18 @@ int lbmd_batch_set_populations(lbmd* c, int32_t rep, const void* d_src) {
   if (rc || !d_src) return rc ? rc : LBMD_EINVAL;
   rc = fail(c, launch_set_populations(c, rep, d_src));
   if (rc) return rc;
+  if (c->p[0].variant == 3) {
+    // the increments received in the current interval are part of the
+    // variant-3 state that the new populations replace
+    const size_t t = c->plan.prec == 32 ? 4 : 8, off = (size_t)c->plan.site_off[rep];
+    const size_t n = (size_t)c->p[rep].nx * c->p[rep].ny * c->p[rep].nz;
+    rc = fail(c, hipMemsetAsync((char*)at(c, c->plan.lay.transfer) + off * 4 * t, 0, n * 4 * t,
+                                c->stream));
+    if (!rc)
+      rc = fail(c, hipMemsetAsync((char*)at(c, c->plan.lay.vc_stress) + off * 8 * t, 0,
+                                  n * 8 * t, c->stream));
+    if (rc) return rc;
+  }
   return fail(c, invalidate_corner_cache(c));
 }
 
@@ -583,7 +599,7 @@ AdjLayout adj_layout(const Context* c, int K) {
 }
 
 bool adjoint_supported(const Context* c) {
-  return c->plan.R == 1 && c->p[0].force_model <= 1;
+  return c->plan.R == 1 && c->p[0].force_model <= 1 && c->p[0].variant <= 2;
 }
 
 // Particles, counters and an empty transfer field from a saved state (the
@@ -610,6 +626,10 @@ int load_common(lbmd* c, const char* src, const StateLayout& sl) {
   if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.mark), 0, (S / 64) * 8, c->stream));
   if (!rc)
     rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.shared_site), 0, (S / 64) * 8, c->stream));
+  if (!rc && c->p[0].variant == 3) {
+    rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.jstep), 0, S * 4 * t, c->stream));
+    if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.vc_stress), 0, S * 8 * t, c->stream));
+  }
   if (rc) return rc;
   c->t_lb = cnt[0];
   c->t_md = cnt[1];

@@ -4,6 +4,7 @@
 // every replica of a context in one launch.
 #include <algorithm>
 
+#include "forcing.hpp"
 #include "lbmd_internal.hpp"
 
 namespace lbmd_impl {
@@ -33,7 +34,10 @@ __device__ __forceinline__ int replica_of_item(const int32_t* __restrict__ item_
 // this LB step, collides and writes its 19 results at r in the other buffer
 // (coalesced).  J is only read where the site's bit in `mark` is set (the
 // coupling sets it when it transfers momentum there), and is cleared with it,
-// so the untouched bulk of the lattice costs no transfer traffic.  A work
+// so the untouched bulk of the lattice costs no transfer traffic.  In
+// variant 3 (VarC) the interval's transfers already belong to the state: the
+// thread adds their mode increments (momentum J, stress S) to the pulled
+// populations and collides with the body force alone.  A work
 // item is 256 consecutive sites of one replica; replica offsets are
 // multiples of 64, so one wavefront owns exactly one 64-bit mark word.
 // Persistent grid: blocks stride over the items.
@@ -47,16 +51,20 @@ struct StreamArgs {
   const RepLB<T>* __restrict__ rep;
   const int32_t* __restrict__ item_off;
   const Clock* __restrict__ clock;
+  Vec4<T>* __restrict__ jstep;                // variant 3: step transfer at shared sites
+  Stress8<T>* __restrict__ S;                 // variant 3: stress increments of the interval
+  const Vec4<T>* __restrict__ vcm;            // variant 3: (j, 1/rho) of shared sites
   Vec4<T>* __restrict__ jrec;                 // recording: J consumed at marked sites
   unsigned long long* __restrict__ mrec;      // recording: mark words
   size_t P;  // population stride (padded total sites)
   int R, nitems;
+  int varc;  // variant 3: J belongs to the fluid state (fields read j + J)
 };
 
 // With Rec, the transfer field and the mark words the step consumes are also
 // copied out for the reverse sweep (the adjoint needs the force density of
 // the step and the set of sites the MD steps touched).
-template <typename T, bool Rec>
+template <typename T, bool Rec, bool VarC>
 __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   const int cur = a.clock->cur;
   const long long t = a.clock->t_lb;
@@ -85,9 +93,19 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
     T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
     if ((word >> (gsite & 63)) & 1ull) {
       const Vec4<T> jv = a.J[gsite];
-      Fx += jv.x;
-      Fy += jv.y;
-      Fz += jv.z;
+      if (VarC) {
+        const Stress8<T> sv = a.S[gsite];
+        const T sm[6] = {sv.a.x, sv.a.y, sv.a.z, sv.a.w, sv.b.x, sv.b.y};
+        T dd[19];
+        mode_increments_to_pops<T>(jv.x, jv.y, jv.z, sm, dd);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) d[i] += dd[i];
+        a.S[gsite] = Stress8<T>{};
+      } else {
+        Fx += jv.x;
+        Fy += jv.y;
+        Fz += jv.z;
+      }
       a.J[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
       if (Rec) a.jrec[gsite] = jv;
     }
@@ -117,6 +135,9 @@ static StreamArgs<T> stream_args(Context* c) {
   a.pop[0] = (T*)c->popv[0];
   a.pop[1] = (T*)c->popv[1];
   a.J = (Vec4<T>*)at(c, c->plan.lay.transfer);
+  a.jstep = (Vec4<T>*)at(c, c->plan.lay.jstep);
+  a.S = (Stress8<T>*)at(c, c->plan.lay.vc_stress);
+  a.vcm = (const Vec4<T>*)at(c, c->plan.lay.vc_moments);
   a.jrec = (Vec4<T>*)c->rec_J;
   a.mrec = c->rec_mark;
   a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
@@ -127,6 +148,7 @@ static StreamArgs<T> stream_args(Context* c) {
   a.P = (size_t)c->plan.Stot;
   a.R = c->plan.R;
   a.nitems = c->plan.nitems;
+  a.varc = c->p[0].variant == 3 ? 1 : 0;
   return a;
 }
 
@@ -134,15 +156,96 @@ template <typename T>
 static hipError_t collide_stream_t(Context* c) {
   StreamArgs<T> a = stream_args<T>(c);
   const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
-  if (a.jrec)
-    hipLaunchKernelGGL((k_collide_stream<T, true>), dim3(blocks), dim3(kBlock), 0, c->stream, a);
+  if (c->p[0].variant == 3)  // no adjoint for variant 3: never recording
+    hipLaunchKernelGGL((k_collide_stream<T, false, true>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
+  else if (a.jrec)
+    hipLaunchKernelGGL((k_collide_stream<T, true, false>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
   else
-    hipLaunchKernelGGL((k_collide_stream<T, false>), dim3(blocks), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_collide_stream<T, false, false>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_collide_stream(Context* c) {
   return c->plan.prec == 32 ? collide_stream_t<float>(c) : collide_stream_t<double>(c);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 3 (the paper's variant C), sites shared by several particles.
+// After every MD step each receiving site takes the step's transfer dJ into
+// its state through the forcing part of the collision alone (no relaxation,
+// no noise, no streaming): momentum +dJ, stress modes + (1+gamma)/2 q(u, dJ)
+// with u = (j + J + dJ/2)/rho, where j, rho are the site's moments at the
+// start of the interval and J the momentum it received since.  The library
+// keeps these increments per site (J and S) until the LB step adds them to
+// the populations.  A site claimed by a single particle in the interval is
+// updated by that particle's spreading lane; this kernel does the sites
+// flagged as shared, whose step transfer was summed in the step field and
+// whose start-of-interval (j, 1/rho) the spreading lanes stored.  One thread
+// per 64-site word of the shared bitmap.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int replica_of_site(const RepLB<T>* __restrict__ rep, int R, int gs) {
+  int lo = 0, hi = R;  // rep[lo].site_off <= gs < rep[hi].site_off
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rep[mid].site_off <= gs)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_site_update(StreamArgs<T> a, int64_t nwords) {
+  for (int64_t wd = (int64_t)blockIdx.x * kBlock + threadIdx.x; wd < nwords;
+       wd += (int64_t)gridDim.x * kBlock) {
+    unsigned long long word = a.shared_site[wd];
+    if (!word) continue;
+    const int gs0 = (int)(wd * 64);
+    const RepLB<T>& q = a.rep[a.R == 1 ? 0 : replica_of_site(a.rep, a.R, gs0)];
+    while (word) {
+      const int b = __builtin_ctzll(word);
+      word &= word - 1ull;
+      const int gsite = gs0 + b;
+      const Vec4<T> dJ = a.jstep[gsite];
+      if (dJ.x == T(0) && dJ.y == T(0) && dJ.z == T(0)) continue;
+      const Vec4<T> m0 = a.vcm[gsite];
+      Vec4<T> jv = a.J[gsite];
+      T sm[6];
+      stress_increment<T>(m0.x, m0.y, m0.z, m0.w, jv.x, jv.y, jv.z, dJ.x, dJ.y, dJ.z, q.k.hb,
+                          q.k.hs, sm);
+      Stress8<T> sv = a.S[gsite];
+      sv.a.x += sm[0];
+      sv.a.y += sm[1];
+      sv.a.z += sm[2];
+      sv.a.w += sm[3];
+      sv.b.x += sm[4];
+      sv.b.y += sm[5];
+      a.S[gsite] = sv;
+      jv.x += dJ.x;
+      jv.y += dJ.y;
+      jv.z += dJ.z;
+      a.J[gsite] = jv;
+      a.jstep[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
+    }
+  }
+}
+
+template <typename T>
+static hipError_t site_update_t(Context* c) {
+  StreamArgs<T> a = stream_args<T>(c);
+  const int64_t nwords = c->plan.Stot / 64;
+  const int blocks = (int)std::max<int64_t>(1, (nwords + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_site_update<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a, nwords);
+  return hipGetLastError();
+}
+
+hipError_t launch_site_update(Context* c) {
+  return c->plan.prec == 32 ? site_update_t<float>(c) : site_update_t<double>(c);
 }
 
 // End of an LB step: advance the device clock (graph-capturable).
@@ -206,6 +309,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_r
       T drho, jx, jy, jz;
       moments_deviation<T>(d, drho, jx, jy, jz);
       const T rho = q.k.rho0 + drho;
+      const Vec4<T> jv = a.J[q.site_off + local];
+      acc[1] = (double)jx;
+      acc[2] = (double)jy;
+      acc[3] = (double)jz;
+      if (a.varc) {
+        jx += jv.x;
+        jy += jv.y;
+        jz += jv.z;
+      }
       if (rr == field_rep) {
         if (rho_out) rho_out[local] = rho;
         if (u_out) {
@@ -215,11 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_r
           u_out[2 * S + local] = jz / rho;
         }
       }
-      const Vec4<T> jv = a.J[q.site_off + local];
       acc[0] = (double)drho;
-      acc[1] = (double)jx;
-      acc[2] = (double)jy;
-      acc[3] = (double)jz;
       acc[4] = (double)jv.x;
       acc[5] = (double)jv.y;
       acc[6] = (double)jv.z;
@@ -284,20 +392,36 @@ hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d
 // Copies between pull storage and the plain post-stream layout of one
 // replica ([19][S] and [3][S] arrays in the run precision).
 // ---------------------------------------------------------------------------
+// Variant 3 (pend != nullptr): a copy out adds the increments the site has
+// received in the current interval (J, S at marked sites), so that it shows
+// the populations as the paper's variant C holds them after each MD step.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy_pop(T* __restrict__ pop, size_t P, int site_off,
-                                                     Geom g, T* __restrict__ plain, int to_plain) {
+                                                     Geom g, T* __restrict__ plain, int to_plain,
+                                                     const Vec4<T>* __restrict__ pend_J,
+                                                     const Stress8<T>* __restrict__ pend_S,
+                                                     const unsigned long long* __restrict__ mark) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= g.S) return;
   int x, y, z, sidx[19];
   site_coords(g, r, x, y, z);
   pull_sources(g, x, y, z, sidx);
   const size_t S = (size_t)g.S;
+  T dd[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) dd[i] = T(0);
+  const int gs = site_off + r;
+  if (to_plain && pend_J && ((mark[gs >> 6] >> (gs & 63)) & 1ull)) {
+    const Vec4<T> jv = pend_J[gs];
+    const Stress8<T> sv = pend_S[gs];
+    const T sm[6] = {sv.a.x, sv.a.y, sv.a.z, sv.a.w, sv.b.x, sv.b.y};
+    mode_increments_to_pops<T>(jv.x, jv.y, jv.z, sm, dd);
+  }
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     T* q = pop + (size_t)i * P + site_off + sidx[i];
     if (to_plain)
-      plain[(size_t)i * S + r] = *q;
+      plain[(size_t)i * S + r] = *q + dd[i];
     else
       *q = plain[(size_t)i * S + r];
   }
@@ -332,8 +456,12 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
     return hipGetLastError();
   }
   T* pop = (T*)c->popv[c->cur];
+  const bool pend = c->p[0].variant == 3;
   hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
-                     (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0);
+                     (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0,
+                     pend ? (const Vec4<T>*)at(c, c->plan.lay.transfer) : nullptr,
+                     pend ? (const Stress8<T>*)at(c, c->plan.lay.vc_stress) : nullptr,
+                     (const unsigned long long*)at(c, c->plan.lay.mark));
   return hipGetLastError();
 }
 

@@ -102,9 +102,10 @@ def test_batch_replicas_match_single_runs(lb, orc, prec, variant):
         assert np.allclose(tot[r, 7:11], ts[7:11], rtol=mtol, atol=1e-12)
 
 
-def test_batch_replicas_match_oracle(lb, orc):
+@pytest.mark.parametrize("variant", [2, 3])
+def test_batch_replicas_match_oracle(lb, orc, variant):
     c, w, e, b = orc.tables()
-    reps, xs, vs = make_replicas(4, 64, 2, seed=5)
+    reps, xs, vs = make_replicas(4, 64, variant, seed=5)
     B = lb.Batch(reps)
     B.bind_particles(xs, vs)
     B.run_cycles(5)

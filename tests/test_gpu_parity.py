@@ -97,10 +97,10 @@ def test_random_state_rates_force(lb, orc, prec, shape):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_c1_coupled(lb, orc, prec, variant):
     """The plain-method case: 16^3, 32 particles, gamma = 1, n = 5, 100 LB
-    steps (500 MD steps), both variants."""
+    steps (500 MD steps), variants A, B and C."""
     cfg = wl.CONFIGS["c1"]
     x, v = wl.free_particles(cfg["shape"], cfg["n_particles"], cfg["kT"], 1.0, cfg["seed"])
     kw = dict(kT=cfg["kT"], nu=cfg["nu"], seed=1, n_particles=cfg["n_particles"],
@@ -123,10 +123,10 @@ def test_c1_coupled(lb, orc, prec, variant):
 @pytest.mark.parametrize("prec", [64, 32])
 def test_dense_particles_share_sites(lb, orc, prec):
     """Many particles per cube (the variant-2 read-before-write hazard and
-    atomic contention): 4^3 lattice, 300 particles, both variants."""
+    atomic contention): 4^3 lattice, 300 particles, all variants."""
     shape = (4, 4, 4)
     x, v = wl.free_particles(shape, 300, 1e-3, 1.0, 17)
-    for variant in (1, 2):
+    for variant in (1, 2, 3):
         kw = dict(kT=1e-3, seed=5, n_particles=300, friction=0.5, n_sub=4, variant=variant,
                   rho0=2.0)
         g, o, w, rho0 = run_pair(lb, orc, shape, 10, x=x, v=v, precision=prec, **kw)
@@ -150,10 +150,11 @@ def test_n1_variants_coincide(lb, orc):
     assert np.abs(res[0][1] - res[1][1]).max() < 1e-15
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_momentum_granularity_gpu(lb, variant):
-    """Sec. 3: variant 2 conserves fluid + particle momentum at every MD step,
-    variant 1 only at LB steps; FP64 reductions on the GPU, FP32 run."""
+    """Sec. 3: variants 2 and 3 conserve the momentum the coupling sees plus
+    the particles' at every MD step, variant 1 only at LB steps; FP64
+    reductions on the GPU, FP32 run."""
     shape = (24, 16, 8)
     N = 200
     x, v = wl.free_particles(shape, N, 1e-3, 1.0, 8)
@@ -174,7 +175,7 @@ def test_momentum_granularity_gpu(lb, variant):
         t = g.moments()
         assert np.abs(t[4:7] + t[7:10] - seen0).max() < 1e-6
         assert abs(t[0] - t0[0]) < 1e-6 * t0[0]
-    if variant == 2:
+    if variant >= 2:
         assert dev < 1e-6
     else:
         assert dev > 1e-4
@@ -185,8 +186,9 @@ def test_error_codes(lb):
     with pytest.raises(lb.LbmdError) as ei:
         lb.Lattice((16, 16, 16), n_sub=0)
     assert ei.value.code == lb.EINVAL
-    with pytest.raises(lb.LbmdError):
-        lb.Lattice((16, 16, 16), variant=3)
+    for bad in (0, 4):  # variants are 1 (A), 2 (B), 3 (C)
+        with pytest.raises(lb.LbmdError):
+            lb.Lattice((16, 16, 16), variant=bad)
     with pytest.raises(lb.LbmdError):
         lb.Lattice((1, 16, 16))
     g = lb.Lattice((8, 8, 8), n_sub=2, n_particles=4)
@@ -210,7 +212,7 @@ def test_error_codes(lb):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_polymer_forces_coupled(lb, orc, prec, variant):
     """Bead-spring chains (harmonic bonds + WCA through the GPU cell list)
     coupled to the fluid, against the oracle's all-pairs forces: 20^3 lattice,
@@ -252,17 +254,17 @@ def test_fast_particles_wrap(lb, orc):
     assert err < 1e-12, err
 
 
-@pytest.mark.parametrize("prec", [32, 64])
-def test_full_size_sampled_parity(lb, orc, prec):
+@pytest.mark.parametrize("prec,variant", [(32, 2), (64, 2), (32, 3)])
+def test_full_size_sampled_parity(lb, orc, prec, variant):
     """The 256^3 workload as bench.py times it (1e5 free particles, n = 10,
-    gamma = 10, kT = 1e-4, variant 2, default launch shapes): one coupled
-    cycle from the seeded start, every particle and 2048 random sites against
-    the FP64 oracle (which evaluates the sampled sites one by one)."""
+    gamma = 10, kT = 1e-4, variant 2 (and 3), default launch shapes): one
+    coupled cycle from the seeded start, every particle and 2048 random sites
+    against the FP64 oracle (which evaluates the sampled sites one by one)."""
     cfg = wl.CONFIGS["c3"]
     shape = cfg["shape"]
     x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
                              cfg["seed"])
-    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
+    kw = dict(n_sub=cfg["n_sub"], variant=variant, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
               friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
               particle_mass=cfg["particle_mass"])
     g = lb.Lattice(shape, precision=prec, **kw)
@@ -278,9 +280,59 @@ def test_full_size_sampled_parity(lb, orc, prec):
     c, w, e, b = orc.tables()
     dev = g.populations()[:, sites].double().cpu().numpy().T
     rel = np.abs(dev + w * cfg["rho0"] - ref) / (w * cfg["rho0"])
-    print(f"256^3 fp{prec} one cycle, sampled sites: max {rel.max():.3e}, "
+    print(f"256^3 fp{prec} variant {variant} one cycle, sampled sites: max {rel.max():.3e}, "
           f"rms {np.sqrt(np.mean(rel ** 2)):.3e}")
     assert rel.max() < TOL[prec]
     check_particles(g, o, shape, TOL[prec], cfg["kT"], cfg["particle_mass"])
     g.close()
     o.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_variant3_moments_and_site_update(lb, orc, prec):
+    """Variant C mid-interval: after each MD step the populations hold the
+    step's transfer (fluid momentum from the populations alone plus particle
+    momentum is conserved), and the state matches the oracle's."""
+    shape = (10, 8, 6)
+    x, v = wl.free_particles(shape, 40, 1e-3, 1.0, 21)
+    kw = dict(kT=1e-3, seed=4, n_particles=40, friction=1.5, n_sub=4, variant=3)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=prec, **kw)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    t0 = g.moments()
+    for _ in range(3):
+        g.md_couple_substep()
+        o.md_couple_substep()
+        t = g.moments()
+        p = t[1:4] + t[7:10]
+        assert np.abs(p - (t0[1:4] + t0[7:10])).max() < (1e-12 if prec == 64 else 1e-6)
+        err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+        assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_variant3_get_set_mid_interval(lb, prec):
+    """Variant C keeps the MD steps' increments beside the stored
+    populations: copying the populations out mid-interval and setting them
+    back must leave the run unchanged (up to rounding)."""
+    shape = (12, 10, 8)
+    x, v = wl.free_particles(shape, 60, 1e-3, 1.0, 5)
+    kw = dict(kT=1e-3, seed=6, n_particles=60, friction=2.0, n_sub=4, variant=3,
+              precision=prec)
+    runs = []
+    for roundtrip in (False, True):
+        g = lb.Lattice(shape, **kw)
+        g.bind_particles(x, v)
+        for s in range(8):
+            g.md_couple_substep()
+            if roundtrip and s % 4 == 1:
+                g.set_populations(g.populations().clone())
+            if s % 4 == 3:
+                g.lb_step()
+        runs.append((g.populations().double().cpu().numpy(), g.v.cpu().numpy()))
+        g.close()
+    tol = 1e-13 if prec == 64 else 2e-6
+    assert np.abs(runs[0][0] - runs[1][0]).max() < tol
+    assert np.abs(runs[0][1] - runs[1][1]).max() < tol * 10

@@ -230,10 +230,11 @@ def test_momentum_no_particles_and_body_force(orc):
         assert np.allclose(o2.moments()[1:4], t * g * 60, rtol=1e-12, atol=1e-16)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_momentum_granularity_by_variant(orc, variant):
-    """Sec. 3: variant B conserves fluid + particle momentum at every MD step;
-    variant A only at every LB step (the fluid velocity it sees is frozen)."""
+    """Sec. 3: variants B and C conserve fluid + particle momentum at every MD
+    step; variant A only at every LB step (the fluid velocity it sees is
+    frozen)."""
     o = make_c1_like(orc, variant, kT=1e-3)
     n = o.prm["n_sub"]
     tot = lambda t: t[1:4] + t[7:10]      # sum j + sum J + sum m v
@@ -250,7 +251,7 @@ def test_momentum_granularity_by_variant(orc, variant):
         o.lb_step()
         t = o.moments()
         assert np.abs(seen(t) - seen(t0)).max() < 1e-12
-    if variant == 2:
+    if variant >= 2:
         assert seen_dev < 1e-12
     else:
         assert seen_dev > 1e-6
@@ -523,3 +524,66 @@ def test_wrap_any_displacement(orc):
     L = np.array([[4.0], [5.0], [6.0]])
     assert (x >= 0).all() and (x < L).all()
     assert np.allclose(x + L * img, x0 + 0.5 * v0, rtol=0, atol=1e-12)
+
+
+def test_variant_c_velocities_equal_variant_b_within_an_interval(orc):
+    """Variant C (Sec. 3) applies each MD step's transfer to the populations;
+    the momentum part of that update is the transfer itself, so until the
+    next LB step the particles read exactly the velocities (j + J)/rho of
+    variant B.  The LB step then differs at second order in the transfers."""
+    b = make_c1_like(orc, 2, kT=1e-3)
+    c = make_c1_like(orc, 3, kT=1e-3)
+    for _ in range(b.prm["n_sub"]):
+        assert b.md_couple_substep() == 0
+        assert c.md_couple_substep() == 0
+        for u, v in zip(b.particles()[:2], c.particles()[:2]):
+            assert np.abs(u - v).max() < 1e-13
+    Jmax = np.abs(b.J()).max()          # the interval's transfer per site
+    b.lb_step()
+    c.lb_step()
+    diff = np.abs(b.populations() - c.populations()).max()
+    assert 0.0 < diff < Jmax ** 2       # second order in the transfer
+    # mass and total momentum agree after the LB step as well
+    tb, tc = b.moments(), c.moments()
+    assert abs(tb[0] - tc[0]) < 1e-12 * tb[0]
+    assert np.abs((tb[1:4] + tb[7:10]) - (tc[1:4] + tc[7:10])).max() < 1e-13
+
+
+def _one_variant_c_step(orc, v0, nu):
+    """One MD step of a single particle in a fluid at rest, variant C, no
+    noise; returns (population change, particle momentum change)."""
+    shape = (5, 4, 6)
+    o = orc.Oracle(*shape, n_sub=5, variant=3, kT=0.0, friction=2.0, nu=nu, nu_bulk=-1.0,
+                   n_particles=1, seed=3)
+    x = np.array([[2.3], [1.6], [3.8]])
+    v = np.asarray(v0, float).reshape(3, 1)
+    o.set_particles(x, v)
+    f0 = o.populations()
+    assert o.md_couple_substep() == 0
+    return o.populations() - f0, (o.particles()[1] - v)[:, 0]
+
+
+def test_variant_c_update_moves_only_momentum_and_stress(orc):
+    """The variant-C update of one MD step leaves the mass and the kinetic
+    modes of every site unchanged, moves exactly the particle's momentum loss
+    into the fluid (Eq. 7-8), and its stress part is second order in the
+    transfer on a fluid at rest (quadratic) and carries the factor
+    (1 + gamma_s)/2 of the forcing term."""
+    c, w, e, b = orc.tables()
+    v0 = np.array([0.02, -0.01, 0.015])
+    df, dv = _one_variant_c_step(orc, v0, 1.0 / 6.0)
+    modes = e @ df                      # [19, S]
+    assert np.abs(modes[0]).max() < 1e-15
+    assert np.abs(modes[10:]).max() < 1e-15
+    assert np.abs(modes[1:4].sum(1) + dv).max() < 1e-15   # particle mass 1
+    # quadratic in the transfer: doubling the velocity doubles dP
+    df2, dv2 = _one_variant_c_step(orc, 2 * v0, 1.0 / 6.0)
+    assert np.allclose(dv2, 2 * dv, rtol=1e-13, atol=0)
+    s1, s2 = (e @ df)[4:10], (e @ df2)[4:10]
+    big = np.abs(s1) > 1e-3 * np.abs(s1).max()
+    assert np.allclose(s2[big] / s1[big], 4.0, rtol=1e-9)
+    # the forcing factor: gamma_s = 0 at nu = 1/6, gamma_s = 1/2 at nu = 1/2
+    df3, dv3 = _one_variant_c_step(orc, v0, 0.5)
+    assert np.allclose(dv3, dv, rtol=1e-14, atol=0)
+    s3 = (e @ df3)[4:10]
+    assert np.allclose(s3[big] / s1[big], 1.5, rtol=1e-9)
