@@ -133,10 +133,12 @@ int lbmd_bind_particles(lbmd *c, void *d_x, void *d_v, int32_t *d_img);
  * variant 1 only by the next lb_step(); in variant 3 it changes the
  * state of the receiving sites before the next MD step (momentum + dJ,
  * stress modes + (1+gamma)/2 times the image of u dJ + dJ u with
- * u = (j + dJ/2)/rho; the library keeps these increments per site and adds
- * them to the stored populations at the next lb_step(), which is the same
- * state in exact arithmetic).  At most n_sub calls per LB interval
- * (LBMD_ESTATE otherwise).
+ * u = (j + dJ/2)/rho).  Summed over an interval these increments depend
+ * only on the interval-start momentum j0, the density and the total
+ * transfer J (stress: the image of (j0 J + J j0 + J J)/rho), so the library
+ * accumulates J as in variant 2 and adds the increments where the state is
+ * read (lb_step(), population copies, moments).  At most n_sub calls per LB
+ * interval (LBMD_ESTATE otherwise).
  */
 int md_couple_substep(lbmd *c);
 

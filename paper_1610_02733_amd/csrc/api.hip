@@ -96,10 +96,6 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.pop[0] = o; o = up(o + 19 * S * t);
   L.pop[1] = o; o = up(o + 19 * S * t);
   L.transfer = o; o = up(o + 4 * S * t);
-  const size_t S3 = p[0].variant == 3 ? S : 0;  // variant-3 per-site fields
-  L.jstep = o; o = up(o + 4 * S3 * t);
-  L.vc_stress = o; o = up(o + 8 * S3 * t);
-  L.vc_moments = o; o = up(o + 4 * S3 * t);
   L.mark = o; o = up(o + (S / 64) * 8);
   L.rep_lb = o; o = up(o + (size_t)R * (pl.prec == 32 ? sizeof(RepLB<float>) : sizeof(RepLB<double>)));
   L.rep_md = o; o = up(o + (size_t)R * sizeof(RepMD));
@@ -502,15 +498,12 @@ int lbmd_batch_set_populations(lbmd* c, int32_t rep, const void* d_src) {
   rc = fail(c, launch_set_populations(c, rep, d_src));
   if (rc) return rc;
   if (c->p[0].variant == 3) {
-    // the increments received in the current interval are part of the
+    // the transfer received in the current interval is part of the
     // variant-3 state that the new populations replace
     const size_t t = c->plan.prec == 32 ? 4 : 8, off = (size_t)c->plan.site_off[rep];
     const size_t n = (size_t)c->p[rep].nx * c->p[rep].ny * c->p[rep].nz;
     rc = fail(c, hipMemsetAsync((char*)at(c, c->plan.lay.transfer) + off * 4 * t, 0, n * 4 * t,
                                 c->stream));
-    if (!rc)
-      rc = fail(c, hipMemsetAsync((char*)at(c, c->plan.lay.vc_stress) + off * 8 * t, 0,
-                                  n * 8 * t, c->stream));
     if (rc) return rc;
   }
   return fail(c, invalidate_corner_cache(c));
@@ -626,10 +619,6 @@ int load_common(lbmd* c, const char* src, const StateLayout& sl) {
   if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.mark), 0, (S / 64) * 8, c->stream));
   if (!rc)
     rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.shared_site), 0, (S / 64) * 8, c->stream));
-  if (!rc && c->p[0].variant == 3) {
-    rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.jstep), 0, S * 4 * t, c->stream));
-    if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.vc_stress), 0, S * 8 * t, c->stream));
-  }
   if (rc) return rc;
   c->t_lb = cnt[0];
   c->t_md = cnt[1];

@@ -5,7 +5,6 @@
 // reads its replica's constants.
 #include <algorithm>
 
-#include "forcing.hpp"
 #include "particle_geom.hpp"
 
 namespace lbmd_impl {
@@ -30,11 +29,6 @@ struct CoupleArgs {
   int32_t* __restrict__ cc_cell;
   int32_t* __restrict__ cc_stamp;
   unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
-  Vec4<T>* __restrict__ spread_dst;  // where a variant-2 transfer goes (J)
-  Vec4<T>* __restrict__ jstep;       // variant 3: step transfer at shared sites
-  Stress8<T>* __restrict__ S;        // variant 3: stress increments of the interval
-  Vec4<T>* __restrict__ vcm;         // variant 3: (j, 1/rho) of shared sites
-  const RepLB<T>* __restrict__ rep_lb;  // per-replica LB constants (variant-3 updates)
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
@@ -148,16 +142,18 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
 //
 // Each lane fetches its corner's cached moments (a particle that left its
 // cube since the refill gathers the new corners itself, one corner per lane)
-// and, in variant 2, the corner's pending transfer; the interpolated fluid
+// and, in variants 2 and 3, the corner's pending transfer; the interpolated fluid
 // velocity (Eq. 5) is the sum over the eight lanes (butterfly shuffles, the
 // same order on every lane).  Friction + noise (Eq. 4, 6) and velocity
 // Verlet are evaluated on all eight lanes alike; lane 0 stores the particle.
 // Variant 1 then transfers the momentum right away (Eq. 7-8): the 24
 // (corner, component) adds of a particle are spread over its 8 lanes in
 // three rounds, so the lanes of one atomic instruction share a few sites
-// rather than touching 64 unrelated cache lines.  Variant 2 stores (cube,
-// dP) for the spreading kernel instead, because every particle must first
-// read the velocities as of the end of the previous MD step.
+// rather than touching 64 unrelated cache lines.  Variants 2 and 3 store
+// (cube, dP) for the spreading kernel instead, because every particle must
+// first read the velocities as of the end of the previous MD step (variant 3
+// sees the same velocities as variant 2 inside an interval; its transfer
+// differs only in how the LB step applies it).
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
@@ -329,73 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
       q.s[d] = a.rec_frac[d * N + p];
       dp[d] = a.rec_dp[d * N + p];
     }
-    spread_corner<T>(a.spread_dst, a.shared_site, m, q, k, dp);
-  }
-}
-
-// Variant 3 (the paper's variant C): the MD step's transfer, eight lanes per
-// particle.  A site that takes momentum dJ in an MD step changes its state
-// through the forcing part of the collision alone: momentum + dJ, stress
-// modes + (1+gamma)/2 q(u, dJ) with u = (j + J + dJ/2)/rho (j, rho: the
-// site's moments at the start of the interval, in the lane's corner cache;
-// J: what the site received since).  These increments are kept per site
-// (J, S) until the LB step puts them into the populations; j + J is already
-// what the particles read in every MD step.  At a site claimed once in the
-// interval the lane is the only writer and updates J and S itself; shared
-// sites sum the step's transfer in the step field and leave the site's
-// (j, 1/rho) for k_site_update (every writer stores the same moments).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spread_update(CoupleArgs<T> a) {
-  const int64_t N = a.N;
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kCornerLanes;
-       t += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = t / kCornerLanes;
-    const int k = (int)(t & (kCornerLanes - 1));
-    Cube q;
-    q.base[0] = a.rec_cell[p];
-    if (q.base[0] < 0) continue;
-    const int rr = a.single ? 0 : a.part_rep[p];
-    const RepMD& m = a.md[rr];
-    q.base[1] = a.rec_cell[N + p];
-    q.base[2] = a.rec_cell[2 * N + p];
-    double dp[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      q.s[d] = a.rec_frac[d * N + p];
-      dp[d] = a.rec_dp[d * N + p];
-    }
-    int cx, cy, cz, site;
-    double w;
-    corner_of(q, m.g, k, cx, cy, cz, site, w);
-    const int gs = m.site_off + site;
-    const T ax = (T)(-w * dp[0]), ay = (T)(-w * dp[1]), az = (T)(-w * dp[2]);
-    // the couple kernel of this step left the moments of the cube it used
-    // (rec_cell) in the corner cache
-    const Vec4<T> cv = *cache_entry(a, p, k);
-    if ((a.shared_site[gs >> 6] >> (gs & 63)) & 1ull) {
-      T* dst = (T*)(a.jstep + gs);
-      atomicAdd(dst + 0, ax);
-      atomicAdd(dst + 1, ay);
-      atomicAdd(dst + 2, az);
-      a.vcm[gs] = cv;
-      continue;
-    }
-    const CollideConsts<T>& kc = a.rep_lb[rr].k;
-    Vec4<T> jv = a.J[gs];
-    T sm[6];
-    stress_increment<T>(cv.x, cv.y, cv.z, cv.w, jv.x, jv.y, jv.z, ax, ay, az, kc.hb, kc.hs, sm);
-    Stress8<T> sv = a.S[gs];
-    sv.a.x += sm[0];
-    sv.a.y += sm[1];
-    sv.a.z += sm[2];
-    sv.a.w += sm[3];
-    sv.b.x += sm[4];
-    sv.b.y += sm[5];
-    a.S[gs] = sv;
-    jv.x += ax;
-    jv.y += ay;
-    jv.z += az;
-    a.J[gs] = jv;
+    spread_corner<T>(a.J, a.shared_site, m, q, k, dp);
   }
 }
 
@@ -419,11 +349,6 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.cc_cell = (int32_t*)at(c, L.cc_cell);
   a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
   a.shared_site = (unsigned long long*)at(c, L.shared_site);
-  a.spread_dst = (Vec4<T>*)at(c, L.transfer);
-  a.jstep = (Vec4<T>*)at(c, L.jstep);
-  a.S = (Stress8<T>*)at(c, L.vc_stress);
-  a.vcm = (Vec4<T>*)at(c, L.vc_moments);
-  a.rep_lb = (const RepLB<T>*)at(c, L.rep_lb);
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
@@ -458,20 +383,12 @@ static hipError_t couple_t(Context* c, int substep) {
     hipLaunchKernelGGL((k_couple<T, true>), cgrid, dim3(kBlock), 0, c->stream, a);
   else
     hipLaunchKernelGGL((k_couple<T, false>), cgrid, dim3(kBlock), 0, c->stream, a);
-  // variant 2: the transfer waits until every particle has read J; with
-  // position-dependent forces it runs inside the force kernel.  Variant 3:
-  // the same wait, then the per-site updates (single-claimer sites in the
-  // spreading kernel, shared ones after it).
-  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1) return e;
-  if (a.variant == 2 && c->plan.any_forces2) return e;
+  // variants 2 and 3: the transfer waits until every particle has read J;
+  // with position-dependent forces it runs inside the force kernel
+  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1 || c->plan.any_forces2) return e;
   const dim3 sgrid(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
-  if (a.variant == 2) {
-    hipLaunchKernelGGL(k_spread<T>, sgrid, dim3(kBlock), 0, c->stream, a);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_spread_update<T>, sgrid, dim3(kBlock), 0, c->stream, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_site_update(c);
+  hipLaunchKernelGGL(k_spread<T>, sgrid, dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_couple(Context* c, int substep) {

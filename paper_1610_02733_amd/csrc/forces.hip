@@ -133,9 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
 // stores the force and, after an MD step, applies the second half-kick of
 // velocity Verlet (new conservative force + the coupling force held over the
-// step).  In variant 2 lanes 0-7 also transfer the step's momentum to the 8
-// cube corners (the spreading of k_spread): this kernel runs after every
-// particle of the step has read the transfer field.
+// step).  In variants 2 and 3 lanes 0-7 also transfer the step's momentum to
+// the 8 cube corners (the spreading of k_spread): this kernel runs after
+// every particle of the step has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -162,7 +162,7 @@ struct ForceArgs {
   const int32_t* __restrict__ start;
   const int32_t* __restrict__ tiles;
   const int32_t* __restrict__ sorted;
-  // variant-2 transfer of the MD step
+  // variant-2/3 transfer of the MD step
   const int32_t* __restrict__ rec_cell;
   const double* __restrict__ rec_frac;
   const double* __restrict__ rec_dp;
@@ -363,14 +363,14 @@ hipError_t launch_init_forces(Context* c) {
 }
 
 // After an MD step of replicas with position-dependent forces: binning,
-// forces at the new positions, the second half-kick and, in variant 2, the
-// step's momentum transfer (so the coupling step launches no spreading
-// kernel of its own).
+// forces at the new positions, the second half-kick and, in variants 2 and
+// 3, the step's momentum transfer (so the coupling step launches no
+// spreading kernel of its own).
 hipError_t launch_forces_and_kick(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e = launch_binning(c);
   if (e != hipSuccess) return e;
-  const bool v2 = c->p[0].variant == 2;
+  const bool v2 = c->p[0].variant >= 2;
   if (c->plan.prec == 32)
     return v2 ? forces_t<float, true, true>(c) : forces_t<float, true, false>(c);
   return v2 ? forces_t<double, true, true>(c) : forces_t<double, true, false>(c);

@@ -1,17 +1,19 @@
-// The forcing part of the collision operator on its own: the paper's variant
-// C update of a site after an MD step (Sec. 3).  A site that receives the
-// momentum dJ in an MD step, with current momentum j and density rho, takes
-//   dm_{1,2,3} = dJ,   dm_k = (1 + gamma_k)/2 q_k(u, dJ)  (stress modes 4..9),
-// u = (j + dJ/2) / rho, mass and kinetic modes unchanged; q_k are the mode
-// images of u dJ + dJ u (the Guo source of the LB step).
+// The paper's variant C (Sec. 3) in closed form.
 //
-// Nothing reads a site's populations inside an LB interval except through
-// rho and j (the particles' interpolation and the next update's u), so the
-// library keeps the increments per site -- the momentum in the transfer field
-// J, the six stress-mode increments in a stress field -- and adds them to the
-// pulled populations when the LB step (or a copy of the state) reads the
-// site.  In exact arithmetic this is the same as changing the populations at
-// every MD step.
+// In variant C every MD step k puts its transfer dJ_k into the populations
+// of each receiving site through the forcing part of the collision alone:
+// momentum + dJ_k, stress modes + (1 + gamma)/2 times the mode image of
+// u_k dJ_k + dJ_k u_k with u_k = (j_k + dJ_k/2)/rho, mass and kinetic modes
+// unchanged.  With j_k = j0 + J_k (J_k: what the site received before step
+// k; rho does not change) the stress sources of an interval telescope:
+//   sum_k (u_k dJ_k + dJ_k u_k) = (j0 J + J j0 + J J) / rho,
+// J = sum_k dJ_k, because (J_k + dJ_k/2) dJ_k + dJ_k (J_k + dJ_k/2)
+// = J_{k+1} J_{k+1} - J_k J_k.  The state after the interval's MD steps is
+// therefore a function of the interval-start populations and the total
+// transfer J alone, and the velocity (j0 + J)/rho the particles read inside
+// the interval is the one variant B reads.  The library accumulates J as in
+// variant B and applies these increments where the state is read: in the
+// collide-stream kernel and in population copies.
 #pragma once
 
 #include "lbmd_device.hpp"
@@ -19,23 +21,24 @@
 namespace lbmd_impl {
 using namespace lbmd_dev;
 
-// Stress-mode increments (mode units, k = 4..9) of one variant-C update:
-// j0 and irho are the site's momentum and inverse density at the start of
-// the LB interval, J the momentum it received earlier in the interval, dJ
-// the transfer of this MD step.
+// Stress-mode increments s[0..5] (modes 4..9, mode units) of an interval
+// that moved the momentum J into a site with interval-start momentum j0 and
+// inverse density irho.
 template <typename T>
-__device__ __forceinline__ void stress_increment(T j0x, T j0y, T j0z, T irho, T Jx, T Jy, T Jz,
-                                                 T dx, T dy, T dz, T hb, T hs, T s[6]) {
-  const T ux = (j0x + Jx + T(0.5) * dx) * irho;
-  const T uy = (j0y + Jy + T(0.5) * dy) * irho;
-  const T uz = (j0z + Jz + T(0.5) * dz) * irho;
-  const T fx = ux * dx, fy = uy * dy, fz = uz * dz;
-  s[0] = hb * T(2) * (fx + fy + fz);
-  s[1] = hs * T(2) * (T(2) * fx - fy - fz);
-  s[2] = hs * T(2) * (fy - fz);
-  s[3] = hs * (ux * dy + uy * dx);
-  s[4] = hs * (uy * dz + uz * dy);
-  s[5] = hs * (ux * dz + uz * dx);
+__device__ __forceinline__ void varc_stress(T j0x, T j0y, T j0z, T irho, T Jx, T Jy, T Jz, T hb,
+                                            T hs, T s[6]) {
+  const T qxx = (T(2) * j0x + Jx) * Jx * irho;
+  const T qyy = (T(2) * j0y + Jy) * Jy * irho;
+  const T qzz = (T(2) * j0z + Jz) * Jz * irho;
+  const T qxy = (j0x * Jy + Jx * j0y + Jx * Jy) * irho;
+  const T qyz = (j0y * Jz + Jy * j0z + Jy * Jz) * irho;
+  const T qxz = (j0x * Jz + Jx * j0z + Jx * Jz) * irho;
+  s[0] = hb * (qxx + qyy + qzz);
+  s[1] = hs * (T(2) * qxx - qyy - qzz);
+  s[2] = hs * (qyy - qzz);
+  s[3] = hs * qxy;
+  s[4] = hs * qyz;
+  s[5] = hs * qxz;
 }
 
 // Population-deviation increments dd_i = w_i sum_k e_k(c_i) dm_k / b_k for
@@ -69,11 +72,5 @@ __device__ __forceinline__ void mode_increments_to_pops(T Jx, T Jy, T Jz, const 
   dd[17] = (Dyz - M8 + M2 - M3) * w2;
   dd[18] = (Dyz - M8 - M2 + M3) * w2;
 }
-
-// Stress accumulator of a site: (s4, s5, s6, s7) and (s8, s9, -, -).
-template <typename T>
-struct Stress8 {
-  Vec4<T> a, b;
-};
 
 }  // namespace lbmd_impl

@@ -35,9 +35,9 @@ __device__ __forceinline__ int replica_of_item(const int32_t* __restrict__ item_
 // (coalesced).  J is only read where the site's bit in `mark` is set (the
 // coupling sets it when it transfers momentum there), and is cleared with it,
 // so the untouched bulk of the lattice costs no transfer traffic.  In
-// variant 3 (VarC) the interval's transfers already belong to the state: the
-// thread adds their mode increments (momentum J, stress S) to the pulled
-// populations and collides with the body force alone.  A work
+// variant 3 (VarC) the interval's transfer already belongs to the state: the
+// collision adds it as the momentum and stress increments of the paper's
+// variant C and relaxes with the body force alone.  A work
 // item is 256 consecutive sites of one replica; replica offsets are
 // multiples of 64, so one wavefront owns exactly one 64-bit mark word.
 // Persistent grid: blocks stride over the items.
@@ -51,9 +51,6 @@ struct StreamArgs {
   const RepLB<T>* __restrict__ rep;
   const int32_t* __restrict__ item_off;
   const Clock* __restrict__ clock;
-  Vec4<T>* __restrict__ jstep;                // variant 3: step transfer at shared sites
-  Stress8<T>* __restrict__ S;                 // variant 3: stress increments of the interval
-  const Vec4<T>* __restrict__ vcm;            // variant 3: (j, 1/rho) of shared sites
   Vec4<T>* __restrict__ jrec;                 // recording: J consumed at marked sites
   unsigned long long* __restrict__ mrec;      // recording: mark words
   size_t P;  // population stride (padded total sites)
@@ -91,16 +88,13 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
     for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(sbase + (size_t)i * a.P + sidx[i]);
 
     T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
+    T Jx = T(0), Jy = T(0), Jz = T(0);
     if ((word >> (gsite & 63)) & 1ull) {
       const Vec4<T> jv = a.J[gsite];
       if (VarC) {
-        const Stress8<T> sv = a.S[gsite];
-        const T sm[6] = {sv.a.x, sv.a.y, sv.a.z, sv.a.w, sv.b.x, sv.b.y};
-        T dd[19];
-        mode_increments_to_pops<T>(jv.x, jv.y, jv.z, sm, dd);
-#pragma unroll
-        for (int i = 0; i < 19; ++i) d[i] += dd[i];
-        a.S[gsite] = Stress8<T>{};
+        Jx = jv.x;
+        Jy = jv.y;
+        Jz = jv.z;
       } else {
         Fx += jv.x;
         Fy += jv.y;
@@ -117,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
       hw[0] = o0.w0; hw[1] = o0.w1; hw[2] = o0.w2; hw[3] = o0.w3;
       hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
     }
-    collide_deviation<T>(d, Fx, Fy, Fz, hw, q.k);
+    collide_deviation<T, VarC>(d, Fx, Fy, Fz, hw, q.k, Jx, Jy, Jz);
     // every population is written once per step: stream the stores past the
     // caches (non-temporal hint)
 #pragma unroll
@@ -135,9 +129,6 @@ static StreamArgs<T> stream_args(Context* c) {
   a.pop[0] = (T*)c->popv[0];
   a.pop[1] = (T*)c->popv[1];
   a.J = (Vec4<T>*)at(c, c->plan.lay.transfer);
-  a.jstep = (Vec4<T>*)at(c, c->plan.lay.jstep);
-  a.S = (Stress8<T>*)at(c, c->plan.lay.vc_stress);
-  a.vcm = (const Vec4<T>*)at(c, c->plan.lay.vc_moments);
   a.jrec = (Vec4<T>*)c->rec_J;
   a.mrec = c->rec_mark;
   a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
@@ -170,82 +161,6 @@ static hipError_t collide_stream_t(Context* c) {
 
 hipError_t launch_collide_stream(Context* c) {
   return c->plan.prec == 32 ? collide_stream_t<float>(c) : collide_stream_t<double>(c);
-}
-
-// ---------------------------------------------------------------------------
-// Variant 3 (the paper's variant C), sites shared by several particles.
-// After every MD step each receiving site takes the step's transfer dJ into
-// its state through the forcing part of the collision alone (no relaxation,
-// no noise, no streaming): momentum +dJ, stress modes + (1+gamma)/2 q(u, dJ)
-// with u = (j + J + dJ/2)/rho, where j, rho are the site's moments at the
-// start of the interval and J the momentum it received since.  The library
-// keeps these increments per site (J and S) until the LB step adds them to
-// the populations.  A site claimed by a single particle in the interval is
-// updated by that particle's spreading lane; this kernel does the sites
-// flagged as shared, whose step transfer was summed in the step field and
-// whose start-of-interval (j, 1/rho) the spreading lanes stored.  One thread
-// per 64-site word of the shared bitmap.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ int replica_of_site(const RepLB<T>* __restrict__ rep, int R, int gs) {
-  int lo = 0, hi = R;  // rep[lo].site_off <= gs < rep[hi].site_off
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rep[mid].site_off <= gs)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_site_update(StreamArgs<T> a, int64_t nwords) {
-  for (int64_t wd = (int64_t)blockIdx.x * kBlock + threadIdx.x; wd < nwords;
-       wd += (int64_t)gridDim.x * kBlock) {
-    unsigned long long word = a.shared_site[wd];
-    if (!word) continue;
-    const int gs0 = (int)(wd * 64);
-    const RepLB<T>& q = a.rep[a.R == 1 ? 0 : replica_of_site(a.rep, a.R, gs0)];
-    while (word) {
-      const int b = __builtin_ctzll(word);
-      word &= word - 1ull;
-      const int gsite = gs0 + b;
-      const Vec4<T> dJ = a.jstep[gsite];
-      if (dJ.x == T(0) && dJ.y == T(0) && dJ.z == T(0)) continue;
-      const Vec4<T> m0 = a.vcm[gsite];
-      Vec4<T> jv = a.J[gsite];
-      T sm[6];
-      stress_increment<T>(m0.x, m0.y, m0.z, m0.w, jv.x, jv.y, jv.z, dJ.x, dJ.y, dJ.z, q.k.hb,
-                          q.k.hs, sm);
-      Stress8<T> sv = a.S[gsite];
-      sv.a.x += sm[0];
-      sv.a.y += sm[1];
-      sv.a.z += sm[2];
-      sv.a.w += sm[3];
-      sv.b.x += sm[4];
-      sv.b.y += sm[5];
-      a.S[gsite] = sv;
-      jv.x += dJ.x;
-      jv.y += dJ.y;
-      jv.z += dJ.z;
-      a.J[gsite] = jv;
-      a.jstep[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
-    }
-  }
-}
-
-template <typename T>
-static hipError_t site_update_t(Context* c) {
-  StreamArgs<T> a = stream_args<T>(c);
-  const int64_t nwords = c->plan.Stot / 64;
-  const int blocks = (int)std::max<int64_t>(1, (nwords + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_site_update<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a, nwords);
-  return hipGetLastError();
-}
-
-hipError_t launch_site_update(Context* c) {
-  return c->plan.prec == 32 ? site_update_t<float>(c) : site_update_t<double>(c);
 }
 
 // End of an LB step: advance the device clock (graph-capturable).
@@ -392,39 +307,43 @@ hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d
 // Copies between pull storage and the plain post-stream layout of one
 // replica ([19][S] and [3][S] arrays in the run precision).
 // ---------------------------------------------------------------------------
-// Variant 3 (pend != nullptr): a copy out adds the increments the site has
-// received in the current interval (J, S at marked sites), so that it shows
-// the populations as the paper's variant C holds them after each MD step.
+// Variant 3 (pend != nullptr): a copy out adds the increments of the
+// transfer the site has received in the current interval (J at marked
+// sites), so that it shows the populations as the paper's variant C holds
+// them after each MD step.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy_pop(T* __restrict__ pop, size_t P, int site_off,
                                                      Geom g, T* __restrict__ plain, int to_plain,
-                                                     const Vec4<T>* __restrict__ pend_J,
-                                                     const Stress8<T>* __restrict__ pend_S,
-                                                     const unsigned long long* __restrict__ mark) {
+                                                     const Vec4<T>* __restrict__ pend,
+                                                     const unsigned long long* __restrict__ mark,
+                                                     const RepLB<T>* __restrict__ rep, int rr) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= g.S) return;
   int x, y, z, sidx[19];
   site_coords(g, r, x, y, z);
   pull_sources(g, x, y, z, sidx);
   const size_t S = (size_t)g.S;
-  T dd[19];
+  if (!to_plain) {
 #pragma unroll
-  for (int i = 0; i < 19; ++i) dd[i] = T(0);
+    for (int i = 0; i < 19; ++i) pop[(size_t)i * P + site_off + sidx[i]] = plain[(size_t)i * S + r];
+    return;
+  }
+  T d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
   const int gs = site_off + r;
-  if (to_plain && pend_J && ((mark[gs >> 6] >> (gs & 63)) & 1ull)) {
-    const Vec4<T> jv = pend_J[gs];
-    const Stress8<T> sv = pend_S[gs];
-    const T sm[6] = {sv.a.x, sv.a.y, sv.a.z, sv.a.w, sv.b.x, sv.b.y};
+  if (pend && ((mark[gs >> 6] >> (gs & 63)) & 1ull)) {
+    const Vec4<T> jv = pend[gs];
+    const CollideConsts<T>& k = rep[rr].k;
+    T drho, jx, jy, jz, sm[6], dd[19];
+    moments_deviation<T>(d, drho, jx, jy, jz);
+    varc_stress<T>(jx, jy, jz, T(1) / (k.rho0 + drho), jv.x, jv.y, jv.z, k.hb, k.hs, sm);
     mode_increments_to_pops<T>(jv.x, jv.y, jv.z, sm, dd);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] += dd[i];
   }
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    T* q = pop + (size_t)i * P + site_off + sidx[i];
-    if (to_plain)
-      plain[(size_t)i * S + r] = *q + dd[i];
-    else
-      *q = plain[(size_t)i * S + r];
-  }
+  for (int i = 0; i < 19; ++i) plain[(size_t)i * S + r] = d[i];
 }
 
 template <typename T>
@@ -460,8 +379,8 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
   hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
                      (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0,
                      pend ? (const Vec4<T>*)at(c, c->plan.lay.transfer) : nullptr,
-                     pend ? (const Stress8<T>*)at(c, c->plan.lay.vc_stress) : nullptr,
-                     (const unsigned long long*)at(c, c->plan.lay.mark));
+                     (const unsigned long long*)at(c, c->plan.lay.mark),
+                     (const RepLB<T>*)at(c, c->plan.lay.rep_lb), rep);
   return hipGetLastError();
 }
 

@@ -88,10 +88,18 @@ struct CollideConsts {
 // opposite populations.  Equilibrium stress moments are the images of
 // rho c_s^2 I + rho u u with u = (j + F/2)/rho; the kinetic modes have zero
 // equilibrium; the Guo source adds (1+g)/2 times the image of u F + F u.
-template <typename T>
+//
+// VarC: the site also holds the momentum J that the MD steps of the interval
+// moved into it in the paper's variant C.  Its state is then the pulled one
+// plus momentum J and the stress increments (1+g)/2 times the image of
+// (j J + J j + J J)/rho (j: the pulled momentum), which are added in mode
+// space before the relaxation (F then carries the body force alone).
+template <typename T, bool VarC = false>
 __host__ __device__ __forceinline__ void collide_deviation(T d[19], T Fx, T Fy, T Fz,
                                                            const uint32_t hw[8],
-                                                           const CollideConsts<T>& k) {
+                                                           const CollideConsts<T>& k,
+                                                           T Jx = T(0), T Jy = T(0),
+                                                           T Jz = T(0)) {
   const T s12 = d[1] + d[2], a12 = d[1] - d[2];
   const T s34 = d[3] + d[4], a34 = d[3] - d[4];
   const T s56 = d[5] + d[6], a56 = d[5] - d[6];
@@ -106,22 +114,45 @@ __host__ __device__ __forceinline__ void collide_deviation(T d[19], T Fx, T Fy, 
   const T saxis = s12 + s34 + s56;
 
   const T drho = d[0] + saxis + sdiag;
-  const T jx = a12 + a78 + a9a + abc + ade;
-  const T jy = a34 + a78 - a9a + afg + ahi;
-  const T jz = a56 + abc - ade + afg - ahi;
+  T jx = a12 + a78 + a9a + abc + ade;
+  T jy = a34 + a78 - a9a + afg + ahi;
+  T jz = a56 + abc - ade + afg - ahi;
   const T rho = k.rho0 + drho;
   const T irho = T(1) / rho;
+  T i4 = T(0), i5 = T(0), i6 = T(0), i7 = T(0), i8 = T(0), i9 = T(0);
+  if (VarC) {
+    const T qxx = (T(2) * jx + Jx) * Jx * irho;
+    const T qyy = (T(2) * jy + Jy) * Jy * irho;
+    const T qzz = (T(2) * jz + Jz) * Jz * irho;
+    i4 = k.hb * (qxx + qyy + qzz);
+    i5 = k.hs * (T(2) * qxx - qyy - qzz);
+    i6 = k.hs * (qyy - qzz);
+    i7 = k.hs * (jx * Jy + Jx * jy + Jx * Jy) * irho;
+    i8 = k.hs * (jy * Jz + Jy * jz + Jy * Jz) * irho;
+    i9 = k.hs * (jx * Jz + Jx * jz + Jx * Jz) * irho;
+    jx += Jx;
+    jy += Jy;
+    jz += Jz;
+  }
   const T ux = (jx + T(0.5) * Fx) * irho;
   const T uy = (jy + T(0.5) * Fy) * irho;
   const T uz = (jz + T(0.5) * Fz) * irho;
 
   // stress modes
-  const T m4 = sdiag - d[0];
-  const T m5 = T(2) * s12 - s34 - s56 + sxy + sxz - T(2) * syz;
-  const T m6 = s34 - s56 + sxy - sxz;
-  const T m7 = s78 - s9a;
-  const T m8 = sfg - shi;
-  const T m9 = sbc - sde;
+  T m4 = sdiag - d[0];
+  T m5 = T(2) * s12 - s34 - s56 + sxy + sxz - T(2) * syz;
+  T m6 = s34 - s56 + sxy - sxz;
+  T m7 = s78 - s9a;
+  T m8 = sfg - shi;
+  T m9 = sbc - sde;
+  if (VarC) {
+    m4 += i4;
+    m5 += i5;
+    m6 += i6;
+    m7 += i7;
+    m8 += i8;
+    m9 += i9;
+  }
   // kinetic modes
   const T m10 = a78 + a9a + abc + ade - T(2) * a12;
   const T m11 = a78 - a9a + afg + ahi - T(2) * a34;

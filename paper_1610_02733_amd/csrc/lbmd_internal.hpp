@@ -63,9 +63,6 @@ struct Clock {
 struct Layout {
   size_t pop[2];     // [19][Stot] population deviations, pull storage
   size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z, unused)
-  size_t jstep;      // [Stot] Vec4<T>: transfer of the current MD step at shared sites (variant 3)
-  size_t vc_stress;  // [Stot][8] T: variant-3 stress-mode increments of the interval
-  size_t vc_moments; // [Stot] Vec4<T>: (j, 1/rho) at the interval start (variant-3 shared sites)
   size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
   size_t rep_lb;     // [R] RepLB<T>
   size_t rep_md;     // [R] RepMD
@@ -185,7 +182,6 @@ hipError_t launch_couple_adjoint(Context* c);
 hipError_t launch_adjoint_fold(Context* c);
 hipError_t launch_store_counters(Context* c, void* dst, int64_t t_lb, int64_t t_md);
 hipError_t launch_clock_advance(Context* c);
-hipError_t launch_site_update(Context* c);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
 hipError_t launch_get_populations(Context* c, int rep, void* dst);

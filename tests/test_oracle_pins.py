@@ -587,3 +587,49 @@ def test_variant_c_update_moves_only_momentum_and_stress(orc):
     assert np.allclose(dv3, dv, rtol=1e-14, atol=0)
     s3 = (e @ df3)[4:10]
     assert np.allclose(s3[big] / s1[big], 1.5, rtol=1e-9)
+
+
+def test_variant_c_interval_state_closed_form(orc):
+    """Variant C (Sec. 3): after the n MD steps of an interval each site holds
+    its interval-start populations plus momentum J and the forcing stress
+    (1 + gamma)/2 times the Guo image of (j0 J + J j0 + J J)/rho, J being
+    the interval's total transfer: the per-step sources u_k dJ_k + dJ_k u_k,
+    u_k = (j0 + J_k + dJ_k/2)/rho, telescope.  The Guo image is taken here
+    in its textbook population form w_i (9/2)(c_i c_i - I/3) : Q and
+    projected on the modes, independently of the oracle's update; J comes
+    from a variant-B run with the same noise."""
+    c, w, e, bn = orc.tables()
+    shape, nu, nu_b = (6, 5, 4), 0.3, 0.5
+    S = int(np.prod(shape))
+    f0 = w[:, None] * (1.0 + 0.05 * np.random.default_rng(3).standard_normal((19, S)))
+    runs = {}
+    for variant in (2, 3):
+        o = make_c1_like(orc, variant, kT=1e-3, friction=2.0, nu=nu, nu_bulk=nu_b)
+        o.set_populations(f0)
+        for _ in range(o.prm["n_sub"]):
+            assert o.md_couple_substep() == 0
+        runs[variant] = o
+    J = runs[2].J()                                  # [3, S]
+    rho = f0.sum(0)
+    j0 = c.T.astype(float) @ f0                      # [3, S]
+    Q = (j0[:, None] * J[None] + J[:, None] * j0[None] + J[:, None] * J[None]) / rho
+    cc = np.einsum('ia,ib->iab', c, c).astype(float) - np.eye(3) / 3.0
+    G = w[:, None] * 4.5 * np.einsum('iab,abs->is', cc, Q)   # [19, S]
+    g = e @ G
+    gs = (6 * nu - 1) / (6 * nu + 1)
+    gb = (9 * nu_b - 1) / (9 * nu_b + 1)
+    dm = np.zeros((19, S))
+    dm[1:4] = J
+    dm[4] = 0.5 * (1 + gb) * g[4]
+    dm[5:10] = 0.5 * (1 + gs) * g[5:10]
+    expect = f0 + w[:, None] * (e.T @ (dm / bn[:, None]))
+    got = runs[3].populations()
+    assert np.abs(got - expect).max() < 1e-15
+    # the check resolves every term: dropping the stress part, its j0 J share
+    # or its J J share moves some population by far more than the tolerance
+    for part in (Q, (j0[:, None] * J[None] + J[:, None] * j0[None]) / rho,
+                 J[:, None] * J[None] / rho):
+        gp = e @ (w[:, None] * 4.5 * np.einsum('iab,abs->is', cc, part))
+        dp = np.zeros((19, S))
+        dp[4], dp[5:10] = 0.5 * (1 + gb) * gp[4], 0.5 * (1 + gs) * gp[5:10]
+        assert np.abs(w[:, None] * (e.T @ (dp / bn[:, None]))).max() > 1e-9
