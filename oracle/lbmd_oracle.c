@@ -195,7 +195,8 @@ typedef struct {
   int32_t n_sub;       /* n = tau_LB / tau_MD, integer >= 1 (Sec. 3)      */
   int32_t variant;     /* 1 = variant A, 2 = variant B, 3 = variant C       */
   int32_t n_particles;
-  int32_t force_model; /* 0 none, 1 constant f_ext, 2 harmonic bonds + WCA */
+  int32_t force_model; /* 0 none, 1 constant f_ext, 2 harmonic bonds + WCA,
+                          3 Kremer-Grest: FENE bonds + LJ cut at 2^(7/6) sigma */
   int32_t chain_len;   /* beads per chain for force model 2                 */
   uint32_t replica;    /* enters the noise counter                          */
   uint32_t pad_;
@@ -264,8 +265,10 @@ int orc_create(const orc_params *p, orc_ctx **out) {
   if (!(p->nu > 0.0) || !(p->kT >= 0.0) || !(p->friction >= 0.0)) return ORC_EINVAL;
   if (!(p->rho0 > 0.0) || p->n_particles < 0) return ORC_EINVAL;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return ORC_EINVAL;
-  if (p->force_model == 2 && (p->chain_len < 1 || p->n_particles % p->chain_len))
+  if (p->force_model < 0 || p->force_model > 3) return ORC_EINVAL;
+  if (p->force_model >= 2 && (p->chain_len < 1 || p->n_particles % p->chain_len))
     return ORC_EINVAL;
+  if (p->force_model == 3 && !(p->r0_bond > 0.0)) return ORC_EINVAL;
   orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
   c->p = *p;
   c->nsites = (int64_t)p->nx * p->ny * p->nz;
@@ -304,9 +307,12 @@ static void conservative_forces(orc_ctx *c) {
   if (p->force_model == 1) {
     for (int64_t a = 0; a < N; ++a)
       for (int d = 0; d < 3; ++d) F[d * N + a] = p->f_ext[d];
-  } else if (p->force_model == 2) {
+  } else if (p->force_model >= 2) {
     double L[3] = {p->nx, p->ny, p->nz};
-    /* harmonic bonds U = k/2 (r - r0)^2 between consecutive beads of a chain */
+    /* bonds between consecutive beads of a chain.  Model 2: harmonic
+       U = k/2 (r - r0)^2.  Model 3 (Kremer-Grest, Sec. 3): FENE
+       U = -k R0^2/2 ln(1 - (r/R0)^2) with R0 = r0_bond, undefined (NaN
+       force) for r >= R0 */
     for (int64_t a = 0; a + 1 < N; ++a) {
       if ((a + 1) % p->chain_len == 0) continue;
       int64_t b = a + 1;
@@ -315,15 +321,25 @@ static void conservative_forces(orc_ctx *c) {
         d[k] = min_image(c->x[k * N + a] - c->x[k * N + b], L[k]);
         r2 += d[k] * d[k];
       }
-      double r = sqrt(r2);
-      double fmag = -p->k_bond * (r - p->r0_bond) / r; /* force on a along d */
+      double fmag; /* force on a along d, per unit of d */
+      if (p->force_model == 2) {
+        double r = sqrt(r2);
+        fmag = -p->k_bond * (r - p->r0_bond) / r;
+      } else {
+        double x2 = r2 / (p->r0_bond * p->r0_bond);
+        fmag = x2 < 1.0 ? -p->k_bond / (1.0 - x2) : NAN;
+      }
       for (int k = 0; k < 3; ++k) {
         F[k * N + a] += fmag * d[k];
         F[k * N + b] -= fmag * d[k];
       }
     }
-    /* WCA: U = 4 eps[(s/r)^12 - (s/r)^6] + eps for r < 2^(1/6) s, all pairs */
-    double rc2 = pow(2.0, 1.0 / 3.0) * p->wca_sigma * p->wca_sigma;
+    /* Lennard-Jones 4 eps[(s/r)^12 - (s/r)^6] between all pairs (bonded
+       ones included), cut at r_c: model 2 WCA, r_c = 2^(1/6) s (shifted by
+       + eps); model 3 the paper's cut-off r_c = 2^(7/6) s.  The energy
+       shift at r_c does not enter the force. */
+    double rc2 = (p->force_model == 2 ? pow(2.0, 1.0 / 3.0) : pow(2.0, 7.0 / 3.0)) *
+                 p->wca_sigma * p->wca_sigma;
     for (int64_t a = 0; a < N; ++a)
       for (int64_t b = a + 1; b < N; ++b) {
         double d[3], r2 = 0.0;

@@ -633,3 +633,91 @@ def test_variant_c_interval_state_closed_form(orc):
         dp = np.zeros((19, S))
         dp[4], dp[5:10] = 0.5 * (1 + gb) * gp[4], 0.5 * (1 + gs) * gp[5:10]
         assert np.abs(w[:, None] * (e.T @ (dp / bn[:, None]))).max() > 1e-9
+
+
+def _kg_energy(xx, shape, chain_len, kb, R0, eps, sig):
+    """Kremer-Grest energy of Sec. 3: FENE bonds -k R0^2/2 ln(1 - (r/R0)^2)
+    within chains, Lennard-Jones between all pairs cut (and shifted) at
+    2^(7/6) sigma, minimum image."""
+    L = np.array(shape, float)
+    N = xx.shape[1]
+    rc = 2 ** (7 / 6) * sig
+    shift = 4 * eps * ((sig / rc) ** 12 - (sig / rc) ** 6)
+    U = 0.0
+    for a in range(N):
+        for bb in range(a + 1, N):
+            d = xx[:, a] - xx[:, bb]
+            d -= L * np.round(d / L)
+            r = np.linalg.norm(d)
+            if bb == a + 1 and bb % chain_len != 0:
+                U += -0.5 * kb * R0 ** 2 * np.log(1 - (r / R0) ** 2)
+            if r < rc:
+                U += 4 * eps * ((sig / r) ** 12 - (sig / r) ** 6) - shift
+    return U
+
+
+def test_kremer_grest_forces_are_gradients(orc):
+    """Force model 3 (the paper's polymer model, Sec. 3): FENE k = 30,
+    R0 = 1.5 and LJ cut at 2^(7/6) sigma, as minus the gradient of the
+    energy written out above; the configuration puts non-bonded pairs in the
+    attractive range beyond the WCA cut-off (so a WCA cut fails)."""
+    shape = (9, 9, 9)
+    rng = np.random.default_rng(21)
+    k = np.arange(6)
+    a = np.stack([2 + 0.97 * k, 4 + 0 * k, 4 + 0 * k])
+    b = np.stack([3.4 + 0.97 * k, 5.6 + 0 * k, 4.3 + 0 * k])          # 1.3-1.7 from chain a
+    cc = np.stack([7 + 0 * k, 7.5 + 0 * k, np.mod(7.5 + 1.05 * k, 9)])  # crosses the z boundary
+    x = np.mod(np.concatenate([a, b, cc], 1) + 0.03 * rng.standard_normal((3, 18)), 9)
+    N = x.shape[1]
+    kb, R0, eps, sig = 30.0, 1.5, 1.0, 1.0
+    h = 1e-6
+    F = np.zeros_like(x)
+    for p in range(N):
+        for d in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[d, p] += h
+            xm[d, p] -= h
+            F[d, p] = -(_kg_energy(xp, shape, 6, kb, R0, eps, sig)
+                        - _kg_energy(xm, shape, 6, kb, R0, eps, sig)) / (2 * h)
+    o = orc.Oracle(*shape, n_sub=100, variant=2, n_particles=N, force_model=3, chain_len=6,
+                   k_bond=kb, r0_bond=R0, wca_eps=eps, wca_sigma=sig, particle_mass=1.0)
+    o.set_particles(x, np.zeros_like(x))
+    tau = 0.01
+    x1 = x + tau * (tau / 2) * F
+    o.md_couple_substep()
+    xo, vo, _ = o.particles()
+    assert np.abs(F).max() > 10
+    assert np.allclose(np.mod(x1, 9), xo, atol=1e-10)
+    assert np.abs(vo.sum(1)).max() < 1e-14 * np.abs(vo).max() * N
+    # the attractive tail acts: with the same beads, model 2 (WCA) differs
+    o2 = orc.Oracle(*shape, n_sub=100, variant=2, n_particles=N, force_model=2, chain_len=6,
+                    k_bond=kb, r0_bond=1.0, wca_eps=eps, wca_sigma=sig, particle_mass=1.0)
+    o2.set_particles(x, np.zeros_like(x))
+    o2.md_couple_substep()
+    assert np.abs(o2.particles()[0] - xo).max() > 1e-7
+
+
+def test_fene_closed_form_and_overstretch(orc):
+    """FENE force magnitude k r / (1 - (r/R0)^2): 54 at r = 1 for k = 30,
+    R0 = 1.5 (two beads, no LJ); a bond stretched to R0 has no finite force
+    and the particles become non-finite."""
+    shape = (8, 8, 8)
+    x = np.array([[3.0, 4.0], [4.0, 4.0], [4.0, 4.0]])
+    o = orc.Oracle(*shape, n_sub=100, variant=2, n_particles=2, force_model=3, chain_len=2,
+                   k_bond=30.0, r0_bond=1.5, wca_eps=0.0, wca_sigma=1.0, particle_mass=1.0)
+    o.set_particles(x, np.zeros_like(x))
+    o.md_couple_substep()
+    v = o.particles()[1]
+    tau = 0.01
+    # velocity Verlet: x1 = x0 + tau^2/2 F(x0), dv = tau/2 (F(x0) + F(x1))
+    fene = lambda r: 30.0 * r / (1.0 - (r / 1.5) ** 2)
+    F0 = fene(1.0)
+    assert abs(F0 - 54.0) < 1e-12
+    r1 = 1.0 - tau * tau * F0
+    assert abs(v[0, 0] - tau / 2 * (F0 + fene(r1))) < 1e-12
+    assert abs(v[0, 0] + v[0, 1]) < 1e-14
+    o2 = orc.Oracle(*shape, n_sub=100, variant=2, n_particles=2, force_model=3, chain_len=2,
+                    k_bond=30.0, r0_bond=1.5, wca_eps=0.0, wca_sigma=1.0, particle_mass=1.0)
+    o2.set_particles(np.array([[3.0, 4.6], [4.0, 4.0], [4.0, 4.0]]), np.zeros_like(x))
+    o2.md_couple_substep()
+    assert not np.isfinite(o2.particles()[1]).all()
