@@ -61,6 +61,9 @@ WORKLOAD_NAMES = {
           "list), n=10, gamma=20, kT=1, FP32 deviations, variant 2",
     "c2p": "polymer-128^3-stable: 128^3 lattice, 200 chains x 50 beads (harmonic k=30 kT + "
            "WCA eps=kT, cell list), n=10, gamma=2, kT=1e-4, FP32 deviations, variant 2",
+    "c2kg": "polymer-128^3-kremer-grest: 128^3 lattice, 200 chains x 50 beads (FENE k=30 kT, "
+            "R0=1.5 + LJ eps=kT cut at 2^(7/6), cell list), n=10, gamma=2, kT=0.01, nu=0.3, "
+            "FP32 deviations, variant 2",
 }
 # workload whose collide-stream launch the committed PMC summary covers
 TRAFFIC_WORKLOAD = "c3"
@@ -352,10 +355,11 @@ def main():
                     help="skip the FP32-vs-FP64 comparison on the workload")
     ap.add_argument("--variants", default="1,2,3",
                     help="coupling variants to time (1 = A, 2 = B, 3 = C); the JSON value is variant 2")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c2p"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c2p", "c2kg"],
                     help="c3: 256^3, 1e5 free particles (default); c2: 128^3 polymer "
                          "solution, 200 chains x 50 beads, bonds + WCA, as specified "
-                         "(unstable); c2p: the same shapes at stable parameters")
+                         "(unstable); c2p: the same shapes at stable parameters; c2kg: "
+                         "the same shapes with the paper's Kremer-Grest force field")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-replica batched-ensemble measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -389,7 +393,7 @@ def main():
     shape = cfg["shape"]
     S = int(np.prod(shape))
     copy_gbs = copy_ceiling(lbmd, torch, 19 * S * (4 if cfg["precision"] == 32 else 8))
-    if args.workload in ("c2", "c2p"):
+    if args.workload in ("c2", "c2p", "c2kg"):
         x, v = wl.chains(shape, cfg["n_particles"] // cfg["chain_len"], cfg["chain_len"],
                          cfg["kT"], cfg["particle_mass"], cfg["seed"],
                          min_dist=cfg.get("min_dist", 0.0))

@@ -80,9 +80,12 @@ typedef struct {
                              w_i rho0; 64: double (also deviations)            */
   int32_t n_particles;    /* N >= 0                                            */
   int32_t force_model;    /* 0 none; 1 constant force f_ext on every particle;
-                             2 harmonic bonds within chains + WCA (all pairs)  */
-  int32_t chain_len;      /* beads per chain for force_model 2 (N % chain_len
-                             == 0; bead b is bonded to b+1 inside a chain)     */
+                             2 harmonic bonds within chains + WCA (all pairs);
+                             3 the paper's Kremer-Grest polymer (Sec. 3): FENE
+                             bonds + Lennard-Jones cut at 2^(7/6) sigma        */
+  int32_t chain_len;      /* beads per chain for force_models 2, 3 (N %
+                             chain_len == 0; bead b is bonded to b+1 inside a
+                             chain)                                            */
   uint32_t replica;       /* replica id entering the noise counter             */
   uint64_t seed;          /* Philox key                                        */
   double rho0;            /* mean fluid mass density, > 0                      */
@@ -94,8 +97,13 @@ typedef struct {
   double particle_mass;   /* > 0 when N > 0                                    */
   double body_force[3];   /* uniform force density on the fluid                */
   double f_ext[3];        /* force_model 1                                     */
-  double k_bond, r0_bond; /* force_model 2: U = k/2 (r - r0)^2                 */
-  double wca_eps, wca_sigma; /* force_model 2: WCA cut at 2^(1/6) sigma        */
+  double k_bond, r0_bond; /* force_model 2: U = k/2 (r - r0)^2; force_model 3:
+                             FENE U = -k R0^2/2 ln(1 - (r/R0)^2), R0 = r0_bond
+                             > 0 (a bond at r >= R0 makes its beads
+                             non-finite, LBMD_ENONFINITE)                      */
+  double wca_eps, wca_sigma; /* Lennard-Jones eps, sigma between all pairs:
+                             cut at 2^(1/6) sigma (WCA, model 2) or at
+                             2^(7/6) sigma (model 3)                           */
 } lbmd_params;
 
 /* Device bytes lb_create() needs for these parameters (0 if invalid). */

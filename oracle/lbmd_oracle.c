@@ -347,7 +347,9 @@ static void conservative_forces(orc_ctx *c) {
           d[k] = min_image(c->x[k * N + a] - c->x[k * N + b], L[k]);
           r2 += d[k] * d[k];
         }
-        if (r2 >= rc2) continue;
+        /* beyond the cut-off, or a bead that is no longer finite: no pair
+           force (a diverged bead leaves the pair sums of the others) */
+        if (!(r2 < rc2)) continue;
         double sr2 = p->wca_sigma * p->wca_sigma / r2;
         double sr6 = sr2 * sr2 * sr2;
         double fmag = 24.0 * p->wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;

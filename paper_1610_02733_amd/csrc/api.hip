@@ -38,11 +38,12 @@ bool valid_one(const lbmd_params* p) {
   if (!(p->nu_bulk < 0.0 || p->nu_bulk > 0.0)) return false;
   if (!(fabs(p->gamma_ghost) < 1.0)) return false;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return false;
-  if (p->force_model < 0 || p->force_model > 2) return false;
-  if (p->force_model == 2) {
+  if (p->force_model < 0 || p->force_model > 3) return false;
+  if (p->force_model >= 2) {
     if (p->chain_len < 1 || (p->n_particles % p->chain_len) != 0) return false;
     if (!(p->wca_sigma > 0.0) || !(p->wca_eps >= 0.0) || !(p->k_bond >= 0.0)) return false;
     if (!isfinite(p->r0_bond)) return false;
+    if (p->force_model == 3 && !(p->r0_bond > 0.0)) return false;  // FENE R0
   }
   for (int d = 0; d < 3; ++d)
     if (!isfinite(p->body_force[d]) || !isfinite(p->f_ext[d])) return false;
@@ -85,7 +86,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
     pl.Ntot += p[r].n_particles;
     pl.Ctot += force_cells(p + r);
     pl.nitems += (int)((S + kBlock - 1) / kBlock);
-    pl.any_forces2 = pl.any_forces2 || (p[r].force_model == 2 && p[r].n_particles > 0);
+    pl.any_forces2 = pl.any_forces2 || (p[r].force_model >= 2 && p[r].n_particles > 0);
   }
   pl.item_off.push_back(pl.nitems);
   Layout& L = pl.lay;
@@ -181,9 +182,9 @@ RepMD rep_md(const Context* c, int r) {
   m.cell_off = (int)c->plan.cell_off[r];
   m.variant = p.variant;
   m.noise = (p.kT > 0.0 && p.friction > 0.0) ? 1 : 0;
-  m.split_kick = p.force_model == 2 ? 1 : 0;
+  m.split_kick = p.force_model >= 2 ? 1 : 0;
   m.force_model = p.force_model;
-  m.chain_len = p.force_model == 2 ? p.chain_len : 1;
+  m.chain_len = p.force_model >= 2 ? p.chain_len : 1;
   m.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
   m.key1 = (uint32_t)(p.seed >> 32);
   m.tag = lbmd_dev::noise_tag(lbmd_dev::kPurposeParticle, p.replica, 0);

@@ -1,7 +1,9 @@
 // Conservative particle forces F_cons (Eq. 4; they act on the particles
-// only) for the bead-spring workload: harmonic bonds between consecutive
-// beads of a chain and the purely repulsive WCA potential between all pairs,
-// found through a cell list.  Also the counting-sort binning of particles
+// only) for the bead-spring workloads, with pairs found through a cell list:
+// model 2, harmonic bonds between consecutive beads of a chain and the purely
+// repulsive WCA potential between all pairs; model 3, the paper's
+// Kremer-Grest polymer (Sec. 3), FENE bonds and the Lennard-Jones potential
+// cut at 2^(7/6) sigma.  Also the counting-sort binning of particles
 // into cells (histogram, three-level exclusive scan, scatter).
 #include <algorithm>
 #include <cmath>
@@ -12,7 +14,7 @@ namespace lbmd_impl {
 
 // ---------------------------------------------------------------------------
 // Binning: cell = floor(x / edge) per axis on each replica's grid of
-// nb[0] x nb[1] x nb[2] cells of edge L / nb >= the WCA cut-off; cells of all
+// nb[0] x nb[1] x nb[2] cells of edge L / nb >= the pair cut-off; cells of all
 // replicas share one global index space (offset cell_off).  Non-finite
 // particles go to no cell (they are left out of the force loop).
 // ---------------------------------------------------------------------------
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__
   if (p >= N) return;
   const double X[3] = {x[p], x[N + p], x[2 * N + p]};
   const RepMD& m = md[part_rep[p]];
-  if (m.force_model != 2 || !(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) {
+  if (m.force_model < 2 || !(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) {
     bin[p] = -1;
     return;
   }
@@ -182,10 +184,12 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
     const int lane = (int)(t & (kForceLanes - 1));
     const RepMD& m = a.md[a.part_rep[p]];
     double F[3] = {0.0, 0.0, 0.0};
-    const int c = m.force_model == 2 ? a.bin[p] : -1;
+    const int c = m.force_model >= 2 ? a.bin[p] : -1;
     if (c >= 0) {
       const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
-      const double rc2 = 1.2599210498948732 * m.wca_sigma * m.wca_sigma;  // (2^(1/6) sigma)^2
+      // pair cut-off squared: (2^(1/6) sigma)^2 (WCA) or (2^(7/6) sigma)^2
+      const double rc2 = (m.force_model == 2 ? 1.2599210498948732 : 5.0396841995794928) *
+                         m.wca_sigma * m.wca_sigma;
       const double sig2 = m.wca_sigma * m.wca_sigma;
       if (lane < 27) {
         const int o[3] = {lane % 3, (lane / 3) % 3, lane / 9};
@@ -224,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
           }
         }
       } else if (lane == 27) {
-        // harmonic bonds to the chain neighbours
+        // bonds to the chain neighbours: harmonic (model 2) or FENE (model 3,
+        // no finite force at r >= R0)
         const int pos = (int)((p - m.part_off) % m.chain_len);
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
@@ -236,8 +241,14 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
             dx[d] = min_image(X[d] - a.x[d * N + q], m.L[d]);
             r2 += dx[d] * dx[d];
           }
-          const double r = sqrt(r2);
-          const double fm = -m.k_bond * (r - m.r0_bond) / r;
+          double fm;
+          if (m.force_model == 2) {
+            const double r = sqrt(r2);
+            fm = -m.k_bond * (r - m.r0_bond) / r;
+          } else {
+            const double x2 = r2 / (m.r0_bond * m.r0_bond);
+            fm = x2 < 1.0 ? -m.k_bond / (1.0 - x2) : __builtin_nan("");
+          }
 #pragma unroll
           for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
         }
@@ -274,19 +285,20 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
   }
 }
 
-// Force cells per axis: edge just above the WCA cut-off 2^(1/6) sigma, so the
-// 27 neighbouring cells hold every interacting pair.  Larger cells (about one
+// Force cells per axis: edge just above the pair cut-off (2^(1/6) sigma for
+// WCA, 2^(7/6) sigma for the Kremer-Grest model), so the 27 neighbouring
+// cells hold every interacting pair.  Larger cells (about one
 // particle per cell on average) were measured slower on chains: a chain's
 // beads then crowd a few cells and the per-lane cell loops serialise.
 int cells_per_axis(const lbmd_params* p, int d) {
-  const double rc = std::pow(2.0, 1.0 / 6.0) * p->wca_sigma;
+  const double rc = std::pow(2.0, p->force_model == 3 ? 7.0 / 6.0 : 1.0 / 6.0) * p->wca_sigma;
   const int L[3] = {p->nx, p->ny, p->nz};
   const int q = (int)std::floor((double)L[d] / rc);
   return q < 1 ? 1 : q;
 }
 
 int64_t force_cells(const lbmd_params* p) {
-  if (p->force_model != 2) return 0;
+  if (p->force_model < 2) return 0;
   int64_t n = 1;
   for (int d = 0; d < 3; ++d) n *= cells_per_axis(p, d);
   return n;
@@ -316,7 +328,7 @@ static ForceArgs<T> force_args(Context* c) {
   return a;
 }
 
-// Bin the particles of force-model-2 replicas into their cells.
+// Bin the particles of bead-spring replicas (models 2, 3) into their cells.
 static hipError_t launch_binning(Context* c) {
   const int64_t N = c->plan.Ntot;
   const Layout& L = c->plan.lay;

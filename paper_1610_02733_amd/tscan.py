@@ -11,12 +11,13 @@ n = tau_LB/dt in {1, 5, 10}.  The library works in lattice units (a = 1,
 tau_LB = 1, bead mass 1), so with s = n dt (tau_LB in units of tau):
 
     kT = s^2,  nu = 3 s,  zeta_lattice = zeta s,
-    bead-spring forces: WCA eps = kT, sigma = 1; bonds k = 30 kT, r0 = 1.
+    bead forces: LJ eps = kT, sigma = 1; bond stiffness k = 30 kT.
 
-The paper's melt is pre-relaxed Kremer-Grest (Lennard-Jones cut at
-2^(7/6) sigma, FENE bonds); the chains here are random walks with
-harmonic bonds and WCA repulsion (force model 2), a good-solvent stand-in
-of the same size and density.  One batch per (variant, n, dt) holds one
+The paper's system is a pre-relaxed Kremer-Grest solution (Lennard-Jones
+between all beads cut at 2^(7/6) sigma, FENE bonds k = 30 eps/sigma^2,
+R0 = 1.5 sigma): model "kg" (force model 3) uses that force field on
+seeded random-walk chains, which are not pre-relaxed; model "wca"
+(force model 2: harmonic bonds, WCA repulsion) is a good-solvent variant.  One batch per (variant, n, dt) holds one
 replica per friction value; every replica starts from the same seeded
 configuration and draws its own noise (replica id).  The temperature is
 2 KE / (3 N kT), sampled every `sample_tau` after `equil_tau`, with a
@@ -43,12 +44,19 @@ PAPER_NS = (1, 5, 10)
 ZETAS = (1.0, 2.0, 5.0, 10.0, 20.0)
 
 
-def lattice_params(n, dt, zeta):
-    """Lattice-unit parameters of one scan point (LJ units in, see module doc)."""
+def lattice_params(n, dt, zeta, model="kg"):
+    """Lattice-unit parameters of one scan point (LJ units in, see module
+    doc).  model "kg": the paper's Kremer-Grest force field (FENE k = 30 eps,
+    R0 = 1.5 sigma; LJ cut at 2^(7/6) sigma); "wca": harmonic bonds
+    (k = 30 eps, r0 = sigma) and WCA."""
     s = n * dt
     kT = s * s
-    return dict(kT=kT, nu=3.0 * s, friction=zeta * s, k_bond=30.0 * kT, r0_bond=1.0,
-                wca_eps=kT, wca_sigma=1.0)
+    p = dict(kT=kT, nu=3.0 * s, friction=zeta * s, k_bond=30.0 * kT, wca_eps=kT, wca_sigma=1.0)
+    if model == "kg":
+        p.update(force_model=3, r0_bond=1.5)
+    else:
+        p.update(force_model=2, r0_bond=1.0)
+    return p
 
 
 def _block_error(samples, blocks=8):
@@ -73,7 +81,8 @@ def _start(box, n_chains, chain_len, seed):
 
 
 def scan_batch(variant, n, dt, zetas, *, box=20, n_chains=10, chain_len=256, t_tau=50.0,
-               equil_tau=10.0, sample_tau=0.5, seed=1, precision=32, device="cuda"):
+               equil_tau=10.0, sample_tau=0.5, seed=1, precision=32, model="kg",
+               device="cuda"):
     """One batch: the friction values `zetas` at fixed (variant, n, dt).
     Returns one dict per friction value."""
     shape = (box, box, box)
@@ -84,9 +93,8 @@ def scan_batch(variant, n, dt, zetas, *, box=20, n_chains=10, chain_len=256, t_t
     reps = []
     for r, z in enumerate(zetas):
         kw = dict(precision=precision, n_sub=n, variant=variant, seed=seed, replica=r,
-                  n_particles=N, particle_mass=1.0, force_model=2, chain_len=chain_len,
-                  rho0=1.0)
-        kw.update(lattice_params(n, dt, z))
+                  n_particles=N, particle_mass=1.0, chain_len=chain_len, rho0=1.0)
+        kw.update(lattice_params(n, dt, z, model))
         reps.append((shape, kw))
     B = lbmd.Batch(reps, device=device)
     B.bind_particles([x] * len(zetas), [v] * len(zetas))
@@ -142,6 +150,8 @@ def main(argv=None):
     ap.add_argument("--sample-tau", type=float, default=0.5)
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--model", default="kg", choices=["kg", "wca"],
+                    help="kg: the paper's Kremer-Grest force field; wca: harmonic + WCA")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -153,7 +163,7 @@ def main(argv=None):
         dts=[float(t) for t in args.dts.split(",")],
         zetas=[float(t) for t in args.zetas.split(",")],
         t_tau=args.t_tau, equil_tau=args.equil_tau, sample_tau=args.sample_tau,
-        precision=args.precision, seed=args.seed, log=log, **PAPER_SYSTEM)
+        precision=args.precision, seed=args.seed, model=args.model, log=log, **PAPER_SYSTEM)
     for r in rows:
         print(json.dumps(r), flush=True)
 

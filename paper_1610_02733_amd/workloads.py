@@ -37,6 +37,14 @@ CONFIGS = {
                 kT=1e-4, n_particles=10_000, chain_len=50, particle_mass=1.0, friction=2.0,
                 n_sub=10, lb_steps=1000, seed=2, precision=32, variant=2, force_model=2,
                 k_bond=3e-3, r0_bond=1.0, wca_eps=1e-4, wca_sigma=1.0, min_dist=0.9),
+    # the paper's polymer model (Kremer-Grest: FENE k = 30 kT, R0 = 1.5 sigma,
+    # Lennard-Jones eps = kT cut at 2^(7/6) sigma) on the c2p shapes, in the
+    # lattice units of n = 10, dt = 0.01 tau (kT = 0.01, nu = 0.3,
+    # zeta = 20 mu/tau -> gamma = 2)
+    "c2kg": dict(shape=(128, 128, 128), rho0=1.0, nu=0.3, nu_bulk=-1.0, gamma_ghost=0.0,
+                 kT=0.01, n_particles=10_000, chain_len=50, particle_mass=1.0, friction=2.0,
+                 n_sub=10, lb_steps=1000, seed=2, precision=32, variant=2, force_model=3,
+                 k_bond=0.3, r0_bond=1.5, wca_eps=0.01, wca_sigma=1.0, min_dist=0.9),
     "c3": dict(shape=(256, 256, 256), rho0=1.0, nu=NU_1_6, nu_bulk=-1.0, gamma_ghost=0.0,
                kT=1e-4, n_particles=100_000, particle_mass=1.0, friction=10.0, n_sub=10,
                lb_steps=200, seed=3, precision=32),

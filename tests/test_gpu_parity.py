@@ -227,6 +227,51 @@ def test_polymer_forces_coupled(lb, orc, prec, variant):
     check_particles(g, o, shape, TOL[prec] * 10, 1e-3)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_kremer_grest_coupled(lb, orc, prec, variant):
+    """The paper's polymer model (force model 3: FENE k = 30 kT, R0 = 1.5,
+    Lennard-Jones eps = kT cut at 2^(7/6) sigma) coupled to the fluid, in the
+    lattice units of n = 10, dt = 0.01 tau (kT = 0.01, nu = 0.3, zeta = 20
+    mu/tau -> 2): 20^3 lattice, 12 chains x 10 beads, 10 LB steps, against
+    the oracle's all-pairs forces."""
+    shape = (20, 20, 20)
+    x, v = wl.chains(shape, 12, 10, 0.01, 1.0, seed=33, bond=0.97, min_dist=0.95)
+    kw = dict(kT=0.01, nu=0.3, seed=9, n_particles=120, friction=2.0, n_sub=10, variant=variant,
+              force_model=3, chain_len=10, k_bond=0.3, r0_bond=1.5, wca_eps=0.01,
+              wca_sigma=1.0)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 10, x=x, v=v, precision=prec, **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < TOL[prec], err
+    check_particles(g, o, shape, TOL[prec] * 10, 0.01)
+
+
+def test_fene_overstretch_is_flagged(lb, orc):
+    """A FENE bond stretched to R0 has no finite force: its beads become
+    non-finite and the context reports ENONFINITE; the other chain stays
+    finite and equals the oracle's."""
+    shape = (8, 8, 8)
+    x = np.array([[3.0, 4.6, 1.0, 2.0], [4.0, 4.0, 6.0, 6.0], [4.0, 4.0, 6.0, 6.0]])
+    # k = 0.3 with tau_MD = 0.1: the intact bond (r = 1) moves its beads by
+    # ~1e-3 per MD step; the bond at r = 1.6 > R0 has no finite force at all
+    g = lb.Lattice(shape, precision=64, n_sub=10, variant=2, kT=0.0, n_particles=4,
+                   friction=0.5, force_model=3, chain_len=2, k_bond=0.3, r0_bond=1.5,
+                   wca_eps=0.0, wca_sigma=1.0)
+    g.bind_particles(x, np.zeros_like(x))
+    g.cycle(1)
+    v = g.v.cpu().numpy()
+    assert not np.isfinite(v[:, :2]).all() and np.isfinite(v[:, 2:]).all()
+    with pytest.raises(lb.LbmdError) as ei:
+        g.moments()
+    assert ei.value.code == lb.ENONFINITE
+    o = orc.Oracle(*shape, n_sub=10, variant=2, kT=0.0, n_particles=4, friction=0.5,
+                   force_model=3, chain_len=2, k_bond=0.3, r0_bond=1.5, wca_eps=0.0,
+                   wca_sigma=1.0)
+    o.set_particles(x, np.zeros_like(x))
+    o.cycle(1)
+    assert np.abs(o.particles()[1][:, 2:] - v[:, 2:]).max() < 1e-12
+
+
 def test_polymer_small_box_cell_grid(lb, orc):
     """A box narrower than three WCA cells per axis (cell stencil must not
     visit a cell twice), FP64."""

@@ -14,5 +14,7 @@ def test_lj_to_lattice_units():
     assert math.isclose(p["friction"], 20.0 * s)        # zeta in mu / tau
     assert math.isclose(p["k_bond"], 30.0 * s * s)      # 30 eps / sigma^2
     assert math.isclose(p["wca_eps"], p["kT"]) and p["wca_sigma"] == 1.0
+    assert p["force_model"] == 3 and p["r0_bond"] == 1.5           # FENE R0 = 1.5 sigma
+    assert lattice_params(10, 0.01, 20.0, "wca")["force_model"] == 2
     # the dimensionless friction per MD step is unit-free: zeta dt = zeta_lat tau_MD / m
     assert math.isclose(p["friction"] * (1.0 / 10), 20.0 * 0.01)
