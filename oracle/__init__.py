@@ -41,7 +41,7 @@ class OrcParams(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("n_sub", C.c_int32), ("variant", C.c_int32), ("n_particles", C.c_int32),
         ("force_model", C.c_int32), ("chain_len", C.c_int32),
-        ("replica", C.c_uint32), ("pad_", C.c_uint32),
+        ("replica", C.c_uint32), ("stencil", C.c_int32),
         ("seed", C.c_uint64),
         ("rho0", C.c_double), ("nu", C.c_double), ("nu_bulk", C.c_double),
         ("gamma_ghost", C.c_double), ("kT", C.c_double), ("friction", C.c_double),
@@ -86,6 +86,7 @@ def lib():
         L.orc_lb_step_sampled.argtypes = [P, C.c_int64, lp, dp]
         L.orc_collide_site.argtypes = [P, C.c_int64, C.c_int64, dp, dp, dp]
         L.orc_cube_weights.argtypes = [P, dp, lp, dp]
+        L.orc_stencil3_weights.argtypes = [P, dp, lp, dp]
         L.orc_moments.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
         for name in ("orc_create", "orc_set_particles", "orc_get_particles",
                      "orc_set_populations", "orc_get_populations", "orc_get_J",
@@ -129,7 +130,7 @@ _PARAM_DEFAULTS = dict(nu_bulk=-1.0, gamma_ghost=0.0, kT=0.0, friction=0.0,
                        particle_mass=1.0, body_force=(0.0, 0.0, 0.0),
                        f_ext=(0.0, 0.0, 0.0), k_bond=0.0, r0_bond=1.0,
                        wca_eps=0.0, wca_sigma=1.0, force_model=0, chain_len=1,
-                       replica=0, seed=0, n_particles=0, variant=2, n_sub=1,
+                       replica=0, seed=0, n_particles=0, variant=2, n_sub=1, stencil=0,
                        rho0=1.0, nu=1.0 / 6.0)
 
 
@@ -253,6 +254,12 @@ class Oracle:
         sites = np.zeros(8, np.int64)
         w = np.zeros(8)
         lib().orc_cube_weights(self._h, np.ascontiguousarray(R, np.float64), sites, w)
+        return sites, w
+
+    def stencil3_weights(self, R):
+        sites = np.zeros(27, np.int64)
+        w = np.zeros(27)
+        lib().orc_stencil3_weights(self._h, np.ascontiguousarray(R, np.float64), sites, w)
         return sites, w
 
     def moments(self, fields=False):

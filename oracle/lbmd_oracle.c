@@ -199,7 +199,9 @@ typedef struct {
                           3 Kremer-Grest: FENE bonds + LJ cut at 2^(7/6) sigma */
   int32_t chain_len;   /* beads per chain for force model 2                 */
   uint32_t replica;    /* enters the noise counter                          */
-  uint32_t pad_;
+  int32_t stencil;     /* interpolation / spreading stencil (Eq. 5, 7):
+                          0 trilinear over the 8 cube sites, 1 the 3-point
+                          kernel per axis over 27 sites                     */
   uint64_t seed;
   double rho0, nu, nu_bulk, gamma_ghost, kT, friction, particle_mass;
   double body_force[3], f_ext[3];
@@ -266,6 +268,7 @@ int orc_create(const orc_params *p, orc_ctx **out) {
   if (!(p->rho0 > 0.0) || p->n_particles < 0) return ORC_EINVAL;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return ORC_EINVAL;
   if (p->force_model < 0 || p->force_model > 3) return ORC_EINVAL;
+  if (p->stencil < 0 || p->stencil > 1) return ORC_EINVAL;
   if (p->force_model >= 2 && (p->chain_len < 1 || p->n_particles % p->chain_len))
     return ORC_EINVAL;
   if (p->force_model == 3 && !(p->r0_bond > 0.0)) return ORC_EINVAL;
@@ -565,6 +568,55 @@ void orc_cube_weights(const orc_ctx *c, const double R[3], int64_t sites[8],
   }
 }
 
+/* Three-point kernel per axis (Roma, Peskin and Berger, J. Comput. Phys.
+ * 153 (1999) 509), the higher-order alternative the paper mentions for
+ * Eq. 5 and Eq. 7 (Sec. 4): for a distance r from a site along one axis
+ *   phi(r) = (1 + sqrt(1 - 3 r^2)) / 3                for |r| <= 1/2,
+ *   phi(r) = (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6 for 1/2 <= |r| <= 3/2,
+ *   phi(r) = 0 otherwise.
+ * The particle at R uses the three sites nearest along each axis,
+ * j = c - 1, c, c + 1 with c = floor(R + 1/2); the site weight is the
+ * product of the three axis weights (27 sites). */
+static double phi3(double r) {
+  double a = fabs(r);
+  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+  if (a <= 1.5) {
+    double b = 1.0 - a;
+    double q = 1.0 - 3.0 * b * b;
+    return (5.0 - 3.0 * a - sqrt(q > 0.0 ? q : 0.0)) / 6.0;
+  }
+  return 0.0;
+}
+
+void orc_stencil3_weights(const orc_ctx *c, const double R[3], int64_t sites[27],
+                          double w[27]) {
+  int64_t L[3] = {c->p.nx, c->p.ny, c->p.nz};
+  int64_t ctr[3];
+  double wa[3][3];
+  for (int d = 0; d < 3; ++d) {
+    ctr[d] = (int64_t)floor(R[d] + 0.5);
+    for (int j = 0; j < 3; ++j) wa[d][j] = phi3(R[d] - (double)(ctr[d] + j - 1));
+  }
+  for (int k = 0; k < 27; ++k) {
+    int o[3] = {k % 3, (k / 3) % 3, k / 9};
+    w[k] = wa[0][o[0]] * wa[1][o[1]] * wa[2][o[2]];
+    sites[k] = site_index(c, wrap_coord(ctr[0] + o[0] - 1, L[0]),
+                          wrap_coord(ctr[1] + o[1] - 1, L[1]),
+                          wrap_coord(ctr[2] + o[2] - 1, L[2]));
+  }
+}
+
+/* The sites and weights of the context's stencil; returns their count. */
+static int stencil_weights(const orc_ctx *c, const double R[3], int64_t sites[27],
+                           double w[27]) {
+  if (c->p.stencil == 1) {
+    orc_stencil3_weights(c, R, sites, w);
+    return 27;
+  }
+  orc_cube_weights(c, R, sites, w);
+  return 8;
+}
+
 /* fluid velocity seen by the coupling at a site: u = j/rho of the
  * post-stream state (variant A), plus the momentum already transferred in
  * this LB interval, (j + J)/rho (variant B: "update the lattice velocities
@@ -677,8 +729,9 @@ int orc_md_couple_substep(orc_ctx *c) {
   double tau = 1.0 / p->n_sub;
   double amp = sqrt(2.0 * p->friction * p->kT / tau);
   double *Fc = (double *)calloc(3 * (N > 0 ? N : 1), sizeof(double));
-  int64_t (*sites)[8] = malloc(sizeof(int64_t[8]) * (N > 0 ? N : 1));
-  double (*wts)[8] = malloc(sizeof(double[8]) * (N > 0 ? N : 1));
+  int64_t (*sites)[27] = malloc(sizeof(int64_t[27]) * (N > 0 ? N : 1));
+  double (*wts)[27] = malloc(sizeof(double[27]) * (N > 0 ? N : 1));
+  int K = 8;  /* sites per particle: 8 (trilinear) or 27 (3-point kernel) */
   char *ok = (char *)calloc(N > 0 ? N : 1, 1);
   for (int64_t a = 0; a < N; ++a) {
     double R[3], v[3];
@@ -693,9 +746,9 @@ int orc_md_couple_substep(orc_ctx *c) {
       continue;
     }
     ok[a] = 1;
-    orc_cube_weights(c, R, sites[a], wts[a]);
+    K = stencil_weights(c, R, sites[a], wts[a]);
     double uR[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < K; ++k) {
       double uk[3];
       site_velocity(c, sites[a][k], uk);
       for (int d = 0; d < 3; ++d) uR[d] += wts[a][k] * uk[d];
@@ -709,7 +762,7 @@ int orc_md_couple_substep(orc_ctx *c) {
   double *target = p->variant == 3 ? c->dJ : c->J;
   for (int64_t a = 0; a < N; ++a) {
     if (!ok[a]) continue;
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < K; ++k)
       for (int d = 0; d < 3; ++d)
         target[d * S + sites[a][k]] -= wts[a][k] * tau * Fc[d * N + a];
   }
@@ -719,7 +772,7 @@ int orc_md_couple_substep(orc_ctx *c) {
        start: the updates touch disjoint sites) */
     for (int64_t a = 0; a < N; ++a) {
       if (!ok[a]) continue;
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < K; ++k) {
         int64_t r = sites[a][k];
         double dJ[3] = {c->dJ[r], c->dJ[S + r], c->dJ[2 * S + r]};
         if (dJ[0] == 0.0 && dJ[1] == 0.0 && dJ[2] == 0.0) continue; /* done or empty */

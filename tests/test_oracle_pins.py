@@ -721,3 +721,60 @@ def test_fene_closed_form_and_overstretch(orc):
     o2.set_particles(np.array([[3.0, 4.6], [4.0, 4.0], [4.0, 4.0]]), np.zeros_like(x))
     o2.md_couple_substep()
     assert not np.isfinite(o2.particles()[1]).all()
+
+
+def test_three_point_stencil_defining_conditions(orc):
+    """The 3-point kernel of the higher-order stencil is fixed by three
+    conditions per axis at every position: its weights sum to one, its first
+    moment vanishes (affine functions are reproduced), and the sum of its
+    squared weights is 1/2 (the same for every position).  Over the 27-site
+    tensor product these become sum w = 1, sum w (x_k - R) = 0 and
+    sum w^2 = 1/8; the sites are the three nearest per axis."""
+    o = orc.Oracle(8, 7, 6, stencil=1)
+    L = np.array([[8], [7], [6]])
+    rng = np.random.default_rng(6)
+    Rs = list(rng.random((200, 3)) * [8, 7, 6]) + [np.array([3.5, 2.5, 0.5]),
+                                                   np.array([0.0, 6.999999, 5.25])]
+    for R in Rs:
+        sites, w = o.stencil3_weights(R)
+        assert len(set(sites.tolist())) == 27
+        assert abs(w.sum() - 1) < 1e-14 and (w >= -1e-17).all()
+        xs = np.stack([sites % 8, (sites // 8) % 7, sites // 56], 0).astype(float)
+        xs = xs + np.round((R[:, None] - xs) / L) * L
+        assert np.all(np.abs(xs - R[:, None]) <= 1.5 + 1e-12)
+        assert np.allclose(xs @ w, R, atol=1e-13)
+        assert abs((w * w).sum() - 0.125) < 1e-13
+    # on a site: 2/3 there and 1/6 at each axis neighbour
+    sites, w = o.stencil3_weights(np.array([3.0, 2.0, 1.0]))
+    assert abs(w.max() - (2 / 3) ** 3) < 1e-15
+    assert abs(np.sort(w)[0] - (1 / 6) ** 3) < 1e-15
+
+
+def test_three_point_stencil_in_the_coupling(orc):
+    """With stencil 1 the coupling interpolates over the 27 sites (Eq. 5)
+    and spreads -dP with the same weights (Eq. 7): an affine velocity field
+    is seen exactly and the fluid receives exactly -dP, spread over 27
+    sites with the stencil's weights."""
+    c, w, e, b = orc.tables()
+    shape = (7, 7, 7)
+    S = 343
+    idx = np.arange(S)
+    pos = np.stack([idx % 7, (idx // 7) % 7, idx // 49], 0).astype(float)
+    a = np.array([1e-3, -2e-3, 5e-4])
+    B = 1e-4 * np.array([[1, 2, 3], [-1, 0.5, 2], [0.3, -0.7, 1]])
+    u = a[:, None] + B @ pos
+    f = np.stack([feq_poly(c, w, 1.0, u[:, s]) for s in range(S)], 1)
+    R = np.array([[3.3], [3.7], [2.45]])
+    gamma, n = 0.8, 4
+    for variant in (1, 2):
+        o = orc.Oracle(*shape, n_sub=n, variant=variant, friction=gamma, n_particles=1,
+                       stencil=1)
+        o.set_populations(f)
+        o.set_particles(R, np.zeros((3, 1)))
+        o.md_couple_substep()
+        dP = o.particles()[1][:, 0]
+        assert np.allclose(dP, gamma / n * (a + B @ R[:, 0]), rtol=1e-12, atol=1e-18)
+        J = o.J()
+        sites, wts = o.stencil3_weights(R[:, 0])
+        assert np.count_nonzero(np.abs(J).sum(0)) == 27
+        assert np.allclose(J[:, sites], -wts[None, :] * dP[:, None], rtol=1e-12, atol=1e-20)
