@@ -104,6 +104,13 @@ typedef struct {
   double wca_eps, wca_sigma; /* Lennard-Jones eps, sigma between all pairs:
                              cut at 2^(1/6) sigma (WCA, model 2) or at
                              2^(7/6) sigma (model 3)                           */
+  int32_t stencil;        /* velocity interpolation and force spreading (Eq. 5,
+                             Eq. 7, always the same): 0 trilinear over the 8
+                             sites of the particle's cube; 1 the three-point
+                             kernel of Roma, Peskin and Berger per axis over
+                             the 27 nearest sites (the higher-order scheme of
+                             Sec. 4).  Equal for all replicas of a batch; the
+                             adjoint requires 0                                */
 } lbmd_params;
 
 /* Device bytes lb_create() needs for these parameters (0 if invalid). */

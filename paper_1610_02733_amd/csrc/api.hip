@@ -39,6 +39,7 @@ bool valid_one(const lbmd_params* p) {
   if (!(fabs(p->gamma_ghost) < 1.0)) return false;
   if (p->n_particles > 0 && !(p->particle_mass > 0.0)) return false;
   if (p->force_model < 0 || p->force_model > 3) return false;
+  if (p->stencil < 0 || p->stencil > 1) return false;
   if (p->force_model >= 2) {
     if (p->chain_len < 1 || (p->n_particles % p->chain_len) != 0) return false;
     if (!(p->wca_sigma > 0.0) || !(p->wca_eps >= 0.0) || !(p->k_bond >= 0.0)) return false;
@@ -58,7 +59,7 @@ bool valid_set(const lbmd_params* p, int32_t R) {
   for (int r = 0; r < R; ++r) {
     if (!valid_one(p + r)) return false;
     if (p[r].n_sub != p[0].n_sub || p[r].precision != p[0].precision ||
-        p[r].variant != p[0].variant)
+        p[r].variant != p[0].variant || p[r].stencil != p[0].stencil)
       return false;
     S += ((int64_t)p[r].nx * p[r].ny * p[r].nz + 63) / 64 * 64;
     N += p[r].n_particles;
@@ -108,7 +109,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.rec_frac = o; o = up(o + 3 * N * 8);
   L.rec_dp = o; o = up(o + 3 * N * 8);
   L.fc_held = o; o = up(o + 3 * N * 8);
-  L.cc = o; o = up(o + 32 * N * t);
+  L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
   L.cc_cell = o; o = up(o + N * 4);
   L.cc_stamp = o; o = up(o + N * 4);
   L.shared_site = o; o = up(o + (S / 64) * 8);
@@ -184,6 +185,7 @@ RepMD rep_md(const Context* c, int r) {
   m.noise = (p.kT > 0.0 && p.friction > 0.0) ? 1 : 0;
   m.split_kick = p.force_model >= 2 ? 1 : 0;
   m.force_model = p.force_model;
+  m.stencil = p.stencil;
   m.chain_len = p.force_model >= 2 ? p.chain_len : 1;
   m.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
   m.key1 = (uint32_t)(p.seed >> 32);
@@ -593,7 +595,8 @@ AdjLayout adj_layout(const Context* c, int K) {
 }
 
 bool adjoint_supported(const Context* c) {
-  return c->plan.R == 1 && c->p[0].force_model <= 1 && c->p[0].variant <= 2;
+  return c->plan.R == 1 && c->p[0].force_model <= 1 && c->p[0].variant <= 2 &&
+         c->p[0].stencil == 0;
 }
 
 // Particles, counters and an empty transfer field from a saved state (the

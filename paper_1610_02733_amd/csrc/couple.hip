@@ -1,8 +1,10 @@
 // Particle coupling kernels (Sec. 3, Eq. 4-8): fluid velocity at the
-// particle by interpolation over the 8 sites of its cube, friction plus
-// noise, velocity Verlet, and transfer of -dP to the same 8 sites with the
-// same weights.  Particles of all replicas in one launch; each particle
-// reads its replica's constants.
+// particle by interpolation over the sites of its stencil (the 8 sites of
+// its cube, or 27 with the three-point kernel), friction plus noise,
+// velocity Verlet, and transfer of -dP to the same sites with the same
+// weights.  Particles of all replicas in one launch; each particle reads its
+// replica's constants.  Kernels are templated on the stencil (ST, see
+// particle_geom.hpp); the adjoint exists for the trilinear one only.
 #include <algorithm>
 
 #include "particle_geom.hpp"
@@ -41,10 +43,10 @@ struct CoupleArgs {
   int single;   // one replica: its constants are uniform across the grid
 };
 
-// Corner cache entry k of particle p: (jx, jy, jz, 1/rho) of the corner.
-template <typename T>
+// Cache entry k of particle p: (jx, jy, jz, 1/rho) of stencil site k.
+template <int ST = 0, typename T>
 __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
-  return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * 8 + k;
+  return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
 }
 
 __device__ __forceinline__ int cache_stamp(const Clock* clk) {
@@ -136,6 +138,49 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
   }
 }
 
+// The same refill for the three-point stencil: 32 lanes per particle, lane k
+// < 27 gathers the 19 pulled populations of stencil site k itself.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
+  const T* __restrict__ pop = a.pop[a.clock->cur];
+  const int stamp = cache_stamp(a.clock);
+  const int64_t lanes = a.N * 32;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / 32;
+    const int k = (int)(t & 31);
+    if (k >= Stencil<1>::kSites) continue;
+    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    const int64_t N = a.N;
+    double X[3];
+    bool finite = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      X[d] = a.x[d * N + p];
+      finite = finite && isfinite(X[d]);
+    }
+    if (!finite) continue;
+    Cube q;
+    Stencil<1>::locate(X, m.g, q);
+    int cx, cy, cz, site;
+    double w;
+    Stencil<1>::site(q, m.g, k, cx, cy, cz, site, w);
+    int sidx[19];
+    pull_sources(m.g, cx, cy, cz, sidx);
+    T d[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
+    T drho, jx, jy, jz;
+    moments_deviation<T>(d, drho, jx, jy, jz);
+    *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
+    if (k == 0) {
+      a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+      a.cc_stamp[p] = stamp;
+    }
+    claim_site(a, m.site_off + site);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One MD step (Sec. 3, Eq. 4-8), eight lanes per particle, one per corner of
 // its cube.
@@ -163,36 +208,41 @@ __device__ __forceinline__ double pick3(const double v[3], int c) {
   return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
 }
 
-// Transfer -w_k dP of one particle (Eq. 7-8) from its 8 lanes: pair
-// index 8 r + lane = 3 corner + component, rounds r = 0, 1, 2.
-template <typename T>
+// Transfer -w_k dP of one particle (Eq. 7-8) from its lanes: pair index
+// kLanes r + lane = 3 site + component, rounds r = 0, 1, 2 (24 pairs on 8
+// lanes for the cube, 81 on 32 lanes for the three-point stencil).
+template <typename T, int ST>
 __device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, const RepMD& m,
                                                     const Cube& q, int lane, const double dp[3]) {
 #pragma unroll
   for (int rnd = 0; rnd < 3; ++rnd) {
-    const int pair = rnd * kCornerLanes + lane;
+    const int pair = rnd * Stencil<ST>::kLanes + lane;
+    if (pair >= 3 * Stencil<ST>::kSites) break;
     const int kc = pair / 3, c = pair - 3 * kc;
     int cx, cy, cz, site;
     double w;
-    corner_of(q, m.g, kc, cx, cy, cz, site, w);
+    Stencil<ST>::site(q, m.g, kc, cx, cy, cz, site, w);
     atomicAdd(((T*)(J + m.site_off + site)) + c, (T)(-w * pick3(dp, c)));
   }
 }
 
-template <typename T, bool Rec>
+template <typename T, bool Rec, int ST>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
+  using St = Stencil<ST>;
+  static_assert(!Rec || ST == 0, "recording (adjoint) exists for the trilinear stencil only");
   const T* __restrict__ pop = a.pop[a.clock->cur];
   const int stamp = cache_stamp(a.clock);
   const unsigned long long t_md = (unsigned long long)(a.clock->t_md + a.substep);
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
-  const int64_t lanes = N * kCornerLanes;
-  // lanes come in whole particles (8 | kBlock): the 8 lanes of a particle
+  const int64_t lanes = N * St::kLanes;
+  // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
   // are always active together, as the shuffles require
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
        t += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = t / kCornerLanes;
-    const int k = (int)(t & (kCornerLanes - 1));
+    const int64_t p = t / St::kLanes;
+    const int k = (int)(t & (St::kLanes - 1));
+    const bool act = k < St::kSites;  // lanes past the stencil add zeros
     const int rr = a.single ? 0 : a.part_rep[p];
     double X[3], V[3];
     bool live = true;
@@ -212,15 +262,16 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     }
     const RepMD& m = a.md[rr];
     Cube q;
-    cube_of(X, m.g, q);
+    St::locate(X, m.g, q);
     const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-    int cx, cy, cz, site;
-    double w;
-    corner_of(q, m.g, k, cx, cy, cz, site, w);
-    Vec4<T> cv;
+    int cx = 0, cy = 0, cz = 0, site = 0;
+    double w = 0.0;
+    if (act) St::site(q, m.g, k, cx, cy, cz, site, w);
+    Vec4<T> cv{T(0), T(0), T(0), T(0)};
     const bool hit = a.cc_stamp[p] == stamp && a.cc_cell[p] == cell;
-    if (hit) {
-      cv = *cache_entry(a, p, k);
+    if (!act) {
+    } else if (hit) {
+      cv = *cache_entry<ST>(a, p, k);
     } else {
       // left the cube of the refill: this lane gathers its corner
       int sidx[19];
@@ -231,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       T drho, jx, jy, jz;
       moments_deviation<T>(d, drho, jx, jy, jz);
       cv = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-      *cache_entry(a, p, k) = cv;
+      *cache_entry<ST>(a, p, k) = cv;
       claim_site(a, m.site_off + site);
       if (k == 0) {
         a.cc_cell[p] = cell;
@@ -240,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     }
     // fluid velocity at the particle (Eq. 5)
     double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-    if (a.variant >= 2) {
+    if (a.variant >= 2 && act) {
       const Vec4<T> jv = a.J[m.site_off + site];
       jx += (double)jv.x;
       jy += (double)jv.y;
@@ -260,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       }
     }
     const double wi = w * (double)cv.w;
-    const double u[3] = {oct_sum(wi * jx), oct_sum(wi * jy), oct_sum(wi * jz)};
+    const double u[3] = {St::lane_sum(wi * jx), St::lane_sum(wi * jy), St::lane_sum(wi * jz)};
     // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
@@ -299,20 +350,22 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         }
       }
     }
-    if (a.variant == 1) transfer_from_lanes<T>(a.J, m, q, k, dp);
+    if (a.variant == 1) transfer_from_lanes<T, ST>(a.J, m, q, k, dp);
   }
 }
 
-// Variant-2 momentum transfer of the MD step just taken, eight lanes per
-// particle (one per corner; see spread_corner).  With position-dependent
-// forces the same transfer runs inside the force kernel instead.
-template <typename T>
+// Variant-2 momentum transfer of the MD step just taken, one lane per
+// stencil site (see spread_corner).  With position-dependent forces the same
+// transfer runs inside the force kernel instead.
+template <typename T, int ST>
 __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
+  using St = Stencil<ST>;
   const int64_t N = a.N;
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kCornerLanes;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * St::kLanes;
        t += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = t / kCornerLanes;
-    const int k = (int)(t & (kCornerLanes - 1));
+    const int64_t p = t / St::kLanes;
+    const int k = (int)(t & (St::kLanes - 1));
+    if (k >= St::kSites) continue;
     Cube q;
     q.base[0] = a.rec_cell[p];
     if (q.base[0] < 0) continue;
@@ -325,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
       q.s[d] = a.rec_frac[d * N + p];
       dp[d] = a.rec_dp[d * N + p];
     }
-    spread_corner<T>(a.J, a.shared_site, m, q, k, dp);
+    spread_corner<T, ST>(a.J, a.shared_site, m, q, k, dp);
   }
 }
 
@@ -367,28 +420,38 @@ static int grid_for(int64_t work_blocks, int tuned) {
   return (int)std::max<int64_t>(g, 1);
 }
 
-template <typename T>
-static hipError_t couple_t(Context* c, int substep) {
+template <typename T, int ST>
+static hipError_t launch_refill_st(Context* c, const CoupleArgs<T>& a) {
+  const dim3 grid(grid_for((a.N * 32 + kBlock - 1) / kBlock, c->tune.part_blocks));
+  if (ST == 0)
+    hipLaunchKernelGGL(k_refill<T>, grid, dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(k_refill3<T>, grid, dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, int ST>
+static hipError_t couple_st(Context* c, int substep) {
+  using St = Stencil<ST>;
   CoupleArgs<T> a = couple_args<T>(c, substep);
   hipError_t e;
   const int64_t N = a.N;
-  if (substep == 0) {
-    hipLaunchKernelGGL(k_refill<T>,
-                       dim3(grid_for((N * kRefillLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
-                       dim3(kBlock), 0, c->stream, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  const dim3 cgrid(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
-  if (a.rec)
-    hipLaunchKernelGGL((k_couple<T, true>), cgrid, dim3(kBlock), 0, c->stream, a);
+  if (substep == 0 && (e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
+  const dim3 cgrid(grid_for((N * St::kLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
+  if (ST == 0 && a.rec)
+    hipLaunchKernelGGL((k_couple<T, true, 0>), cgrid, dim3(kBlock), 0, c->stream, a);
   else
-    hipLaunchKernelGGL((k_couple<T, false>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, false, ST>), cgrid, dim3(kBlock), 0, c->stream, a);
   // variants 2 and 3: the transfer waits until every particle has read J;
   // with position-dependent forces it runs inside the force kernel
   if ((e = hipGetLastError()) != hipSuccess || a.variant == 1 || c->plan.any_forces2) return e;
-  const dim3 sgrid(grid_for((N * kCornerLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
-  hipLaunchKernelGGL(k_spread<T>, sgrid, dim3(kBlock), 0, c->stream, a);
+  hipLaunchKernelGGL((k_spread<T, ST>), cgrid, dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t couple_t(Context* c, int substep) {
+  return c->p[0].stencil == 1 ? couple_st<T, 1>(c, substep) : couple_st<T, 0>(c, substep);
 }
 
 hipError_t launch_couple(Context* c, int substep) {
@@ -399,10 +462,7 @@ hipError_t launch_couple(Context* c, int substep) {
 template <typename T>
 static hipError_t refill_t(Context* c) {
   CoupleArgs<T> a = couple_args<T>(c, 0);
-  hipLaunchKernelGGL(k_refill<T>,
-                     dim3(grid_for((a.N * kRefillLanes + kBlock - 1) / kBlock, c->tune.part_blocks)),
-                     dim3(kBlock), 0, c->stream, a);
-  return hipGetLastError();
+  return c->p[0].stencil == 1 ? launch_refill_st<T, 1>(c, a) : launch_refill_st<T, 0>(c, a);
 }
 
 // The corner-cache refill alone (reads particle positions, writes only the

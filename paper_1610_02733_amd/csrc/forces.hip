@@ -135,9 +135,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
 // stores the force and, after an MD step, applies the second half-kick of
 // velocity Verlet (new conservative force + the coupling force held over the
-// step).  In variants 2 and 3 lanes 0-7 also transfer the step's momentum to
-// the 8 cube corners (the spreading of k_spread): this kernel runs after
-// every particle of the step has read the transfer field.
+// step).  In variants 2 and 3 the first lanes (8, or 27 for the three-point
+// stencil) also transfer the step's momentum to the stencil sites (the
+// spreading of k_spread): this kernel runs after every particle of the step
+// has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
         }
       }
     }
-    if (Spread && lane < 8) {
+    if (Spread && lane < (m.stencil ? Stencil<1>::kSites : Stencil<0>::kSites)) {
       Cube q;
       q.base[0] = a.rec_cell[p];
       if (q.base[0] >= 0) {
@@ -279,7 +280,10 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
           q.s[d] = a.rec_frac[d * N + p];
           dp[d] = a.rec_dp[d * N + p];
         }
-        spread_corner<T>(a.J, a.shared_site, m, q, lane, dp);
+        if (m.stencil)
+          spread_corner<T, 1>(a.J, a.shared_site, m, q, lane, dp);
+        else
+          spread_corner<T, 0>(a.J, a.shared_site, m, q, lane, dp);
       }
     }
   }

@@ -41,6 +41,7 @@ struct RepMD {
   int part_off, N;
   int cell_off;  // first force cell of the replica
   int variant, noise, split_kick, force_model, chain_len;
+  int stencil;  // 0 trilinear (8 sites), 1 three-point kernel (27 sites)
   uint32_t key0, key1, tag;
   double rho0, gamma, amp, tau, h;
   double L[3];

@@ -79,20 +79,92 @@ __device__ __forceinline__ double oct_sum(double v) {  // over the 8 lanes of a 
   return v;
 }
 
-// Variant-2 transfer -w_k dP of one particle to corner k of its cube (Eq.
+// ---------------------------------------------------------------------------
+// Interpolation / spreading stencils (Eq. 5 and Eq. 7 use the same one).
+// A particle's stencil is described by a Cube: the lowest site index per
+// axis (wrapped) and the offset s of the particle from a reference site.
+//   ST = 0, trilinear: the 8 corners of the cube with lower corner floor(X),
+//     s = X - floor(X); one lane per corner (8 lanes).
+//   ST = 1, three-point kernel per axis (Roma, Peskin and Berger 1999; the
+//     higher-order scheme the paper mentions, Sec. 4): the 3 sites nearest
+//     along each axis, c - 1, c, c + 1 with c = floor(X + 1/2), s = X - c;
+//     the axis weight of a site at distance r from the particle is
+//       (1 + sqrt(1 - 3 r^2)) / 3                for |r| <= 1/2,
+//       (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6 for 1/2 <= |r| <= 3/2;
+//     27 sites, one lane each in groups of 32 (lanes 27-31 idle).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double kernel3(double r) {
+  const double a = fabs(r);
+  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) * (1.0 / 3.0);
+  const double b = 1.0 - a;  // |r| < 3/2 always holds for the three nearest sites
+  return (5.0 - 3.0 * a - sqrt(1.0 - 3.0 * b * b)) * (1.0 / 6.0);
+}
+
+template <int ST>
+struct Stencil;
+
+template <>
+struct Stencil<0> {
+  static constexpr int kSites = 8, kLanes = 8;
+  __device__ static __forceinline__ void locate(const double X[3], const Geom& g, Cube& q) {
+    cube_of(X, g, q);
+  }
+  __device__ static __forceinline__ void site(const Cube& q, const Geom& g, int k, int& cx,
+                                              int& cy, int& cz, int& s, double& w) {
+    corner_of(q, g, k, cx, cy, cz, s, w);
+  }
+  __device__ static __forceinline__ double lane_sum(double v) { return oct_sum(v); }
+};
+
+template <>
+struct Stencil<1> {
+  static constexpr int kSites = 27, kLanes = 32;
+  __device__ static __forceinline__ void locate(const double X[3], const Geom& g, Cube& q) {
+    const int n3[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double c = floor(X[d] + 0.5);
+      q.s[d] = X[d] - c;
+      q.base[d] = cell_of((int)c - 1, n3[d]);
+    }
+  }
+  __device__ static __forceinline__ void site(const Cube& q, const Geom& g, int k, int& cx,
+                                              int& cy, int& cz, int& s, double& w) {
+    const int ox = k % 3, oy = (k / 3) % 3, oz = k / 9;
+    cx = q.base[0] + ox;
+    cy = q.base[1] + oy;
+    cz = q.base[2] + oz;
+    cx = cx >= g.nx ? cx - g.nx : cx;
+    cy = cy >= g.ny ? cy - g.ny : cy;
+    cz = cz >= g.nz ? cz - g.nz : cz;
+    s = cx + g.nx * (cy + g.ny * cz);
+    w = kernel3(q.s[0] - (double)(ox - 1)) * kernel3(q.s[1] - (double)(oy - 1)) *
+        kernel3(q.s[2] - (double)(oz - 1));
+  }
+  __device__ static __forceinline__ double lane_sum(double v) {  // over 32 lanes
+    v += __shfl_xor(v, 1, 32);
+    v += __shfl_xor(v, 2, 32);
+    v += __shfl_xor(v, 4, 32);
+    v += __shfl_xor(v, 8, 32);
+    v += __shfl_xor(v, 16, 32);
+    return v;
+  }
+};
+
+// Variant-2 transfer -w_k dP of one particle to site k of its stencil (Eq.
 // 7-8).  Every site a transfer reaches was claimed by the transferring
 // particle in this LB interval before the transfer runs, so a site without
 // the shared flag has a single writer and takes a plain read-modify-write of
 // its vector; shared sites take atomic adds.  Either way the site receives
 // the same rounded values.
-template <typename T>
+template <typename T, int ST = 0>
 __device__ __forceinline__ void spread_corner(Vec4<T>* __restrict__ J,
                                               const unsigned long long* __restrict__ shared_site,
                                               const RepMD& m, const Cube& q, int k,
                                               const double dp[3]) {
   int cx, cy, cz, site;
   double w;
-  corner_of(q, m.g, k, cx, cy, cz, site, w);
+  Stencil<ST>::site(q, m.g, k, cx, cy, cz, site, w);
   const int gs = m.site_off + site;
   const T ax = (T)(-w * dp[0]), ay = (T)(-w * dp[1]), az = (T)(-w * dp[2]);
   if ((shared_site[gs >> 6] >> (gs & 63)) & 1ull) {

@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("body_force", C.c_double * 3), ("f_ext", C.c_double * 3),
         ("k_bond", C.c_double), ("r0_bond", C.c_double),
         ("wca_eps", C.c_double), ("wca_sigma", C.c_double),
+        ("stencil", C.c_int32),
     ]
 
 
@@ -115,7 +116,8 @@ def lib():
 DEFAULTS = dict(n_sub=1, variant=2, precision=32, n_particles=0, force_model=0, chain_len=1,
                 replica=0, seed=0, rho0=1.0, nu=1.0 / 6.0, nu_bulk=-1.0, gamma_ghost=0.0,
                 kT=0.0, friction=0.0, particle_mass=1.0, body_force=(0.0, 0.0, 0.0),
-                f_ext=(0.0, 0.0, 0.0), k_bond=0.0, r0_bond=1.0, wca_eps=0.0, wca_sigma=1.0)
+                f_ext=(0.0, 0.0, 0.0), k_bond=0.0, r0_bond=1.0, wca_eps=0.0, wca_sigma=1.0,
+                stencil=0)
 
 
 def stream_copy(dst, src, stream=None):

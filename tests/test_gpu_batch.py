@@ -57,7 +57,7 @@ def test_run_cycles_equals_stepwise(lb, orc, variant):
     assert rel_pop(g.populations().cpu().numpy() + w[:, None], o.populations(), w, 1.0) < 1e-12
 
 
-def make_replicas(nrep, prec, variant, seed=11):
+def make_replicas(nrep, prec, variant, seed=11, stencil=0):
     rng = np.random.default_rng(seed)
     reps, xs, vs = [], [], []
     for r in range(nrep):
@@ -66,7 +66,7 @@ def make_replicas(nrep, prec, variant, seed=11):
         n = int(rng.integers(0, 40)) if r != 1 else 0  # one replica without particles
         kw = dict(precision=prec, n_sub=4, variant=variant, kT=1e-3, seed=7 + r, replica=r,
                   n_particles=n, friction=float(rng.uniform(0.5, 3.0)),
-                  nu=float(rng.uniform(0.1, 0.5)))
+                  nu=float(rng.uniform(0.1, 0.5)), stencil=stencil)
         x, v = wl.free_particles(shape, n, 1e-3, 1.0, 100 + r)
         reps.append((shape, kw))
         xs.append(x)
@@ -102,10 +102,10 @@ def test_batch_replicas_match_single_runs(lb, orc, prec, variant):
         assert np.allclose(tot[r, 7:11], ts[7:11], rtol=mtol, atol=1e-12)
 
 
-@pytest.mark.parametrize("variant", [2, 3])
-def test_batch_replicas_match_oracle(lb, orc, variant):
+@pytest.mark.parametrize("variant,stencil", [(2, 0), (3, 0), (2, 1)])
+def test_batch_replicas_match_oracle(lb, orc, variant, stencil):
     c, w, e, b = orc.tables()
-    reps, xs, vs = make_replicas(4, 64, variant, seed=5)
+    reps, xs, vs = make_replicas(4, 64, variant, seed=5, stencil=stencil)
     B = lb.Batch(reps)
     B.bind_particles(xs, vs)
     B.run_cycles(5)

@@ -381,3 +381,63 @@ def test_variant3_get_set_mid_interval(lb, prec):
     tol = 1e-13 if prec == 64 else 2e-6
     assert np.abs(runs[0][0] - runs[1][0]).max() < tol
     assert np.abs(runs[0][1] - runs[1][1]).max() < tol * 10
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_three_point_stencil_coupled(lb, orc, prec, variant):
+    """The higher-order stencil (three-point kernel per axis, 27 sites) for
+    both the interpolation (Eq. 5) and the spreading (Eq. 7): the c1 case,
+    100 LB steps, against the oracle."""
+    cfg = wl.CONFIGS["c1"]
+    x, v = wl.free_particles(cfg["shape"], cfg["n_particles"], cfg["kT"], 1.0, cfg["seed"])
+    kw = dict(kT=cfg["kT"], nu=cfg["nu"], seed=1, n_particles=cfg["n_particles"],
+              friction=cfg["friction"], n_sub=cfg["n_sub"], variant=variant, stencil=1)
+    g, o, w, rho0 = run_pair(lb, orc, cfg["shape"], cfg["lb_steps"], x=x, v=v, precision=prec,
+                             **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    print(f"c1 three-point stencil variant {variant} fp{prec}: max err / (w rho0) {err:.3e}")
+    assert err < TOL[prec]
+    check_particles(g, o, cfg["shape"], TOL[prec], cfg["kT"])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_three_point_stencil_shared_sites_and_tiny_boxes(lb, orc, prec):
+    """27-site stencils overlap far more often than cubes: 300 particles in a
+    4^3 box (nearly every site shared), and a 2 x 3 x 5 box where the
+    stencil wraps onto itself (the same site twice along x), all variants."""
+    for shape, N in (((4, 4, 4), 300), ((2, 3, 5), 12)):
+        x, v = wl.free_particles(shape, N, 1e-3, 1.0, 19)
+        for variant in (1, 2, 3):
+            kw = dict(kT=1e-3, seed=5, n_particles=N, friction=0.5, n_sub=4, variant=variant,
+                      rho0=2.0, stencil=1)
+            g, o, w, rho0 = run_pair(lb, orc, shape, 6, x=x, v=v, precision=prec, **kw)
+            err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+            assert err < TOL[prec], (shape, variant, err)
+            check_particles(g, o, shape, TOL[prec], 1e-3)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_three_point_stencil_polymer(lb, orc, variant):
+    """Kremer-Grest chains with the three-point stencil: the variant-2
+    transfer then runs from 27 lanes of the force kernel (FP64)."""
+    shape = (20, 20, 20)
+    x, v = wl.chains(shape, 12, 10, 0.01, 1.0, seed=33, bond=0.97, min_dist=0.95)
+    kw = dict(kT=0.01, nu=0.3, seed=9, n_particles=120, friction=2.0, n_sub=10, variant=variant,
+              force_model=3, chain_len=10, k_bond=0.3, r0_bond=1.5, wca_eps=0.01,
+              wca_sigma=1.0, stencil=1)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 10, x=x, v=v, precision=64, **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < TOL[64], err
+    check_particles(g, o, shape, TOL[64] * 10, 0.01)
+
+
+def test_three_point_stencil_rejects_adjoint(lb):
+    import torch
+    g = lb.Lattice((8, 8, 8), precision=64, n_sub=2, variant=2, n_particles=4, friction=1.0,
+                   stencil=1)
+    x = torch.rand(3, 4, dtype=torch.float64) * 8
+    g.bind_particles(x, torch.zeros_like(x))
+    with pytest.raises(lb.LbmdError) as ei:
+        g.adjoint_attach(2)
+    assert ei.value.code == lb.EINVAL
