@@ -79,9 +79,9 @@ def sim_kwargs(cfg, variant):
     return kw
 
 
-def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup):
+def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup, stencil=0):
     shape = cfg["shape"]
-    sim = lbmd.Lattice(shape, **sim_kwargs(cfg, variant))
+    sim = lbmd.Lattice(shape, stencil=stencil, **sim_kwargs(cfg, variant))
     sim.bind_particles(x, v)
     stream = sim.stream
     L = lbmd.lib()
@@ -364,6 +364,8 @@ def main():
                     help="skip the 512-replica batched-ensemble measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the reverse-mode (adjoint) cost measurement")
+    ap.add_argument("--no-stencil3", action="store_true",
+                    help="skip timing the three-point (27-site) interpolation stencil")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -445,6 +447,12 @@ def main():
     if 1 in res and 3 in res:
         out["variant3_ms_per_step"] = round(res[3][0] / args.steps * 1e3, 4)
         out["variant3_over_variant1"] = round(res[3][0] / res[1][0], 4)
+    if not args.no_stencil3 and main_v in res:
+        log(f"three-point stencil, variant {main_v}: {args.warmup} warmup + {args.steps} cycles")
+        w3, k3, f3 = run_variant(lbmd, torch, cfg, main_v, x, v, args.steps, args.warmup,
+                                 stencil=1)
+        out["stencil3"] = {"variant": main_v, "ms_per_step": round(w3 / args.steps * 1e3, 4),
+                           "over_trilinear": round(w3 / res[main_v][0], 4), "finite": f3}
     if not args.no_batch:
         log("batched ensemble: 512 replicas, batched vs serial")
         out["batch"] = batch_measure(lbmd, torch)

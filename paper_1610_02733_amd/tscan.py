@@ -81,7 +81,7 @@ def _start(box, n_chains, chain_len, seed):
 
 
 def scan_batch(variant, n, dt, zetas, *, box=20, n_chains=10, chain_len=256, t_tau=50.0,
-               equil_tau=10.0, sample_tau=0.5, seed=1, precision=32, model="kg",
+               equil_tau=10.0, sample_tau=0.5, seed=1, precision=32, model="kg", stencil=0,
                device="cuda"):
     """One batch: the friction values `zetas` at fixed (variant, n, dt).
     Returns one dict per friction value."""
@@ -93,7 +93,8 @@ def scan_batch(variant, n, dt, zetas, *, box=20, n_chains=10, chain_len=256, t_t
     reps = []
     for r, z in enumerate(zetas):
         kw = dict(precision=precision, n_sub=n, variant=variant, seed=seed, replica=r,
-                  n_particles=N, particle_mass=1.0, chain_len=chain_len, rho0=1.0)
+                  n_particles=N, particle_mass=1.0, chain_len=chain_len, rho0=1.0,
+                  stencil=stencil)
         kw.update(lattice_params(n, dt, z, model))
         reps.append((shape, kw))
     B = lbmd.Batch(reps, device=device)
@@ -114,7 +115,7 @@ def scan_batch(variant, n, dt, zetas, *, box=20, n_chains=10, chain_len=256, t_t
     for r, z in enumerate(zetas):
         col = T[:, r]
         ok = bool(np.isfinite(col).all())
-        out.append(dict(variant=variant, n=n, dt=dt, zeta=float(z),
+        out.append(dict(variant=variant, n=n, dt=dt, zeta=float(z), stencil=stencil,
                         zeta_dt=float(z * dt), T_over_kT=float(np.mean(col)) if ok else None,
                         err=_block_error(col) if ok else None, samples=len(col),
                         cycles=done, finite=ok))
@@ -152,6 +153,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--model", default="kg", choices=["kg", "wca"],
                     help="kg: the paper's Kremer-Grest force field; wca: harmonic + WCA")
+    ap.add_argument("--stencil", type=int, default=0, choices=[0, 1],
+                    help="0: trilinear interpolation; 1: three-point kernel (27 sites)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -163,7 +166,8 @@ def main(argv=None):
         dts=[float(t) for t in args.dts.split(",")],
         zetas=[float(t) for t in args.zetas.split(",")],
         t_tau=args.t_tau, equil_tau=args.equil_tau, sample_tau=args.sample_tau,
-        precision=args.precision, seed=args.seed, model=args.model, log=log, **PAPER_SYSTEM)
+        precision=args.precision, seed=args.seed, model=args.model, stencil=args.stencil,
+        log=log, **PAPER_SYSTEM)
     for r in rows:
         print(json.dumps(r), flush=True)
 
