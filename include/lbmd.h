@@ -139,6 +139,24 @@ int lb_destroy(lbmd *c);
 int lbmd_bind_particles(lbmd *c, void *d_x, void *d_v, int32_t *d_img);
 
 /*
+ * Reorder the bound particles along a space-filling curve (Morton order of
+ * the 4 x 4 x 4-site tiles their positions fall in, within each replica;
+ * stable and deterministic).  The method is unchanged: particles are
+ * independent apart from the fluid, so only their storage order moves,
+ * which lets the particle kernels of Sec. 3 (interpolation, spreading)
+ * share cache lines between neighbours.  x, v and img are permuted in place
+ * in the caller's buffers; d_perm (nullable, device int32[Ntot]) receives
+ * the permutation: new index t holds the particle that had index d_perm[t].
+ * Each particle keeps its identity (its index at binding), which the
+ * particle noise counter follows, so a reordered run is the same run up to
+ * the rounding order of the transfer sums.  Only at an
+ * LB-step boundary (LBMD_ESTATE otherwise, or while an adjoint segment is
+ * recorded), for force models 0 and 1 (bonded chains follow the index
+ * order: LBMD_EINVAL).  LBMD_ENOSPACE if the sort's scratch is too small.
+ */
+int lbmd_sort_particles(lbmd *c, int32_t *d_perm);
+
+/*
  * One MD step of the coupled system (Sec. 3, Eq. 4-8): for every particle,
  * from start-of-step values, interpolate the fluid velocity at its position
  * over the 8 sites of its cube (Eq. 5), form F = -gamma (v - u) + F_rand

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmd.so")
-SOURCES = ["api.hip", "lattice.hip", "couple.hip", "forces.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "lattice.hip", "couple.hip", "forces.hip", "adjoint.hip", "sort.hip"]
 HEADERS = ["lbmd_device.hpp", "lbmd_internal.hpp", "particle_geom.hpp", "forcing.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

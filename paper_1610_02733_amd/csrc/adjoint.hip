@@ -136,6 +136,7 @@ struct AdjMDArgs {
   double* __restrict__ ubar;
   double* __restrict__ pacc;       // [4][N]
   const RepMD* __restrict__ md;
+  const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
   int64_t N;
   long long t_md;                  // MD step being reversed
 };
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
     for (int d = 0; d < 3; ++d) u[d] = oct_sum(w * ir * U[d]);
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
-      const Words4 o = philox10(Words4{(uint32_t)p, step_lo, m.tag, step_hi}, m.key0, m.key1);
+      const Words4 o = philox10(Words4{(uint32_t)a.pid[p], step_lo, m.tag, step_hi}, m.key0,
+                                m.key1);
       const uint32_t ws[3] = {o.w0, o.w1, o.w2};
 #pragma unroll
       for (int d = 0; d < 3; ++d)
@@ -336,6 +338,7 @@ static AdjMDArgs md_adjoint_args(Context* c) {
   a.ubar = (double*)(s.ws + L.ubar);
   a.pacc = (double*)(s.ws + L.pacc);
   a.md = (const RepMD*)at(c, c->plan.lay.rep_md);
+  a.pid = (const int32_t*)at(c, c->plan.lay.pid);
   a.N = c->plan.Ntot;
   a.t_md = (long long)(s.t_md[s.slot] + s.sub);
   return a;

@@ -103,6 +103,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.rep_md = o; o = up(o + (size_t)R * sizeof(RepMD));
   L.item_rep = o; o = up(o + (size_t)(R + 1) * 4);
   L.part_rep = o; o = up(o + N * 4);
+  L.pid = o; o = up(o + N * 4);
   L.clock = o; o = up(o + sizeof(Clock));
   L.fcons = o; o = up(o + 3 * N * 8);
   L.rec_cell = o; o = up(o + 3 * N * 4);
@@ -119,6 +120,9 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.bin_of = o; o = up(o + N * 4);
   L.bin_rank = o; o = up(o + N * 4);
   L.bin_sorted = o; o = up(o + N * 4);
+  L.sort_keys = o; o = up(o + 2 * N * 8);
+  L.sort_vals = o; o = up(o + 2 * N * 4);
+  L.sort_temp = o; o = up(o + sort_temp_bytes((int64_t)N));
   L.flags = o; o = up(o + 16 * 4);
   L.partials = o; o = up(o + (size_t)pl.nitems * kRedWidth * 8);
   L.totals = o; o = up(o + (size_t)R * kRedWidth * 8);
@@ -368,7 +372,22 @@ int lbmd_bind_particles(lbmd* c, void* d_x, void* d_v, int32_t* d_img) {
   c->img = d_img;
   c->bound = c->plan.Ntot > 0;
   drop_graph(c);
+  int rc = fail(c, launch_init_pid(c));
+  if (rc) return rc;
   return fail(c, launch_init_forces(c));
+}
+
+int lbmd_sort_particles(lbmd* c, int32_t* d_perm) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  for (int r = 0; r < c->plan.R; ++r)
+    if (c->p[r].force_model >= 2) return LBMD_EINVAL;  // bonds follow the particle order
+  if (c->plan.Ntot == 0) return LBMD_OK;
+  if (!c->bound || c->subs != 0 || c->rec_part) return LBMD_ESTATE;
+  bool too_small = false;
+  const int rc = fail(c, launch_sort_particles(c, d_perm, &too_small));
+  if (rc) return rc;
+  return too_small ? LBMD_ENOSPACE : LBMD_OK;
 }
 
 int md_couple_substep(lbmd* c) {
@@ -555,7 +574,7 @@ namespace {
 // the context), particle positions, velocities and image counts.  Taken at
 // an LB-step boundary, where the transfer field is empty.
 struct StateLayout {
-  size_t counters, pop, x, v, img, total;
+  size_t counters, pop, x, v, img, pid, total;
 };
 
 StateLayout state_layout(const Context* c) {
@@ -568,6 +587,7 @@ StateLayout state_layout(const Context* c) {
   s.x = o; o = up(o + 3 * N * 8);
   s.v = o; o = up(o + 3 * N * 8);
   s.img = o; o = up(o + 3 * N * 4);
+  s.pid = o; o = up(o + N * 4);
   s.total = o;
   return s;
 }
@@ -616,6 +636,9 @@ int load_common(lbmd* c, const char* src, const StateLayout& sl) {
     if (!rc)
       rc = fail(c, hipMemcpyAsync(c->img, src + sl.img, 3 * N * 4, hipMemcpyDeviceToDevice,
                                   c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(at(c, c->plan.lay.pid), src + sl.pid, N * 4,
+                                  hipMemcpyDeviceToDevice, c->stream));
     if (rc) return rc;
   }
   const size_t t = c->plan.prec == 32 ? 4 : 8;
@@ -659,6 +682,9 @@ int lbmd_save_state(lbmd* c, void* d_dst) {
     if (!rc)
       rc = fail(c, hipMemcpyAsync(dst + sl.img, c->img, 3 * N * 4, hipMemcpyDeviceToDevice,
                                   c->stream));
+    if (!rc)
+      rc = fail(c, hipMemcpyAsync(dst + sl.pid, at(c, c->plan.lay.pid), N * 4,
+                                  hipMemcpyDeviceToDevice, c->stream));
   }
   return rc;
 }

@@ -34,6 +34,7 @@ struct CoupleArgs {
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
+  const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
   const Clock* __restrict__ clock;
   double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
   size_t P;     // population stride
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
-      const uint32_t lp = (uint32_t)(p - m.part_off);
+      const uint32_t lp = (uint32_t)a.pid[p];
       const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
       const uint32_t ws[3] = {o.w0, o.w1, o.w2};
 #pragma unroll
@@ -405,6 +406,7 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
+  a.pid = (const int32_t*)at(c, L.pid);
   a.clock = (const Clock*)at(c, L.clock);
   a.rec = c->rec_part ? c->rec_part + (size_t)substep * kAdjRec * (size_t)c->plan.Ntot : nullptr;
   a.P = (size_t)c->plan.Stot;

@@ -69,6 +69,8 @@ struct Layout {
   size_t rep_md;     // [R] RepMD
   size_t item_rep;   // [R + 1] int32: work-item offsets (prefix) for the LB kernels
   size_t part_rep;   // [Ntot] int32: replica of each particle
+  size_t pid;        // [Ntot] int32: replica-local identity of the particle in each slot
+                     // (its index at binding; the particle noise counter follows it)
   size_t clock;      // Clock
   size_t fcons;      // [3][Ntot] double: conservative force at the current positions
   size_t rec_cell;   // [3][Ntot] int32: lower corner of the particle's cube (-1: skipped)
@@ -85,6 +87,9 @@ struct Layout {
   size_t bin_of;     // [Ntot] int32: global force cell of each particle (-1: none)
   size_t bin_rank;   // [Ntot] int32: slot inside the cell
   size_t bin_sorted; // [Ntot] int32: particles ordered by cell
+  size_t sort_keys;  // [2][Ntot] uint64: spatial sort keys (in, out)
+  size_t sort_vals;  // [2][Ntot] int32: particle indices (in, out = the permutation)
+  size_t sort_temp;  // radix-sort temporary storage
   size_t flags;      // int32[16]: [0] non-finite particle seen
   size_t partials;   // double[nitems][kRedWidth]
   size_t totals;     // double[R][kRedWidth]
@@ -184,6 +189,8 @@ hipError_t launch_adjoint_fold(Context* c);
 hipError_t launch_store_counters(Context* c, void* dst, int64_t t_lb, int64_t t_md);
 hipError_t launch_clock_advance(Context* c);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+size_t sort_temp_bytes(int64_t N);
+hipError_t launch_sort_particles(Context* c, int32_t* d_perm, bool* too_small);
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
 hipError_t launch_get_populations(Context* c, int rep, void* dst);
 hipError_t launch_set_populations(Context* c, int rep, const void* src);
@@ -191,6 +198,7 @@ hipError_t launch_get_transfer(Context* c, int rep, void* dst);
 hipError_t launch_couple(Context* c, int substep);
 hipError_t launch_couple_refill_only(Context* c);
 hipError_t launch_init_forces(Context* c);
+hipError_t launch_init_pid(Context* c);
 hipError_t invalidate_corner_cache(Context* c);
 hipError_t launch_forces(Context* c);
 hipError_t launch_forces_and_kick(Context* c);

@@ -99,7 +99,8 @@ def lib():
         L.lb_step_adjoint.argtypes = [P]
         L.md_couple_substep_adjoint.argtypes = [P]
         L.lbmd_adjoint_result.argtypes = [P, P, P, P]
-        for n in ("lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
+        L.lbmd_sort_particles.argtypes = [P, P]
+        for n in ("lbmd_sort_particles", "lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
                   "lb_step", "lb_moments", "lbmd_get_populations", "lbmd_set_populations",
                   "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters",
                   "lbmd_run_cycles", "lb_create_batch", "lbmd_replica_count",
@@ -218,6 +219,14 @@ class _System:
             rc = L.lb_step(self._h)
             if rc != OK:
                 raise LbmdError(rc, "lb_step")
+
+    def sort_particles(self):
+        """Reorder the bound particles spatially (Morton order of 4^3-site
+        tiles, per replica) in place; returns the permutation (new index t
+        holds old particle perm[t])."""
+        perm = torch.empty(max(self.N, 1), dtype=torch.int32, device=self.device)
+        _check(lib().lbmd_sort_particles(self._h, _ptr(perm)), "lbmd_sort_particles")
+        return perm[: self.N]
 
     def run_cycles(self, ncycles=1):
         """The same cycles replayed from one captured HIP graph."""

@@ -441,3 +441,89 @@ def test_three_point_stencil_rejects_adjoint(lb):
     with pytest.raises(lb.LbmdError) as ei:
         g.adjoint_attach(2)
     assert ei.value.code == lb.EINVAL
+
+
+def _morton_tile_keys(x, shape, rep=None):
+    """Z-order index of each particle's 4^3-site tile (written out here from
+    the definition: bit b of the x, y, z tile coordinates goes to bit 3b,
+    3b + 1, 3b + 2)."""
+    t = (np.floor(x).astype(np.int64) % np.asarray(shape)[:, None]) >> 2
+    key = np.zeros(x.shape[1], np.int64)
+    for b in range(12):
+        for d in range(3):
+            key |= ((t[d] >> b) & 1) << (3 * b + d)
+    return key
+
+
+def test_sort_particles_is_a_spatial_permutation(lb):
+    import torch
+    shape = (40, 36, 28)
+    x, v = wl.free_particles(shape, 3000, 1e-3, 1.0, 4)
+    g = lb.Lattice(shape, precision=32, n_sub=3, variant=2, kT=1e-3, n_particles=3000,
+                   friction=1.0, seed=2)
+    g.bind_particles(x, v)
+    g.cycle(2)
+    x0, v0, i0 = (t.cpu().numpy().copy() for t in (g.x, g.v, g.img))
+    perm = g.sort_particles().cpu().numpy()
+    assert sorted(perm.tolist()) == list(range(3000))
+    assert (g.x.cpu().numpy() == x0[:, perm]).all() and (g.v.cpu().numpy() == v0[:, perm]).all()
+    assert (g.img.cpu().numpy() == i0[:, perm]).all()
+    key = _morton_tile_keys(g.x.cpu().numpy(), shape)
+    assert (np.diff(key) >= 0).all()
+    # stable: equal keys keep their previous order
+    same = np.diff(key) == 0
+    assert (np.diff(perm)[same] > 0).all()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_sorted_run_matches_oracle_with_permuted_particles(lb, orc, variant):
+    """Sorting moves particles between storage slots and nothing else: each
+    keeps its identity, which its noise follows.  The expected order is
+    computed here (stable sort of the Z-order tile keys) and the GPU must
+    produce exactly that permutation; a run sorted at two LB-step boundaries
+    must equal the oracle's unsorted run, slot for particle (FP64)."""
+    shape = (12, 10, 8)
+    x, v = wl.free_particles(shape, 80, 1e-3, 1.0, 7)
+    kw = dict(kT=1e-3, seed=3, n_particles=80, friction=1.5, n_sub=4, variant=variant)
+    g = lb.Lattice(shape, precision=64, **kw)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    ref = np.argsort(_morton_tile_keys(x, shape), kind="stable")
+    assert (g.sort_particles().cpu().numpy() == ref).all()
+    g.cycle(6)
+    o.cycle(6)
+    ref2 = np.argsort(_morton_tile_keys(o.particles()[0][:, ref], shape), kind="stable")
+    assert (g.sort_particles().cpu().numpy() == ref2).all()
+    g.cycle(4)
+    o.cycle(4)
+    slot = ref[ref2]  # original index of the particle in each slot
+    xo, vo, io = o.particles()
+    L = np.asarray(shape, float)[:, None]
+    xg = g.x.cpu().numpy() + L * g.img.cpu().numpy()
+    assert np.abs(xg - (xo + L * io)[:, slot]).max() < 1e-12 * max(shape)
+    assert np.abs(g.v.cpu().numpy() - vo[:, slot]).max() < 1e-12 * max(np.abs(vo).max(), 1e-3 ** 0.5)
+    c, w, e, b = orc.tables()
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < 1e-12, err
+
+
+def test_sort_particles_state_and_model_errors(lb):
+    import torch
+    shape = (8, 8, 8)
+    x, v = wl.chains(shape, 2, 5, 1e-3, 1.0, seed=1, bond=0.97)
+    g = lb.Lattice(shape, precision=64, n_sub=2, variant=2, n_particles=10, force_model=2,
+                   chain_len=5, k_bond=1.0, wca_eps=1e-3)
+    g.bind_particles(x, v)
+    with pytest.raises(lb.LbmdError) as ei:
+        g.sort_particles()
+    assert ei.value.code == lb.EINVAL
+    x, v = wl.free_particles(shape, 10, 1e-3, 1.0, 1)
+    g = lb.Lattice(shape, precision=64, n_sub=2, variant=2, n_particles=10, friction=1.0)
+    g.bind_particles(x, v)
+    g.md_couple_substep()
+    with pytest.raises(lb.LbmdError) as ei:
+        g.sort_particles()
+    assert ei.value.code == lb.ESTATE
+    torch.cuda.synchronize()
