@@ -183,23 +183,26 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// One MD step (Sec. 3, Eq. 4-8), eight lanes per particle, one per corner of
-// its cube.
+// One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
+// ceil(sites / L) sites of its stencil (cube: L = 8 in variant 1, where
+// every lane has one corner, and L = 4 with two corners each in variants 2
+// and 3; three-point stencil: L = 32, one site each).
 //
-// Each lane fetches its corner's cached moments (a particle that left its
-// cube since the refill gathers the new corners itself, one corner per lane)
-// and, in variants 2 and 3, the corner's pending transfer; the interpolated fluid
-// velocity (Eq. 5) is the sum over the eight lanes (butterfly shuffles, the
-// same order on every lane).  Friction + noise (Eq. 4, 6) and velocity
-// Verlet are evaluated on all eight lanes alike; lane 0 stores the particle.
-// Variant 1 then transfers the momentum right away (Eq. 7-8): the 24
-// (corner, component) adds of a particle are spread over its 8 lanes in
-// three rounds, so the lanes of one atomic instruction share a few sites
-// rather than touching 64 unrelated cache lines.  Variants 2 and 3 store
-// (cube, dP) for the spreading kernel instead, because every particle must
-// first read the velocities as of the end of the previous MD step (variant 3
-// sees the same velocities as variant 2 inside an interval; its transfer
-// differs only in how the LB step applies it).
+// Each lane fetches its sites' cached moments (a particle that left its
+// cube since the refill gathers the new sites itself) and, in variants 2 and
+// 3, the sites' pending transfer; the interpolated fluid velocity (Eq. 5)
+// is the sum over the lanes (butterfly shuffles, the same order on every
+// lane).  Friction + noise (Eq. 4, 6) and velocity Verlet are evaluated on
+// all lanes alike; lane 0 stores the particle.  Variant 1 then transfers
+// the momentum right away (Eq. 7-8): the (site, component) adds of a
+// particle are spread over its lanes in rounds, so the lanes of one atomic
+// instruction share a few sites rather than touching 64 unrelated cache
+// lines (eight lanes measured faster here than four).  Variants 2 and 3
+// store (cube, dP) for the spreading kernel instead, because every particle
+// must first read the velocities as of the end of the previous MD step
+// (variant 3 sees the same velocities as variant 2 inside an interval; its
+// transfer differs only in how the LB step applies it); there four lanes
+// with two corners each halve the redundant per-particle arithmetic.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
@@ -209,16 +212,30 @@ __device__ __forceinline__ double pick3(const double v[3], int c) {
   return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
 }
 
+// Lanes of the coupling kernel per particle: L lanes with ceil(sites / L)
+// stencil sites each (8 for the cube in variant 1, whose in-kernel transfer
+// spreads its atomics over the lanes; fewer in variants 2 and 3; 32 for the
+// three-point stencil).
+template <int L>
+struct CoupleShape {
+  static constexpr int kLanes = L;
+  __device__ static __forceinline__ double sum(double v) {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o, L);
+    return v;
+  }
+};
+
 // Transfer -w_k dP of one particle (Eq. 7-8) from its lanes: pair index
-// kLanes r + lane = 3 site + component, rounds r = 0, 1, 2 (24 pairs on 8
-// lanes for the cube, 81 on 32 lanes for the three-point stencil).
-template <typename T, int ST>
+// kLanes r + lane = 3 site + component, over as many rounds as needed.
+template <typename T, int ST, int L>
 __device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, const RepMD& m,
                                                     const Cube& q, int lane, const double dp[3]) {
+  constexpr int kL = L, kPairs = 3 * Stencil<ST>::kSites;
 #pragma unroll
-  for (int rnd = 0; rnd < 3; ++rnd) {
-    const int pair = rnd * Stencil<ST>::kLanes + lane;
-    if (pair >= 3 * Stencil<ST>::kSites) break;
+  for (int rnd = 0; rnd < (kPairs + kL - 1) / kL; ++rnd) {
+    const int pair = rnd * kL + lane;
+    if (pair >= kPairs) break;
     const int kc = pair / 3, c = pair - 3 * kc;
     int cx, cy, cz, site;
     double w;
@@ -227,23 +244,24 @@ __device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, con
   }
 }
 
-template <typename T, bool Rec, int ST>
+template <typename T, bool Rec, int ST, int L>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
+  using Sh = CoupleShape<L>;
+  constexpr int kPer = (St::kSites + L - 1) / L;
   static_assert(!Rec || ST == 0, "recording (adjoint) exists for the trilinear stencil only");
   const T* __restrict__ pop = a.pop[a.clock->cur];
   const int stamp = cache_stamp(a.clock);
   const unsigned long long t_md = (unsigned long long)(a.clock->t_md + a.substep);
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
-  const int64_t lanes = N * St::kLanes;
+  const int64_t lanes = N * Sh::kLanes;
   // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
   // are always active together, as the shuffles require
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
        t += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = t / St::kLanes;
-    const int k = (int)(t & (St::kLanes - 1));
-    const bool act = k < St::kSites;  // lanes past the stencil add zeros
+    const int64_t p = t / Sh::kLanes;
+    const int k0 = (int)(t & (Sh::kLanes - 1));
     const int rr = a.single ? 0 : a.part_rep[p];
     double X[3], V[3];
     bool live = true;
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       live = live && isfinite(X[d]) && isfinite(V[d]);
     }
     if (!live) {
-      if (k == 0) {
+      if (k0 == 0) {
         a.flags[0] = 1;
         if (a.variant >= 2) a.rec_cell[p] = -1;
         if (Rec) a.rec[p] = __builtin_nan("");
@@ -265,54 +283,62 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     Cube q;
     St::locate(X, m.g, q);
     const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-    int cx = 0, cy = 0, cz = 0, site = 0;
-    double w = 0.0;
-    if (act) St::site(q, m.g, k, cx, cy, cz, site, w);
-    Vec4<T> cv{T(0), T(0), T(0), T(0)};
     const bool hit = a.cc_stamp[p] == stamp && a.cc_cell[p] == cell;
-    if (!act) {
-    } else if (hit) {
-      cv = *cache_entry<ST>(a, p, k);
-    } else {
-      // left the cube of the refill: this lane gathers its corner
-      int sidx[19];
-      pull_sources(m.g, cx, cy, cz, sidx);
-      T d[19];
+    double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
-      T drho, jx, jy, jz;
-      moments_deviation<T>(d, drho, jx, jy, jz);
-      cv = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-      *cache_entry<ST>(a, p, k) = cv;
-      claim_site(a, m.site_off + site);
-      if (k == 0) {
-        a.cc_cell[p] = cell;
-        a.cc_stamp[p] = stamp;
-      }
-    }
-    // fluid velocity at the particle (Eq. 5)
-    double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-    if (a.variant >= 2 && act) {
-      const Vec4<T> jv = a.J[m.site_off + site];
-      jx += (double)jv.x;
-      jy += (double)jv.y;
-      jz += (double)jv.z;
-    }
-    if (Rec) {
-      a.rec[(6 + 3 * k) * N + p] = jx;
-      a.rec[(7 + 3 * k) * N + p] = jy;
-      a.rec[(8 + 3 * k) * N + p] = jz;
-      a.rec[(30 + k) * N + p] = (double)cv.w;
-      if (k == 0) {
+    for (int jj = 0; jj < kPer; ++jj) {
+      const int k = k0 + jj * Sh::kLanes;
+      if (k >= St::kSites) break;
+      int cx, cy, cz, site;
+      double w;
+      St::site(q, m.g, k, cx, cy, cz, site, w);
+      Vec4<T> cv;
+      if (hit) {
+        cv = *cache_entry<ST>(a, p, k);
+      } else {
+        // left the cube of the refill: this lane gathers its site
+        int sidx[19];
+        pull_sources(m.g, cx, cy, cz, sidx);
+        T d[19];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          a.rec[d * N + p] = X[d];
-          a.rec[(3 + d) * N + p] = V[d];
+        for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
+        T drho, jx, jy, jz;
+        moments_deviation<T>(d, drho, jx, jy, jz);
+        cv = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
+        *cache_entry<ST>(a, p, k) = cv;
+        claim_site(a, m.site_off + site);
+        if (k == 0) {
+          a.cc_cell[p] = cell;
+          a.cc_stamp[p] = stamp;
         }
       }
+      // fluid velocity at the particle (Eq. 5)
+      double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
+      if (a.variant >= 2) {
+        const Vec4<T> jv = a.J[m.site_off + site];
+        jx += (double)jv.x;
+        jy += (double)jv.y;
+        jz += (double)jv.z;
+      }
+      if (Rec) {
+        a.rec[(6 + 3 * k) * N + p] = jx;
+        a.rec[(7 + 3 * k) * N + p] = jy;
+        a.rec[(8 + 3 * k) * N + p] = jz;
+        a.rec[(30 + k) * N + p] = (double)cv.w;
+      }
+      const double wi = w * (double)cv.w;
+      ux += wi * jx;
+      uy += wi * jy;
+      uz += wi * jz;
     }
-    const double wi = w * (double)cv.w;
-    const double u[3] = {St::lane_sum(wi * jx), St::lane_sum(wi * jy), St::lane_sum(wi * jz)};
+    if (Rec && k0 == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.rec[d * N + p] = X[d];
+        a.rec[(3 + d) * N + p] = V[d];
+      }
+    }
+    const double u[3] = {Sh::sum(ux), Sh::sum(uy), Sh::sum(uz)};
     // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
@@ -331,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     for (int d = 0; d < 3; ++d) {
       const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
       dp[d] = m.tau * Fc;
-      if (k == 0) {
+      if (k0 == 0) {
         const double fc = a.fcons[d * N + p];
         int32_t im = a.img[d * N + p];
         double v1 = V[d] + m.h * (fc + Fc);
@@ -351,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         }
       }
     }
-    if (a.variant == 1) transfer_from_lanes<T, ST>(a.J, m, q, k, dp);
+    if (a.variant == 1) transfer_from_lanes<T, ST, L>(a.J, m, q, k0, dp);
   }
 }
 
@@ -439,15 +465,21 @@ static hipError_t couple_st(Context* c, int substep) {
   hipError_t e;
   const int64_t N = a.N;
   if (substep == 0 && (e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
-  const dim3 cgrid(grid_for((N * St::kLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
+  // lanes per particle of the coupling kernel
+  constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = ST == 0 ? 4 : 32;
+  const int L = (a.variant == 1 || a.rec) ? kL1 : kL2;
+  const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
   if (ST == 0 && a.rec)
-    hipLaunchKernelGGL((k_couple<T, true, 0>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8>), cgrid, dim3(kBlock), 0, c->stream, a);
+  else if (L == kL1)
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL1>), cgrid, dim3(kBlock), 0, c->stream, a);
   else
-    hipLaunchKernelGGL((k_couple<T, false, ST>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL2>), cgrid, dim3(kBlock), 0, c->stream, a);
   // variants 2 and 3: the transfer waits until every particle has read J;
   // with position-dependent forces it runs inside the force kernel
   if ((e = hipGetLastError()) != hipSuccess || a.variant == 1 || c->plan.any_forces2) return e;
-  hipLaunchKernelGGL((k_spread<T, ST>), cgrid, dim3(kBlock), 0, c->stream, a);
+  const dim3 sgrid(grid_for((N * St::kLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
+  hipLaunchKernelGGL((k_spread<T, ST>), sgrid, dim3(kBlock), 0, c->stream, a);
   return hipGetLastError();
 }
 
