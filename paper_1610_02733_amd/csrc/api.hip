@@ -113,6 +113,17 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
   L.cc_cell = o; o = up(o + N * 4);
   L.cc_stamp = o; o = up(o + N * 4);
+  // direct-mode lists: per segment of kBlock coupling lanes, kBlock * (sites
+  // per lane) transfer entries and kBlock / lanes particles; lanes x sites
+  // per lane is 8 for the cube (8 x 1 or 4 x 2) and 32 for the three-point
+  // stencil (32 x 1)
+  const size_t lanes_max = p[0].stencil == 1 ? 32 : 8;
+  pl.nseg = (int64_t)((N * lanes_max + kBlock - 1) / kBlock);
+  const size_t nent = (size_t)pl.nseg * kBlock;  // >= every launch's lanes x sites per lane
+  L.slist_site = o; o = up(o + nent * 4);
+  L.slist_delta = o; o = up(o + nent * 4 * t);
+  L.mlist = o; o = up(o + nent * 4);
+  L.seg_count = o; o = up(o + 2 * (size_t)pl.nseg * 4);
   L.shared_site = o; o = up(o + (S / 64) * 8);
   L.bin_count = o; o = up(o + C * 4);
   L.bin_start = o; o = up(o + (C + 1) * 4);
@@ -295,6 +306,7 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->x = c->v = nullptr;
   c->img = nullptr;
   c->bound = false;
+  c->cache_dirty = true;
   c->t_lb = c->t_md = 0;
   c->subs = 0;
   c->cur = 0;

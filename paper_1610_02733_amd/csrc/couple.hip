@@ -37,6 +37,14 @@ struct CoupleArgs {
   const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
   const Clock* __restrict__ clock;
   double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
+  // direct mode, per segment (one block-sized stretch of coupling lanes):
+  int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
+  Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
+  int32_t* __restrict__ lseg;    //   entries in the segment
+  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step,
+  int32_t* __restrict__ mseg;    //   their number in the segment
+  int direct;  // variants 2 and 3 without a force kernel: the coupling kernel itself
+               // updates J at sites only one particle claimed in the interval
   size_t P;     // population stride
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
@@ -182,6 +190,22 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
   }
 }
 
+// (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
+// populations (for a particle whose cached stencil is out of date).
+template <typename T>
+__device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop, size_t P,
+                                                      int site_off, const Geom& g, int cx,
+                                                      int cy, int cz, T rho0) {
+  int sidx[19];
+  pull_sources(g, cx, cy, cz, sidx);
+  T d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
+  T drho, jx, jy, jz;
+  moments_deviation<T>(d, drho, jx, jy, jz);
+  return Vec4<T>{jx, jy, jz, T(1) / (rho0 + drho)};
+}
+
 // ---------------------------------------------------------------------------
 // One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
 // ceil(sites / L) sites of its stencil (cube: L = 8 in variant 1, where
@@ -244,7 +268,7 @@ __device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, con
   }
 }
 
-template <typename T, bool Rec, int ST, int L>
+template <typename T, bool Rec, int ST, int L, bool Direct>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
   using Sh = CoupleShape<L>;
@@ -256,156 +280,237 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
   const int64_t lanes = N * Sh::kLanes;
+  // direct mode: entries of this block's segment, counted in LDS
+  __shared__ int s_l, s_m;
   // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
-  // are always active together, as the shuffles require
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
-       t += (int64_t)gridDim.x * kBlock) {
+  // are always active together, as the shuffles require; every thread of a
+  // block runs the loop the same number of times (block barriers)
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < lanes; t0 += stride) {
+    const int64_t t = t0 + threadIdx.x;
+    const int64_t seg = t0 / kBlock;
+    if (Direct) {
+      if (threadIdx.x == 0) s_l = s_m = 0;
+      __syncthreads();
+    }
+    bool moved = false;
+    int gs_[kPer];
+    double w_[kPer];
+    Vec4<T> jv_[kPer];
+    bool sh_[kPer];
+    double dp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int jj = 0; jj < kPer; ++jj) {
+      gs_[jj] = -1;
+      sh_[jj] = false;
+    }
     const int64_t p = t / Sh::kLanes;
     const int k0 = (int)(t & (Sh::kLanes - 1));
-    const int rr = a.single ? 0 : a.part_rep[p];
     double X[3], V[3];
-    bool live = true;
+    bool live = t < lanes;
+    if (live) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      X[d] = a.x[d * N + p];
-      V[d] = a.v[d * N + p];
-      live = live && isfinite(X[d]) && isfinite(V[d]);
-    }
-    if (!live) {
-      if (k0 == 0) {
+      for (int d = 0; d < 3; ++d) {
+        X[d] = a.x[d * N + p];
+        V[d] = a.v[d * N + p];
+        live = live && isfinite(X[d]) && isfinite(V[d]);
+      }
+      if (!live && k0 == 0) {
         a.flags[0] = 1;
         if (a.variant >= 2) a.rec_cell[p] = -1;
         if (Rec) a.rec[p] = __builtin_nan("");
       }
-      continue;
     }
-    const RepMD& m = a.md[rr];
-    Cube q;
-    St::locate(X, m.g, q);
-    const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-    const bool hit = a.cc_stamp[p] == stamp && a.cc_cell[p] == cell;
-    double ux = 0.0, uy = 0.0, uz = 0.0;
+    if (live) {
+      const int rr = a.single ? 0 : a.part_rep[p];
+      const RepMD& m = a.md[rr];
+      Cube q;
+      St::locate(X, m.g, q);
+      const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+      // Direct: every live particle's cache covers its current stencil (the
+      // refill, or the previous step's k_after_step for particles that moved)
+      const bool hit = Direct || (a.cc_stamp[p] == stamp && a.cc_cell[p] == cell);
+      double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < kPer; ++jj) {
-      const int k = k0 + jj * Sh::kLanes;
-      if (k >= St::kSites) break;
-      int cx, cy, cz, site;
-      double w;
-      St::site(q, m.g, k, cx, cy, cz, site, w);
-      Vec4<T> cv;
-      if (hit) {
-        cv = *cache_entry<ST>(a, p, k);
-      } else {
-        // left the cube of the refill: this lane gathers its site
-        int sidx[19];
-        pull_sources(m.g, cx, cy, cz, sidx);
-        T d[19];
+      for (int jj = 0; jj < kPer; ++jj) {
+        const int k = k0 + jj * Sh::kLanes;
+        if (k >= St::kSites) break;
+        int cx, cy, cz, site;
+        double w;
+        St::site(q, m.g, k, cx, cy, cz, site, w);
+        const int gs = m.site_off + site;
+        gs_[jj] = gs;
+        w_[jj] = w;
+        Vec4<T> cv;
+        if (hit) {
+          cv = *cache_entry<ST>(a, p, k);
+        } else {
+          // left the cube of the refill: this lane gathers its site
+          cv = gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+          *cache_entry<ST>(a, p, k) = cv;
+          claim_site(a, gs);
+          if (k == 0) {
+            a.cc_cell[p] = cell;
+            a.cc_stamp[p] = stamp;
+          }
+        }
+        // fluid velocity at the particle (Eq. 5)
+        double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
+        jv_[jj] = Vec4<T>{T(0), T(0), T(0), T(0)};
+        if (a.variant >= 2) {
+          jv_[jj] = a.J[gs];
+          if (Direct) sh_[jj] = (a.shared_site[gs >> 6] >> (gs & 63)) & 1ull;
+          jx += (double)jv_[jj].x;
+          jy += (double)jv_[jj].y;
+          jz += (double)jv_[jj].z;
+        }
+        if (Rec) {
+          a.rec[(6 + 3 * k) * N + p] = jx;
+          a.rec[(7 + 3 * k) * N + p] = jy;
+          a.rec[(8 + 3 * k) * N + p] = jz;
+          a.rec[(30 + k) * N + p] = (double)cv.w;
+        }
+        const double wi = w * (double)cv.w;
+        ux += wi * jx;
+        uy += wi * jy;
+        uz += wi * jz;
+      }
+      if (Rec && k0 == 0) {
 #pragma unroll
-        for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
-        T drho, jx, jy, jz;
-        moments_deviation<T>(d, drho, jx, jy, jz);
-        cv = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-        *cache_entry<ST>(a, p, k) = cv;
-        claim_site(a, m.site_off + site);
-        if (k == 0) {
-          a.cc_cell[p] = cell;
-          a.cc_stamp[p] = stamp;
+        for (int d = 0; d < 3; ++d) {
+          a.rec[d * N + p] = X[d];
+          a.rec[(3 + d) * N + p] = V[d];
         }
       }
-      // fluid velocity at the particle (Eq. 5)
-      double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-      if (a.variant >= 2) {
-        const Vec4<T> jv = a.J[m.site_off + site];
-        jx += (double)jv.x;
-        jy += (double)jv.y;
-        jz += (double)jv.z;
+      const double u[3] = {Sh::sum(ux), Sh::sum(uy), Sh::sum(uz)};
+      // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
+      double xi[3] = {0.0, 0.0, 0.0};
+      if (m.noise) {
+        const uint32_t lp = (uint32_t)a.pid[p];
+        const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
+        const uint32_t ws[3] = {o.w0, o.w1, o.w2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
       }
-      if (Rec) {
-        a.rec[(6 + 3 * k) * N + p] = jx;
-        a.rec[(7 + 3 * k) * N + p] = jy;
-        a.rec[(8 + 3 * k) * N + p] = jz;
-        a.rec[(30 + k) * N + p] = (double)cv.w;
-      }
-      const double wi = w * (double)cv.w;
-      ux += wi * jx;
-      uy += wi * jy;
-      uz += wi * jz;
-    }
-    if (Rec && k0 == 0) {
+      // velocity Verlet with the coupling force held over the step; with
+      // position-dependent conservative forces the second half-kick waits
+      // for the forces at the new positions (k_forces)
+      double Xn[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.rec[d * N + p] = X[d];
-        a.rec[(3 + d) * N + p] = V[d];
-      }
-    }
-    const double u[3] = {Sh::sum(ux), Sh::sum(uy), Sh::sum(uz)};
-    // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
-    double xi[3] = {0.0, 0.0, 0.0};
-    if (m.noise) {
-      const uint32_t lp = (uint32_t)a.pid[p];
-      const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
-      const uint32_t ws[3] = {o.w0, o.w1, o.w2};
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        xi[d] = 3.4641016151377546 * (((double)(ws[d] >> 8) + 0.5) * 5.9604644775390625e-08 - 0.5);
-    }
-    // velocity Verlet with the coupling force held over the step; with
-    // position-dependent conservative forces the second half-kick waits
-    // for the forces at the new positions (k_kick)
-    double dp[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
-      dp[d] = m.tau * Fc;
-      if (k0 == 0) {
+        const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
+        dp[d] = m.tau * Fc;
         const double fc = a.fcons[d * N + p];
         int32_t im = a.img[d * N + p];
         double v1 = V[d] + m.h * (fc + Fc);
         double x1 = X[d] + m.tau * v1;
         wrap_coord(x1, im, m.L[d]);
-        if (m.split_kick)
-          a.fc_held[d * N + p] = Fc;
-        else
-          v1 += m.h * (fc + Fc);
-        a.x[d * N + p] = x1;
-        a.v[d * N + p] = v1;
-        a.img[d * N + p] = im;
-        if (a.variant >= 2) {
-          a.rec_cell[d * N + p] = q.base[d];
-          a.rec_frac[d * N + p] = q.s[d];
-          a.rec_dp[d * N + p] = dp[d];
+        Xn[d] = x1;
+        if (k0 == 0) {
+          if (m.split_kick)
+            a.fc_held[d * N + p] = Fc;
+          else
+            v1 += m.h * (fc + Fc);
+          a.x[d * N + p] = x1;
+          a.v[d * N + p] = v1;
+          a.img[d * N + p] = im;
+          if (a.variant >= 2) {
+            a.rec_cell[d * N + p] = q.base[d];
+            a.rec_frac[d * N + p] = q.s[d];
+            a.rec_dp[d * N + p] = dp[d];
+          }
         }
       }
+      if (Direct && k0 == 0) {
+        // the next MD step needs other sites if the stencil moved (a
+        // non-finite new position is caught by that step)
+        if (isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
+          Cube qn;
+          St::locate(Xn, m.g, qn);
+          moved = qn.base[0] != q.base[0] || qn.base[1] != q.base[1] || qn.base[2] != q.base[2];
+        }
+      }
+      if (a.variant == 1) transfer_from_lanes<T, ST, L>(a.J, m, q, k0, dp);
     }
-    if (a.variant == 1) transfer_from_lanes<T, ST, L>(a.J, m, q, k0, dp);
+    if (Direct) {
+      // transfer -w_k dP (Eq. 7-8): a site only this particle claimed in the
+      // interval has no other reader or writer, so it takes the new value
+      // right away; transfers to shared sites wait in the step's list until
+      // every particle has read J (k_after_step)
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj) {
+        const int gs = gs_[jj];
+        const double ww = gs >= 0 ? w_[jj] : 0.0;
+        const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
+        if (gs >= 0 && !sh_[jj]) {
+          Vec4<T> nv = jv_[jj];
+          nv.x += ax;
+          nv.y += ay;
+          nv.z += az;
+          a.J[gs] = nv;
+        }
+        if (gs >= 0 && sh_[jj]) {
+          const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
+          a.lsite[e] = gs;
+          a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
+        }
+      }
+      if (moved) a.mlist[seg * (kBlock / L) + atomicAdd(&s_m, 1)] = (int32_t)p;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        a.lseg[seg] = s_l;
+        a.mseg[seg] = s_m;
+      }
+    }
   }
 }
 
-// Variant-2 momentum transfer of the MD step just taken, one lane per
-// stencil site (see spread_corner).  With position-dependent forces the same
-// transfer runs inside the force kernel instead.
+// After an MD step in the direct mode (variants 2 and 3 without a force
+// kernel), once every particle has read J: the step's transfers to shared
+// sites (atomic adds from the segment lists), then the particles whose
+// stencil moved gather the moments of their new sites and claim them, one
+// lane per site, before the next step reads them.  One block per segment
+// of the coupling kernel (kBlock * per entries and kBlock / L particles at
+// most each).
 template <typename T, int ST>
-__global__ __launch_bounds__(kBlock) void k_spread(CoupleArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
+                                                      int L) {
   using St = Stencil<ST>;
+  const T* __restrict__ pop = a.pop[a.clock->cur];
+  const int stamp = cache_stamp(a.clock);
   const int64_t N = a.N;
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * St::kLanes;
-       t += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = t / St::kLanes;
-    const int k = (int)(t & (St::kLanes - 1));
-    if (k >= St::kSites) continue;
-    Cube q;
-    q.base[0] = a.rec_cell[p];
-    if (q.base[0] < 0) continue;
-    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
-    q.base[1] = a.rec_cell[N + p];
-    q.base[2] = a.rec_cell[2 * N + p];
-    double dp[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      q.s[d] = a.rec_frac[d * N + p];
-      dp[d] = a.rec_dp[d * N + p];
+  for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    const int n = a.lseg[seg];
+    const int64_t base = seg * (int64_t)(kBlock * per);
+    for (int e = threadIdx.x; e < n; e += kBlock) {
+      const Vec4<T> d = a.ldelta[base + e];
+      T* dst = (T*)(a.J + a.lsite[base + e]);
+      atomicAdd(dst + 0, d.x);
+      atomicAdd(dst + 1, d.y);
+      atomicAdd(dst + 2, d.z);
     }
-    spread_corner<T, ST>(a.J, a.shared_site, m, q, k, dp);
+    const int nm = a.mseg[seg] * St::kLanes;
+    const int64_t mbase = seg * (int64_t)(kBlock / L);
+    for (int u = threadIdx.x; u < nm; u += kBlock) {
+      const int64_t p = a.mlist[mbase + u / St::kLanes];
+      const int k = u % St::kLanes;
+      if (k >= St::kSites) continue;
+      const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
+      const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+      Cube q;
+      St::locate(X, m.g, q);
+      int cx, cy, cz, site;
+      double w;
+      St::site(q, m.g, k, cx, cy, cz, site, w);
+      *cache_entry<ST>(a, p, k) =
+          gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+      claim_site(a, m.site_off + site);
+      if (k == 0) {
+        a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+        a.cc_stamp[p] = stamp;
+      }
+    }
   }
 }
 
@@ -435,6 +540,12 @@ static CoupleArgs<T> couple_args(Context* c, int substep) {
   a.pid = (const int32_t*)at(c, L.pid);
   a.clock = (const Clock*)at(c, L.clock);
   a.rec = c->rec_part ? c->rec_part + (size_t)substep * kAdjRec * (size_t)c->plan.Ntot : nullptr;
+  a.lsite = (int32_t*)at(c, L.slist_site);
+  a.ldelta = (Vec4<T>*)at(c, L.slist_delta);
+  a.lseg = (int32_t*)at(c, L.seg_count);
+  a.mlist = (int32_t*)at(c, L.mlist);
+  a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
+  a.direct = (c->p[0].variant >= 2 && !c->plan.any_forces2) ? 1 : 0;
   a.P = (size_t)c->plan.Stot;
   a.N = c->plan.Ntot;
   a.substep = substep;
@@ -464,22 +575,35 @@ static hipError_t couple_st(Context* c, int substep) {
   CoupleArgs<T> a = couple_args<T>(c, substep);
   hipError_t e;
   const int64_t N = a.N;
-  if (substep == 0 && (e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
+  // the whole cache is refilled at the first MD step of an interval, and
+  // after it was invalidated from outside (new populations, counters or
+  // particles): the direct mode relies on it covering every stencil
+  if (substep == 0 || c->cache_dirty) {
+    if ((e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
+    c->cache_dirty = false;
+  }
   // lanes per particle of the coupling kernel
   constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = ST == 0 ? 4 : 32;
   const int L = (a.variant == 1 || a.rec) ? kL1 : kL2;
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
-  if (ST == 0 && a.rec)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8>), cgrid, dim3(kBlock), 0, c->stream, a);
-  else if (L == kL1)
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL1>), cgrid, dim3(kBlock), 0, c->stream, a);
+  if (ST == 0 && a.rec && a.direct)
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, true>), cgrid, dim3(kBlock), 0, c->stream, a);
+  else if (ST == 0 && a.rec)
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, dim3(kBlock), 0, c->stream, a);
+  else if (!a.direct)
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false>), cgrid, dim3(kBlock), 0, c->stream,
+                       a);
   else
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL2>), cgrid, dim3(kBlock), 0, c->stream, a);
-  // variants 2 and 3: the transfer waits until every particle has read J;
-  // with position-dependent forces it runs inside the force kernel
-  if ((e = hipGetLastError()) != hipSuccess || a.variant == 1 || c->plan.any_forces2) return e;
-  const dim3 sgrid(grid_for((N * St::kLanes + kBlock - 1) / kBlock, c->tune.part_blocks));
-  hipLaunchKernelGGL((k_spread<T, ST>), sgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true>), cgrid, dim3(kBlock), 0, c->stream,
+                       a);
+  // variants 2 and 3: transfers to shared sites wait until every particle
+  // has read J; with position-dependent forces the whole transfer runs
+  // inside the force kernel instead
+  if ((e = hipGetLastError()) != hipSuccess || !a.direct) return e;
+  const int Ld = (ST == 0 && a.rec) ? 8 : kL2;  // lanes of the direct kernel just launched
+  const int64_t nseg = (N * Ld + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(nseg, c->tune.part_blocks)),
+                     dim3(kBlock), 0, c->stream, a, nseg, (St::kSites + Ld - 1) / Ld, Ld);
   return hipGetLastError();
 }
 
@@ -510,6 +634,7 @@ hipError_t launch_couple_refill_only(Context* c) {
 // replaced from outside).
 hipError_t invalidate_corner_cache(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
+  c->cache_dirty = true;
   return hipMemsetAsync(at(c, c->plan.lay.cc_stamp), 0, sizeof(int32_t) * c->plan.Ntot,
                         c->stream);
 }

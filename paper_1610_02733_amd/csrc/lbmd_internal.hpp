@@ -80,6 +80,10 @@ struct Layout {
   size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
   size_t cc_cell;    // [Ntot] int32: cube (lower corner, replica-local) cached
   size_t cc_stamp;   // [Ntot] int32: LB step + 1 at which the cache was filled
+  size_t slist_site;  // [sites per stencil * Ntot] int32: shared-site transfers of an MD step
+  size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
+  size_t mlist;      // [segments * kBlock / lanes] int32: particles whose stencil moved
+  size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
   size_t shared_site; // [Stot/64] uint64: site claimed more than once in this LB interval
   size_t bin_count;  // [Ctot] int32: particles per force cell
   size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
@@ -111,6 +115,7 @@ struct Plan {
   int64_t Ntot;  // particles
   int64_t Ctot;  // force cells
   int nitems;    // 256-site work items of the LB kernels
+  int64_t nseg;  // segments (block-sized stretches) of the widest coupling launch
   bool any_forces2;
   std::vector<int64_t> site_off, part_off, cell_off, item_off;
   Layout lay;
@@ -171,6 +176,7 @@ struct Context {
   void* v;
   int32_t* img;
   bool bound;
+  bool cache_dirty;  // the corner cache was invalidated since the last refill
   int64_t t_lb, t_md;
   int32_t subs;
   int cur;  // population buffer holding the current state (mirrors Clock::cur)
