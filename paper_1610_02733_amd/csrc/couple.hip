@@ -41,7 +41,8 @@ struct CoupleArgs {
   int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
   Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
   int32_t* __restrict__ lseg;    //   entries in the segment
-  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step,
+  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int2:
+                                 //   slot, replica-local index of the new stencil base),
   int32_t* __restrict__ mseg;    //   their number in the segment
   int direct;  // variants 2 and 3 without a force kernel: the coupling kernel itself
                // updates J at sites only one particle claimed in the interval
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       __syncthreads();
     }
     bool moved = false;
+    int new_cell = 0;
     int gs_[kPer];
     double w_[kPer];
     Vec4<T> jv_[kPer];
@@ -429,6 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           Cube qn;
           St::locate(Xn, m.g, qn);
           moved = qn.base[0] != q.base[0] || qn.base[1] != q.base[1] || qn.base[2] != q.base[2];
+          new_cell = qn.base[0] + m.g.nx * (qn.base[1] + m.g.ny * qn.base[2]);
         }
       }
       if (a.variant == 1) transfer_from_lanes<T, ST, L>(a.J, m, q, k0, dp);
@@ -456,7 +459,9 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
         }
       }
-      if (moved) a.mlist[seg * (kBlock / L) + atomicAdd(&s_m, 1)] = (int32_t)p;
+      if (moved)
+        reinterpret_cast<int2*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
+            make_int2((int)p, new_cell);
       __syncthreads();
       if (threadIdx.x == 0) {
         a.lseg[seg] = s_l;
@@ -467,48 +472,60 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
 }
 
 // After an MD step in the direct mode (variants 2 and 3 without a force
-// kernel), once every particle has read J: the step's transfers to shared
-// sites (atomic adds from the segment lists), then the particles whose
-// stencil moved gather the moments of their new sites and claim them, one
-// lane per site, before the next step reads them.  One block per segment
-// of the coupling kernel (kBlock * per entries and kBlock / L particles at
-// most each).
+// kernel), once every particle has read J: the particles whose stencil
+// moved gather the moments of their new sites and claim them, one lane per
+// site, before the next step reads them; and the step's transfers to shared
+// sites are applied (atomic adds from the segment lists).  The two jobs are
+// independent (a claim changes no J, the list was fixed by the coupling
+// kernel), so each segment of the coupling kernel (kBlock * per entries and
+// kBlock / L particles at most) gets one block per job: blocks [0, nseg)
+// take the moved particles, whose dependent loads form the longer chain,
+// and blocks [nseg, 2 nseg) the transfers.
 template <typename T, int ST>
 __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
                                                       int L) {
   using St = Stencil<ST>;
-  const T* __restrict__ pop = a.pop[a.clock->cur];
-  const int stamp = cache_stamp(a.clock);
-  const int64_t N = a.N;
-  for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const int n = a.lseg[seg];
-    const int64_t base = seg * (int64_t)(kBlock * per);
-    for (int e = threadIdx.x; e < n; e += kBlock) {
-      const Vec4<T> d = a.ldelta[base + e];
-      T* dst = (T*)(a.J + a.lsite[base + e]);
-      atomicAdd(dst + 0, d.x);
-      atomicAdd(dst + 1, d.y);
-      atomicAdd(dst + 2, d.z);
-    }
-    const int nm = a.mseg[seg] * St::kLanes;
-    const int64_t mbase = seg * (int64_t)(kBlock / L);
-    for (int u = threadIdx.x; u < nm; u += kBlock) {
-      const int64_t p = a.mlist[mbase + u / St::kLanes];
-      const int k = u % St::kLanes;
-      if (k >= St::kSites) continue;
-      const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
-      const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
-      Cube q;
-      St::locate(X, m.g, q);
-      int cx, cy, cz, site;
-      double w;
-      St::site(q, m.g, k, cx, cy, cz, site, w);
-      *cache_entry<ST>(a, p, k) =
-          gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
-      claim_site(a, m.site_off + site);
-      if (k == 0) {
-        a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-        a.cc_stamp[p] = stamp;
+  for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x) {
+    if (it < nseg) {
+      const int64_t seg = it;
+      const int nm = a.mseg[seg] * St::kLanes;
+      if (nm == 0) continue;
+      const T* __restrict__ pop = a.pop[a.clock->cur];
+      const int stamp = cache_stamp(a.clock);
+      const int2* __restrict__ ml = reinterpret_cast<const int2*>(a.mlist) + seg * (kBlock / L);
+      for (int u = threadIdx.x; u < nm; u += kBlock) {
+        const int k = u % St::kLanes;
+        if (k >= St::kSites) continue;
+        // (particle, replica-local index of its new stencil base)
+        const int2 ent = ml[u / St::kLanes];
+        const int64_t p = ent.x;
+        const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+        Cube q;
+        q.base[0] = ent.y % m.g.nx;
+        q.base[1] = (ent.y / m.g.nx) % m.g.ny;
+        q.base[2] = ent.y / (m.g.nx * m.g.ny);
+        q.s[0] = q.s[1] = q.s[2] = 0.0;
+        int cx, cy, cz, site;
+        double w;
+        St::site(q, m.g, k, cx, cy, cz, site, w);
+        *cache_entry<ST>(a, p, k) =
+            gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+        claim_site(a, m.site_off + site);
+        if (k == 0) {
+          a.cc_cell[p] = ent.y;
+          a.cc_stamp[p] = stamp;
+        }
+      }
+    } else {
+      const int64_t seg = it - nseg;
+      const int n = a.lseg[seg];
+      const int64_t base = seg * (int64_t)(kBlock * per);
+      for (int e = threadIdx.x; e < n; e += kBlock) {
+        const Vec4<T> d = a.ldelta[base + e];
+        T* dst = (T*)(a.J + a.lsite[base + e]);
+        atomicAdd(dst + 0, d.x);
+        atomicAdd(dst + 1, d.y);
+        atomicAdd(dst + 2, d.z);
       }
     }
   }
@@ -602,7 +619,7 @@ static hipError_t couple_st(Context* c, int substep) {
   if ((e = hipGetLastError()) != hipSuccess || !a.direct) return e;
   const int Ld = (ST == 0 && a.rec) ? 8 : kL2;  // lanes of the direct kernel just launched
   const int64_t nseg = (N * Ld + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(nseg, c->tune.part_blocks)),
+  hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(2 * nseg, c->tune.part_blocks)),
                      dim3(kBlock), 0, c->stream, a, nseg, (St::kSites + Ld - 1) / Ld, Ld);
   return hipGetLastError();
 }

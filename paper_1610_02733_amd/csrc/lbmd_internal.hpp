@@ -82,7 +82,7 @@ struct Layout {
   size_t cc_stamp;   // [Ntot] int32: LB step + 1 at which the cache was filled
   size_t slist_site;  // [sites per stencil * Ntot] int32: shared-site transfers of an MD step
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
-  size_t mlist;      // [segments * kBlock / lanes] int32: particles whose stencil moved
+  size_t mlist;      // [segments * kBlock / lanes] int2: particles whose stencil moved, new base
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
   size_t shared_site; // [Stot/64] uint64: site claimed more than once in this LB interval
   size_t bin_count;  // [Ctot] int32: particles per force cell
