@@ -222,12 +222,14 @@ __device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop
 // the momentum right away (Eq. 7-8): the (site, component) adds of a
 // particle are spread over its lanes in rounds, so the lanes of one atomic
 // instruction share a few sites rather than touching 64 unrelated cache
-// lines (eight lanes measured faster here than four).  Variants 2 and 3
-// store (cube, dP) for the spreading kernel instead, because every particle
-// must first read the velocities as of the end of the previous MD step
-// (variant 3 sees the same velocities as variant 2 inside an interval; its
-// transfer differs only in how the LB step applies it); there four lanes
-// with two corners each halve the redundant per-particle arithmetic.
+// lines (eight lanes measured faster here than four).  In variants 2 and 3
+// every particle must first read the velocities as of the end of the
+// previous MD step (variant 3 sees the same velocities as variant 2 inside
+// an interval; its transfer differs only in how the LB step applies it):
+// without a force kernel (Direct) the kernel writes the transfer at sites
+// it alone claimed and lists the rest for k_after_step; with one, it stores
+// (cube, dP) for the force kernel's transfer.  There four lanes with two
+// corners each halve the redundant per-particle arithmetic.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are

@@ -136,9 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // stores the force and, after an MD step, applies the second half-kick of
 // velocity Verlet (new conservative force + the coupling force held over the
 // step).  In variants 2 and 3 the first lanes (8, or 27 for the three-point
-// stencil) also transfer the step's momentum to the stencil sites (the
-// spreading of k_spread): this kernel runs after every particle of the step
-// has read the transfer field.
+// stencil) also transfer the step's momentum to the stencil sites: this
+// kernel runs after every particle of the step has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -381,7 +380,7 @@ hipError_t launch_init_forces(Context* c) {
 // After an MD step of replicas with position-dependent forces: binning,
 // forces at the new positions, the second half-kick and, in variants 2 and
 // 3, the step's momentum transfer (so the coupling step launches no
-// spreading kernel of its own).
+// after-step kernel of its own).
 hipError_t launch_forces_and_kick(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e = launch_binning(c);

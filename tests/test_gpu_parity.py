@@ -135,6 +135,27 @@ def test_dense_particles_share_sites(lb, orc, prec):
         check_particles(g, o, shape, TOL[prec], 1e-3)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_cube_changes_into_claimed_sites(lb, orc, prec, variant):
+    """Variants 2 and 3 write the transfer directly at sites only one
+    particle claimed in the LB interval; a particle that changes cubes claims
+    its new sites between two MD steps, which can turn a site another
+    particle owned alone into a shared one.  Fast particles (about 0.3 sites
+    per MD step, 10 MD steps per LB step) at moderate density make such
+    changes frequent; the run must still match the oracle."""
+    shape = (12, 10, 8)  # 60 cubes in 960 sites: shared and unshared sites mix
+    N = 60
+    rng = np.random.default_rng(31)
+    x = rng.random((3, N)) * np.array(shape, float)[:, None]
+    v = rng.uniform(-3.0, 3.0, (3, N))
+    kw = dict(kT=1e-4, seed=7, n_particles=N, friction=0.05, n_sub=10, variant=variant)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 6, x=x, v=v, precision=prec, **kw)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, rho0)
+    assert err < TOL[prec], err
+    check_particles(g, o, shape, TOL[prec], 1e-4)
+
+
 def test_n1_variants_coincide(lb, orc):
     """For n = 1 the two variants are the same algorithm (Sec. 3)."""
     shape = (8, 8, 8)
