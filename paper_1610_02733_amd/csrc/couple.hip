@@ -601,9 +601,10 @@ static hipError_t couple_st(Context* c, int substep) {
     if ((e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
     c->cache_dirty = false;
   }
-  // lanes per particle of the coupling kernel
+  // lanes per particle of the coupling kernel: kL2 in the direct mode
+  // (unless recording), kL1 otherwise
   constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = ST == 0 ? 4 : 32;
-  const int L = (a.variant == 1 || a.rec) ? kL1 : kL2;
+  const int L = (!a.direct || a.rec) ? kL1 : kL2;
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
   if (ST == 0 && a.rec && a.direct)
     hipLaunchKernelGGL((k_couple<T, true, 0, 8, true>), cgrid, dim3(kBlock), 0, c->stream, a);
