@@ -106,9 +106,9 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.pid = o; o = up(o + N * 4);
   L.clock = o; o = up(o + sizeof(Clock));
   L.fcons = o; o = up(o + 3 * N * 8);
-  L.rec_cell = o; o = up(o + 3 * N * 4);
-  L.rec_frac = o; o = up(o + 3 * N * 8);
-  L.rec_dp = o; o = up(o + 3 * N * 8);
+  L.sort_x = o; o = up(o + 3 * N * 8);
+  L.sort_v = o; o = up(o + 3 * N * 8);
+  L.sort_img = o; o = up(o + 3 * N * 4);
   L.fc_held = o; o = up(o + 3 * N * 8);
   L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
   L.cc_cell = o; o = up(o + N * 4);

@@ -7,70 +7,10 @@
 // particle_geom.hpp); the adjoint exists for the trilinear one only.
 #include <algorithm>
 
-#include "particle_geom.hpp"
+#include "couple_state.hpp"
 
 namespace lbmd_impl {
 using namespace lbmd_dev;
-
-// T is the lattice precision (populations, transfer field, corner cache);
-// particle state and all particle arithmetic are FP64 in both precisions.
-template <typename T>
-struct CoupleArgs {
-  double* __restrict__ x;
-  double* __restrict__ v;
-  int32_t* __restrict__ img;
-  const double* __restrict__ fcons;
-  T* pop[2];
-  Vec4<T>* __restrict__ J;
-  unsigned long long* __restrict__ mark;
-  int32_t* __restrict__ rec_cell;
-  double* __restrict__ rec_frac;
-  double* __restrict__ rec_dp;
-  double* __restrict__ fc_held;  // coupling force of the step (split kick)
-  T* __restrict__ cc;
-  int32_t* __restrict__ cc_cell;
-  int32_t* __restrict__ cc_stamp;
-  unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
-  int32_t* __restrict__ flags;
-  const RepMD* __restrict__ md;
-  const int32_t* __restrict__ part_rep;
-  const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
-  const Clock* __restrict__ clock;
-  double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
-  // direct mode, per segment (one block-sized stretch of coupling lanes):
-  int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
-  Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
-  int32_t* __restrict__ lseg;    //   entries in the segment
-  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int2:
-                                 //   slot, replica-local index of the new stencil base),
-  int32_t* __restrict__ mseg;    //   their number in the segment
-  int direct;  // variants 2 and 3 without a force kernel: the coupling kernel itself
-               // updates J at sites only one particle claimed in the interval
-  size_t P;     // population stride
-  int64_t N;    // particles over all replicas
-  int substep;  // MD step inside the LB interval
-  int variant;
-  int single;   // one replica: its constants are uniform across the grid
-};
-
-// Cache entry k of particle p: (jx, jy, jz, 1/rho) of stencil site k.
-template <int ST = 0, typename T>
-__device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
-  return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
-}
-
-__device__ __forceinline__ int cache_stamp(const Clock* clk) {
-  return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
-}
-
-// Mark a site as a receiver of momentum transfer in this LB interval; a site
-// claimed again (by another particle, or by one that changed cubes) is
-// flagged as shared.
-template <typename T>
-__device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
-  const unsigned long long bit = 1ull << (gs & 63);
-  if (atomicOr(a.mark + (gs >> 6), bit) & bit) atomicOr(a.shared_site + (gs >> 6), bit);
-}
 
 // ---------------------------------------------------------------------------
 // Corner-cache refill, once per LB interval (before its first MD step):
@@ -191,22 +131,6 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
   }
 }
 
-// (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
-// populations (for a particle whose cached stencil is out of date).
-template <typename T>
-__device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop, size_t P,
-                                                      int site_off, const Geom& g, int cx,
-                                                      int cy, int cz, T rho0) {
-  int sidx[19];
-  pull_sources(g, cx, cy, cz, sidx);
-  T d[19];
-#pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
-  T drho, jx, jy, jz;
-  moments_deviation<T>(d, drho, jx, jy, jz);
-  return Vec4<T>{jx, jy, jz, T(1) / (rho0 + drho)};
-}
-
 // ---------------------------------------------------------------------------
 // One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
 // ceil(sites / L) sites of its stencil (cube: L = 8 in variant 1, where
@@ -226,10 +150,9 @@ __device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop
 // every particle must first read the velocities as of the end of the
 // previous MD step (variant 3 sees the same velocities as variant 2 inside
 // an interval; its transfer differs only in how the LB step applies it):
-// without a force kernel (Direct) the kernel writes the transfer at sites
-// it alone claimed and lists the rest for k_after_step; with one, it stores
-// (cube, dP) for the force kernel's transfer.  There four lanes with two
-// corners each halve the redundant per-particle arithmetic.
+// the kernel (Direct) writes the transfer at sites it alone claimed and
+// lists the rest for the after-step work (after_step_item).  There four
+// lanes with two corners each halve the redundant per-particle arithmetic.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
@@ -321,7 +244,6 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       }
       if (!live && k0 == 0) {
         a.flags[0] = 1;
-        if (a.variant >= 2) a.rec_cell[p] = -1;
         if (Rec) a.rec[p] = __builtin_nan("");
       }
     }
@@ -419,11 +341,6 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.x[d * N + p] = x1;
           a.v[d * N + p] = v1;
           a.img[d * N + p] = im;
-          if (a.variant >= 2) {
-            a.rec_cell[d * N + p] = q.base[d];
-            a.rec_frac[d * N + p] = q.s[d];
-            a.rec_dp[d * N + p] = dp[d];
-          }
         }
       }
       if (Direct && k0 == 0) {
@@ -473,104 +390,13 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   }
 }
 
-// After an MD step in the direct mode (variants 2 and 3 without a force
-// kernel), once every particle has read J: the particles whose stencil
-// moved gather the moments of their new sites and claim them, one lane per
-// site, before the next step reads them; and the step's transfers to shared
-// sites are applied (atomic adds from the segment lists).  The two jobs are
-// independent (a claim changes no J, the list was fixed by the coupling
-// kernel), so each segment of the coupling kernel (kBlock * per entries and
-// kBlock / L particles at most) gets one block per job: blocks [0, nseg)
-// take the moved particles, whose dependent loads form the longer chain,
-// and blocks [nseg, 2 nseg) the transfers.
+// After an MD step in the direct mode without a force kernel: the
+// after-step work (after_step_item) as a launch of its own.
 template <typename T, int ST>
 __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
                                                       int L) {
-  using St = Stencil<ST>;
-  for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x) {
-    if (it < nseg) {
-      const int64_t seg = it;
-      const int nm = a.mseg[seg] * St::kLanes;
-      if (nm == 0) continue;
-      const T* __restrict__ pop = a.pop[a.clock->cur];
-      const int stamp = cache_stamp(a.clock);
-      const int2* __restrict__ ml = reinterpret_cast<const int2*>(a.mlist) + seg * (kBlock / L);
-      for (int u = threadIdx.x; u < nm; u += kBlock) {
-        const int k = u % St::kLanes;
-        if (k >= St::kSites) continue;
-        // (particle, replica-local index of its new stencil base)
-        const int2 ent = ml[u / St::kLanes];
-        const int64_t p = ent.x;
-        const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
-        Cube q;
-        q.base[0] = ent.y % m.g.nx;
-        q.base[1] = (ent.y / m.g.nx) % m.g.ny;
-        q.base[2] = ent.y / (m.g.nx * m.g.ny);
-        q.s[0] = q.s[1] = q.s[2] = 0.0;
-        int cx, cy, cz, site;
-        double w;
-        St::site(q, m.g, k, cx, cy, cz, site, w);
-        *cache_entry<ST>(a, p, k) =
-            gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
-        claim_site(a, m.site_off + site);
-        if (k == 0) {
-          a.cc_cell[p] = ent.y;
-          a.cc_stamp[p] = stamp;
-        }
-      }
-    } else {
-      const int64_t seg = it - nseg;
-      const int n = a.lseg[seg];
-      const int64_t base = seg * (int64_t)(kBlock * per);
-      for (int e = threadIdx.x; e < n; e += kBlock) {
-        const Vec4<T> d = a.ldelta[base + e];
-        T* dst = (T*)(a.J + a.lsite[base + e]);
-        atomicAdd(dst + 0, d.x);
-        atomicAdd(dst + 1, d.y);
-        atomicAdd(dst + 2, d.z);
-      }
-    }
-  }
-}
-
-template <typename T>
-static CoupleArgs<T> couple_args(Context* c, int substep) {
-  CoupleArgs<T> a;
-  const Layout& L = c->plan.lay;
-  a.x = (double*)c->x;
-  a.v = (double*)c->v;
-  a.img = c->img;
-  a.fcons = (const double*)at(c, L.fcons);
-  a.pop[0] = (T*)c->popv[0];
-  a.pop[1] = (T*)c->popv[1];
-  a.J = (Vec4<T>*)at(c, L.transfer);
-  a.mark = (unsigned long long*)at(c, L.mark);
-  a.rec_cell = (int32_t*)at(c, L.rec_cell);
-  a.rec_frac = (double*)at(c, L.rec_frac);
-  a.rec_dp = (double*)at(c, L.rec_dp);
-  a.fc_held = (double*)at(c, L.fc_held);
-  a.cc = (T*)at(c, L.cc);
-  a.cc_cell = (int32_t*)at(c, L.cc_cell);
-  a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
-  a.shared_site = (unsigned long long*)at(c, L.shared_site);
-  a.flags = (int32_t*)at(c, L.flags);
-  a.md = (const RepMD*)at(c, L.rep_md);
-  a.part_rep = (const int32_t*)at(c, L.part_rep);
-  a.pid = (const int32_t*)at(c, L.pid);
-  a.clock = (const Clock*)at(c, L.clock);
-  a.rec = c->rec_part ? c->rec_part + (size_t)substep * kAdjRec * (size_t)c->plan.Ntot : nullptr;
-  a.lsite = (int32_t*)at(c, L.slist_site);
-  a.ldelta = (Vec4<T>*)at(c, L.slist_delta);
-  a.lseg = (int32_t*)at(c, L.seg_count);
-  a.mlist = (int32_t*)at(c, L.mlist);
-  a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
-  a.direct = (c->p[0].variant >= 2 && !c->plan.any_forces2) ? 1 : 0;
-  a.P = (size_t)c->plan.Stot;
-  a.N = c->plan.Ntot;
-  a.substep = substep;
-  a.variant = c->p[0].variant;
-  a.single = c->plan.R == 1 ? 1 : 0;
-  return a;
+  for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x)
+    after_step_item<T, ST>(a, it, nseg, per, L);
 }
 
 static int grid_for(int64_t work_blocks, int tuned) {
@@ -603,7 +429,7 @@ static hipError_t couple_st(Context* c, int substep) {
   }
   // lanes per particle of the coupling kernel: kL2 in the direct mode
   // (unless recording), kL1 otherwise
-  constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = ST == 0 ? 4 : 32;
+  constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = DirectShape<ST>::kLanes;
   const int L = (!a.direct || a.rec) ? kL1 : kL2;
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
   if (ST == 0 && a.rec && a.direct)
@@ -617,9 +443,10 @@ static hipError_t couple_st(Context* c, int substep) {
     hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true>), cgrid, dim3(kBlock), 0, c->stream,
                        a);
   // variants 2 and 3: transfers to shared sites wait until every particle
-  // has read J; with position-dependent forces the whole transfer runs
-  // inside the force kernel instead
+  // has read J; with position-dependent forces that work rides in extra
+  // blocks of the force kernel's launch, which follows anyway
   if ((e = hipGetLastError()) != hipSuccess || !a.direct) return e;
+  if (c->plan.any_forces2 && !a.rec) return hipSuccess;
   const int Ld = (ST == 0 && a.rec) ? 8 : kL2;  // lanes of the direct kernel just launched
   const int64_t nseg = (N * Ld + kBlock - 1) / kBlock;
   hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(2 * nseg, c->tune.part_blocks)),

@@ -1,0 +1,191 @@
+// State of the particle coupling shared by the coupling kernels and the
+// force kernel: the kernel arguments, the corner cache, site claims, the
+// moments of a site from its pulled populations, and the work that follows
+// an MD step in the direct transfer mode.
+#pragma once
+
+#include "particle_geom.hpp"
+
+namespace lbmd_impl {
+using namespace lbmd_dev;
+
+// T is the lattice precision (populations, transfer field, corner cache);
+// particle state and all particle arithmetic are FP64 in both precisions.
+template <typename T>
+struct CoupleArgs {
+  double* __restrict__ x;
+  double* __restrict__ v;
+  int32_t* __restrict__ img;
+  const double* __restrict__ fcons;
+  T* pop[2];
+  Vec4<T>* __restrict__ J;
+  unsigned long long* __restrict__ mark;
+  double* __restrict__ fc_held;  // coupling force of the step (split kick)
+  T* __restrict__ cc;
+  int32_t* __restrict__ cc_cell;
+  int32_t* __restrict__ cc_stamp;
+  unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
+  int32_t* __restrict__ flags;
+  const RepMD* __restrict__ md;
+  const int32_t* __restrict__ part_rep;
+  const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
+  const Clock* __restrict__ clock;
+  double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
+  // direct mode, per segment (one block-sized stretch of coupling lanes):
+  int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
+  Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
+  int32_t* __restrict__ lseg;    //   entries in the segment
+  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int2:
+                                 //   slot, replica-local index of the new stencil base),
+  int32_t* __restrict__ mseg;    //   their number in the segment
+  int direct;  // variants 2 and 3: the coupling kernel itself updates J at sites
+               // only one particle claimed in the interval
+  size_t P;     // population stride
+  int64_t N;    // particles over all replicas
+  int substep;  // MD step inside the LB interval
+  int variant;
+  int single;   // one replica: its constants are uniform across the grid
+};
+
+// Cache entry k of particle p: (jx, jy, jz, 1/rho) of stencil site k.
+template <int ST = 0, typename T>
+__device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
+  return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
+}
+
+__device__ __forceinline__ int cache_stamp(const Clock* clk) {
+  return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
+}
+
+// Mark a site as a receiver of momentum transfer in this LB interval; a site
+// claimed again (by another particle, or by one that changed cubes) is
+// flagged as shared.
+template <typename T>
+__device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
+  const unsigned long long bit = 1ull << (gs & 63);
+  if (atomicOr(a.mark + (gs >> 6), bit) & bit) atomicOr(a.shared_site + (gs >> 6), bit);
+}
+
+// (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
+// populations (for a particle whose cached stencil is out of date).
+template <typename T>
+__device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop, size_t P,
+                                                      int site_off, const Geom& g, int cx,
+                                                      int cy, int cz, T rho0) {
+  int sidx[19];
+  pull_sources(g, cx, cy, cz, sidx);
+  T d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
+  T drho, jx, jy, jz;
+  moments_deviation<T>(d, drho, jx, jy, jz);
+  return Vec4<T>{jx, jy, jz, T(1) / (rho0 + drho)};
+}
+
+// After an MD step in the direct mode (variants 2 and 3), once every
+// particle has read J: the particles whose stencil moved gather the moments
+// of their new sites and claim them, one lane per site, before the next
+// step reads them; and the step's transfers to shared sites are applied
+// (atomic adds from the segment lists).  The two jobs are
+// independent (a claim changes no J, the list was fixed by the coupling
+// kernel), so each segment of the coupling kernel (kBlock * per entries and
+// kBlock / L particles at most) gets one block per job: items [0, nseg)
+// take the moved particles, whose dependent loads form the longer chain,
+// and items [nseg, 2 nseg) the transfers.  One block runs one item; the
+// work runs as a launch of its own (k_after_step) or in extra blocks of
+// the force kernel's launch.
+// Lanes per particle of the direct-mode coupling kernel (outside recording):
+// four with two corners each for the cube, one per site for the three-point
+// stencil.
+template <int ST>
+struct DirectShape {
+  static constexpr int kLanes = ST == 0 ? 4 : 32;
+  static constexpr int kPer = (Stencil<ST>::kSites + kLanes - 1) / kLanes;
+};
+
+template <typename T, int ST>
+__device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t it, int64_t nseg,
+                                                int per, int L) {
+  using St = Stencil<ST>;
+  if (it < nseg) {
+    const int64_t seg = it;
+    const int nm = a.mseg[seg] * St::kLanes;
+    if (nm == 0) return;
+    const T* __restrict__ pop = a.pop[a.clock->cur];
+    const int stamp = cache_stamp(a.clock);
+    const int2* __restrict__ ml = reinterpret_cast<const int2*>(a.mlist) + seg * (kBlock / L);
+    for (int u = threadIdx.x; u < nm; u += kBlock) {
+      const int k = u % St::kLanes;
+      if (k >= St::kSites) continue;
+      // (particle, replica-local index of its new stencil base)
+      const int2 ent = ml[u / St::kLanes];
+      const int64_t p = ent.x;
+      const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+      Cube q;
+      q.base[0] = ent.y % m.g.nx;
+      q.base[1] = (ent.y / m.g.nx) % m.g.ny;
+      q.base[2] = ent.y / (m.g.nx * m.g.ny);
+      q.s[0] = q.s[1] = q.s[2] = 0.0;
+      int cx, cy, cz, site;
+      double w;
+      St::site(q, m.g, k, cx, cy, cz, site, w);
+      *cache_entry<ST>(a, p, k) =
+          gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+      claim_site(a, m.site_off + site);
+      if (k == 0) {
+        a.cc_cell[p] = ent.y;
+        a.cc_stamp[p] = stamp;
+      }
+    }
+  } else {
+    const int64_t seg = it - nseg;
+    const int n = a.lseg[seg];
+    const int64_t base = seg * (int64_t)(kBlock * per);
+    for (int e = threadIdx.x; e < n; e += kBlock) {
+      const Vec4<T> d = a.ldelta[base + e];
+      T* dst = (T*)(a.J + a.lsite[base + e]);
+      atomicAdd(dst + 0, d.x);
+      atomicAdd(dst + 1, d.y);
+      atomicAdd(dst + 2, d.z);
+    }
+  }
+}
+
+template <typename T>
+inline CoupleArgs<T> couple_args(Context* c, int substep) {
+  CoupleArgs<T> a;
+  const Layout& L = c->plan.lay;
+  a.x = (double*)c->x;
+  a.v = (double*)c->v;
+  a.img = c->img;
+  a.fcons = (const double*)at(c, L.fcons);
+  a.pop[0] = (T*)c->popv[0];
+  a.pop[1] = (T*)c->popv[1];
+  a.J = (Vec4<T>*)at(c, L.transfer);
+  a.mark = (unsigned long long*)at(c, L.mark);
+  a.fc_held = (double*)at(c, L.fc_held);
+  a.cc = (T*)at(c, L.cc);
+  a.cc_cell = (int32_t*)at(c, L.cc_cell);
+  a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
+  a.shared_site = (unsigned long long*)at(c, L.shared_site);
+  a.flags = (int32_t*)at(c, L.flags);
+  a.md = (const RepMD*)at(c, L.rep_md);
+  a.part_rep = (const int32_t*)at(c, L.part_rep);
+  a.pid = (const int32_t*)at(c, L.pid);
+  a.clock = (const Clock*)at(c, L.clock);
+  a.rec = c->rec_part ? c->rec_part + (size_t)substep * kAdjRec * (size_t)c->plan.Ntot : nullptr;
+  a.lsite = (int32_t*)at(c, L.slist_site);
+  a.ldelta = (Vec4<T>*)at(c, L.slist_delta);
+  a.lseg = (int32_t*)at(c, L.seg_count);
+  a.mlist = (int32_t*)at(c, L.mlist);
+  a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
+  a.direct = c->p[0].variant >= 2 ? 1 : 0;
+  a.P = (size_t)c->plan.Stot;
+  a.N = c->plan.Ntot;
+  a.substep = substep;
+  a.variant = c->p[0].variant;
+  a.single = c->plan.R == 1 ? 1 : 0;
+  return a;
+}
+
+}  // namespace lbmd_impl

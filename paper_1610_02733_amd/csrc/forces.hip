@@ -8,7 +8,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "particle_geom.hpp"
+#include "couple_state.hpp"
 
 namespace lbmd_impl {
 
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
 // stores the force and, after an MD step, applies the second half-kick of
 // velocity Verlet (new conservative force + the coupling force held over the
-// step).  In variants 2 and 3 the first lanes (8, or 27 for the three-point
-// stencil) also transfer the step's momentum to the stencil sites: this
-// kernel runs after every particle of the step has read the transfer field.
+// step).  In variants 2 and 3 the launch also carries the after-step work of
+// the direct transfer mode in extra blocks: this kernel runs after every
+// particle of the step has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -164,22 +164,27 @@ struct ForceArgs {
   const int32_t* __restrict__ start;
   const int32_t* __restrict__ tiles;
   const int32_t* __restrict__ sorted;
-  // variant-2/3 transfer of the MD step
-  const int32_t* __restrict__ rec_cell;
-  const double* __restrict__ rec_frac;
-  const double* __restrict__ rec_dp;
-  const unsigned long long* __restrict__ shared_site;
-  Vec4<T>* __restrict__ J;
   int64_t N;
   int64_t ncells;
 };
 
-template <typename T, bool Kick, bool Spread>
-__global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
+// Blocks [0, nfb) compute the forces; with AfterST >= 0 (variants 2 and 3,
+// direct transfer mode) blocks [nfb, nfb + 2 nseg) do the after-step work
+// of the MD step just taken (after_step_item), which is independent of the
+// forces: it touches J, the claims and the corner cache only.
+template <typename T, bool Kick, int AfterST>
+__global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T> ca, int64_t nseg,
+                                                   int per, int L, int64_t nfb) {
+  if constexpr (AfterST >= 0) {
+    if (blockIdx.x >= nfb) {
+      after_step_item<T, AfterST>(ca, (int64_t)blockIdx.x - nfb, nseg, per, L);
+      return;
+    }
+  }
   const int64_t N = a.N;
   // lanes come in whole particles (32 | kBlock), as the shuffles require
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kForceLanes;
-       t += (int64_t)gridDim.x * kBlock) {
+       t += nfb * kBlock) {
     const int64_t p = t / kForceLanes;
     const int lane = (int)(t & (kForceLanes - 1));
     const RepMD& m = a.md[a.part_rep[p]];
@@ -267,24 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a) {
         }
       }
     }
-    if (Spread && lane < (m.stencil ? Stencil<1>::kSites : Stencil<0>::kSites)) {
-      Cube q;
-      q.base[0] = a.rec_cell[p];
-      if (q.base[0] >= 0) {
-        q.base[1] = a.rec_cell[N + p];
-        q.base[2] = a.rec_cell[2 * N + p];
-        double dp[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          q.s[d] = a.rec_frac[d * N + p];
-          dp[d] = a.rec_dp[d * N + p];
-        }
-        if (m.stencil)
-          spread_corner<T, 1>(a.J, a.shared_site, m, q, lane, dp);
-        else
-          spread_corner<T, 0>(a.J, a.shared_site, m, q, lane, dp);
-      }
-    }
   }
 }
 
@@ -321,11 +308,6 @@ static ForceArgs<T> force_args(Context* c) {
   a.start = (const int32_t*)at(c, L.bin_start);
   a.tiles = (const int32_t*)at(c, L.bin_tiles);
   a.sorted = (const int32_t*)at(c, L.bin_sorted);
-  a.rec_cell = (const int32_t*)at(c, L.rec_cell);
-  a.rec_frac = (const double*)at(c, L.rec_frac);
-  a.rec_dp = (const double*)at(c, L.rec_dp);
-  a.shared_site = (const unsigned long long*)at(c, L.shared_site);
-  a.J = (Vec4<T>*)at(c, L.transfer);
   a.N = c->plan.Ntot;
   a.ncells = c->plan.Ctot;
   return a;
@@ -354,11 +336,23 @@ static hipError_t launch_binning(Context* c) {
   return hipGetLastError();
 }
 
-template <typename T, bool Kick, bool Spread>
+template <typename T, bool Kick, int AfterST>
 static hipError_t forces_t(Context* c) {
   const ForceArgs<T> a = force_args<T>(c);
-  const dim3 grid((unsigned)((a.N * kForceLanes + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL((k_forces<T, Kick, Spread>), grid, dim3(kBlock), 0, c->stream, a);
+  const int64_t nfb = (a.N * kForceLanes + kBlock - 1) / kBlock;
+  CoupleArgs<T> ca{};
+  int64_t nseg = 0;
+  int per = 0, L = 0;
+  if (AfterST >= 0) {
+    constexpr int ST = AfterST >= 0 ? AfterST : 0;
+    ca = couple_args<T>(c, 0);
+    L = DirectShape<ST>::kLanes;
+    per = DirectShape<ST>::kPer;
+    nseg = (a.N * L + kBlock - 1) / kBlock;
+  }
+  const dim3 grid((unsigned)(nfb + 2 * nseg));
+  hipLaunchKernelGGL((k_forces<T, Kick, AfterST>), grid, dim3(kBlock), 0, c->stream, a, ca, nseg,
+                     per, L, nfb);
   return hipGetLastError();
 }
 
@@ -367,7 +361,7 @@ hipError_t launch_forces(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e;
   if (c->plan.any_forces2 && (e = launch_binning(c)) != hipSuccess) return e;
-  return c->plan.prec == 32 ? forces_t<float, false, false>(c) : forces_t<double, false, false>(c);
+  return c->plan.prec == 32 ? forces_t<float, false, -1>(c) : forces_t<double, false, -1>(c);
 }
 
 // Forces at the bound positions; the corner cache is stale from here on.
@@ -379,16 +373,19 @@ hipError_t launch_init_forces(Context* c) {
 
 // After an MD step of replicas with position-dependent forces: binning,
 // forces at the new positions, the second half-kick and, in variants 2 and
-// 3, the step's momentum transfer (so the coupling step launches no
-// after-step kernel of its own).
+// 3, the after-step work of the direct transfer mode in the same launch (so
+// the coupling step launches no after-step kernel of its own).
+template <typename T>
+static hipError_t forces_and_kick_t(Context* c) {
+  if (c->p[0].variant < 2 || c->rec_part) return forces_t<T, true, -1>(c);
+  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c) : forces_t<T, true, 0>(c);
+}
+
 hipError_t launch_forces_and_kick(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e = launch_binning(c);
   if (e != hipSuccess) return e;
-  const bool v2 = c->p[0].variant >= 2;
-  if (c->plan.prec == 32)
-    return v2 ? forces_t<float, true, true>(c) : forces_t<float, true, false>(c);
-  return v2 ? forces_t<double, true, true>(c) : forces_t<double, true, false>(c);
+  return c->plan.prec == 32 ? forces_and_kick_t<float>(c) : forces_and_kick_t<double>(c);
 }
 
 }  // namespace lbmd_impl

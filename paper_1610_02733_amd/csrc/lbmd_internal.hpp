@@ -73,9 +73,9 @@ struct Layout {
                      // (its index at binding; the particle noise counter follows it)
   size_t clock;      // Clock
   size_t fcons;      // [3][Ntot] double: conservative force at the current positions
-  size_t rec_cell;   // [3][Ntot] int32: lower corner of the particle's cube (-1: skipped)
-  size_t rec_frac;   // [3][Ntot] double: fractional position inside the cube
-  size_t rec_dp;     // [3][Ntot] double: momentum change dP of the current MD step
+  size_t sort_x;     // [3][Ntot] double: particle sort scratch (positions)
+  size_t sort_v;     // [3][Ntot] double: particle sort scratch (velocities)
+  size_t sort_img;   // [3][Ntot] int32: particle sort scratch (image counters)
   size_t fc_held;    // [3][Ntot] double: coupling force of the MD step (split kick)
   size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
   size_t cc_cell;    // [Ntot] int32: cube (lower corner, replica-local) cached

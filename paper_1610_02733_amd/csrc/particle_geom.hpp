@@ -151,34 +151,4 @@ struct Stencil<1> {
   }
 };
 
-// Variant-2 transfer -w_k dP of one particle to site k of its stencil (Eq.
-// 7-8).  Every site a transfer reaches was claimed by the transferring
-// particle in this LB interval before the transfer runs, so a site without
-// the shared flag has a single writer and takes a plain read-modify-write of
-// its vector; shared sites take atomic adds.  Either way the site receives
-// the same rounded values.
-template <typename T, int ST = 0>
-__device__ __forceinline__ void spread_corner(Vec4<T>* __restrict__ J,
-                                              const unsigned long long* __restrict__ shared_site,
-                                              const RepMD& m, const Cube& q, int k,
-                                              const double dp[3]) {
-  int cx, cy, cz, site;
-  double w;
-  Stencil<ST>::site(q, m.g, k, cx, cy, cz, site, w);
-  const int gs = m.site_off + site;
-  const T ax = (T)(-w * dp[0]), ay = (T)(-w * dp[1]), az = (T)(-w * dp[2]);
-  if ((shared_site[gs >> 6] >> (gs & 63)) & 1ull) {
-    T* dst = (T*)(J + gs);
-    atomicAdd(dst + 0, ax);
-    atomicAdd(dst + 1, ay);
-    atomicAdd(dst + 2, az);
-  } else {
-    Vec4<T> v = J[gs];
-    v.x += ax;
-    v.y += ay;
-    v.z += az;
-    J[gs] = v;
-  }
-}
-
 }  // namespace lbmd_impl

@@ -134,10 +134,9 @@ hipError_t launch_sort_particles(Context* c, int32_t* d_perm, bool* too_small) {
                                          vals + N, (int)N, 0, end_bit, c->stream);
   if (e != hipSuccess) return e;
   const int32_t* perm = vals + N;
-  // scratch: the per-step particle records are free at an LB-step boundary
-  double* xs = (double*)at(c, L.rec_frac);
-  double* vs = (double*)at(c, L.rec_dp);
-  int32_t* is = (int32_t*)at(c, L.rec_cell);
+  double* xs = (double*)at(c, L.sort_x);
+  double* vs = (double*)at(c, L.sort_v);
+  int32_t* is = (int32_t*)at(c, L.sort_img);
   int32_t* ps = (int32_t*)keys;  // the sort keys are no longer needed
   int32_t* pid = (int32_t*)at(c, L.pid);
   hipLaunchKernelGGL(k_permute_gather, dim3(blocks), dim3(kBlock), 0, c->stream, perm, N,
