@@ -194,7 +194,7 @@ __device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, con
   }
 }
 
-template <typename T, bool Rec, int ST, int L, bool Direct>
+template <typename T, bool Rec, int ST, int L, bool Direct, bool Bin>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
   using Sh = CoupleShape<L>;
@@ -245,6 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       if (!live && k0 == 0) {
         a.flags[0] = 1;
         if (Rec) a.rec[p] = __builtin_nan("");
+        if (Bin) a.bin[p] = -1;
       }
     }
     if (live) {
@@ -343,6 +344,16 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.img[d * N + p] = im;
         }
       }
+      if (Bin && k0 == 0) {
+        // force cell at the new position, for the force kernel that follows
+        if (m.force_model >= 2 && isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
+          const int cb = m.cell_off + local_cell(Xn, m);
+          a.bin[p] = cb;
+          a.bin_rank[p] = atomicAdd(a.bin_count + cb, 1);
+        } else {
+          a.bin[p] = -1;
+        }
+      }
       if (Direct && k0 == 0) {
         // the next MD step needs other sites if the stencil moved (a
         // non-finite new position is caught by that step)
@@ -432,16 +443,21 @@ static hipError_t couple_st(Context* c, int substep) {
   constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = DirectShape<ST>::kLanes;
   const int L = (!a.direct || a.rec) ? kL1 : kL2;
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
+  // with position-dependent forces (never recorded) the kernel also bins
+  const bool bin = c->plan.any_forces2 && !a.rec;
+  const dim3 b(kBlock);
   if (ST == 0 && a.rec && a.direct)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, true>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, true, false>), cgrid, b, 0, c->stream, a);
   else if (ST == 0 && a.rec)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false, false>), cgrid, b, 0, c->stream, a);
+  else if (!a.direct && bin)
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false, true>), cgrid, b, 0, c->stream, a);
   else if (!a.direct)
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false>), cgrid, dim3(kBlock), 0, c->stream,
-                       a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false, false>), cgrid, b, 0, c->stream, a);
+  else if (bin)
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true, true>), cgrid, b, 0, c->stream, a);
   else
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true>), cgrid, dim3(kBlock), 0, c->stream,
-                       a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true, false>), cgrid, b, 0, c->stream, a);
   // variants 2 and 3: transfers to shared sites wait until every particle
   // has read J; with position-dependent forces that work rides in extra
   // blocks of the force kernel's launch, which follows anyway

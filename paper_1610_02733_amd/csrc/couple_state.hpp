@@ -40,6 +40,11 @@ struct CoupleArgs {
   int32_t* __restrict__ mseg;    //   their number in the segment
   int direct;  // variants 2 and 3: the coupling kernel itself updates J at sites
                // only one particle claimed in the interval
+  // force cells (position-dependent forces): the coupling kernel bins the
+  // particles at their new positions for the force kernel
+  int32_t* __restrict__ bin_count;  // [cells] particles per cell (zero on entry)
+  int32_t* __restrict__ bin;        // [N] cell of each particle (-1: none)
+  int32_t* __restrict__ bin_rank;   // [N] slot inside the cell
   size_t P;     // population stride
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
@@ -180,6 +185,9 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.mlist = (int32_t*)at(c, L.mlist);
   a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
   a.direct = c->p[0].variant >= 2 ? 1 : 0;
+  a.bin_count = (int32_t*)at(c, L.bin_count);
+  a.bin = (int32_t*)at(c, L.bin_of);
+  a.bin_rank = (int32_t*)at(c, L.bin_rank);
   a.P = (size_t)c->plan.Stot;
   a.N = c->plan.Ntot;
   a.substep = substep;

@@ -14,21 +14,13 @@ namespace lbmd_impl {
 
 // ---------------------------------------------------------------------------
 // Binning: cell = floor(x / edge) per axis on each replica's grid of
-// nb[0] x nb[1] x nb[2] cells of edge L / nb >= the pair cut-off; cells of all
-// replicas share one global index space (offset cell_off).  Non-finite
-// particles go to no cell (they are left out of the force loop).
+// nb[0] x nb[1] x nb[2] cells of edge L / nb >= the pair cut-off (local_cell);
+// cells of all replicas share one global index space (offset cell_off).
+// Non-finite particles go to no cell (they are left out of the force loop).
+// After an MD step the coupling kernel has already counted the particles
+// into their cells (it knows the new positions first), so only the scan and
+// the scatter follow; k_bin_count serves the binning at bound positions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int local_cell(const double X[3], const RepMD& m) {
-  int c[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int q = (int)floor(X[d] * m.inv_edge[d]);
-    q = q < 0 ? 0 : (q >= m.nb[d] ? m.nb[d] - 1 : q);
-    c[d] = q;
-  }
-  return c[0] + m.nb[0] * (c[1] + m.nb[1] * c[2]);
-}
-
 __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__ x, int64_t N,
                                                       const RepMD* __restrict__ md,
                                                       const int32_t* __restrict__ part_rep,
@@ -51,7 +43,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__
 // Exclusive scan of the n cell counts in two launches: per-block scans
 // (kScanTile cells per block, which also reset the counts) and a single-block
 // scan of the tile totals.  The start of cell c is then the in-tile scan plus
-// its tile's offset (bin_begin); the total sits at index n.
+// its tile's offset (bin_begin); the total sits at index n.  (Folding the
+// second launch into the first with a last-block counter needs a device-wide
+// fence in every block, which on this multi-die part costs far more than the
+// launch.)
 constexpr int kScanTile = 1024;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh) {
@@ -314,7 +309,9 @@ static ForceArgs<T> force_args(Context* c) {
 }
 
 // Bin the particles of bead-spring replicas (models 2, 3) into their cells.
-static hipError_t launch_binning(Context* c) {
+// counted: the coupling kernel of the MD step already filled count, bin
+// and rank.
+static hipError_t launch_binning(Context* c, bool counted) {
   const int64_t N = c->plan.Ntot;
   const Layout& L = c->plan.lay;
   const int pb = (int)((N + kBlock - 1) / kBlock);
@@ -324,9 +321,10 @@ static hipError_t launch_binning(Context* c) {
   int32_t* bin = (int32_t*)at(c, L.bin_of);
   int32_t* start = (int32_t*)at(c, L.bin_start);
   const int64_t n = c->plan.Ctot;
-  hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x, N,
-                     (const RepMD*)at(c, L.rep_md), (const int32_t*)at(c, L.part_rep), count, bin,
-                     rank);
+  if (!counted)
+    hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x,
+                       N, (const RepMD*)at(c, L.rep_md), (const int32_t*)at(c, L.part_rep), count,
+                       bin, rank);
   const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, c->stream, count, n, start,
                      tiles);
@@ -360,7 +358,7 @@ static hipError_t forces_t(Context* c) {
 hipError_t launch_forces(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e;
-  if (c->plan.any_forces2 && (e = launch_binning(c)) != hipSuccess) return e;
+  if (c->plan.any_forces2 && (e = launch_binning(c, false)) != hipSuccess) return e;
   return c->plan.prec == 32 ? forces_t<float, false, -1>(c) : forces_t<double, false, -1>(c);
 }
 
@@ -383,7 +381,7 @@ static hipError_t forces_and_kick_t(Context* c) {
 
 hipError_t launch_forces_and_kick(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
-  hipError_t e = launch_binning(c);
+  hipError_t e = launch_binning(c, !c->rec_part);
   if (e != hipSuccess) return e;
   return c->plan.prec == 32 ? forces_and_kick_t<float>(c) : forces_and_kick_t<double>(c);
 }

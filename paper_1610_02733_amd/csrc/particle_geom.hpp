@@ -33,6 +33,18 @@ __device__ __forceinline__ int cell_of(int c, int n) {
   return c < 0 ? c + n : c;
 }
 
+// Force cell of a position on its replica's cell grid (clamped to the grid).
+__device__ __forceinline__ int local_cell(const double X[3], const RepMD& m) {
+  int c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int q = (int)floor(X[d] * m.inv_edge[d]);
+    q = q < 0 ? 0 : (q >= m.nb[d] ? m.nb[d] - 1 : q);
+    c[d] = q;
+  }
+  return c[0] + m.nb[0] * (c[1] + m.nb[1] * c[2]);
+}
+
 // D3Q19 velocities in the library's order (opposite pairs adjacent).
 static __device__ const int8_t kVel[19][3] = {
     {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
