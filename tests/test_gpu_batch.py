@@ -119,6 +119,49 @@ def test_batch_replicas_match_oracle(lb, orc, variant, stencil):
             assert np.abs(B.particles(r)[1].cpu().numpy() - o.particles()[1]).max() < 1e-12
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_batch_mixed_force_models_match_oracle(lb, orc, variant):
+    """Replicas with different force models in one batch (Kremer-Grest
+    chains, harmonic + WCA chains, free particles, a uniform external force):
+    the coupling kernel bins only the bead-spring replicas, and the after-step
+    work of variants 2 and 3 rides in the force kernel's launch.  Every
+    replica must equal its own oracle run (FP64)."""
+    c, w, e, b = orc.tables()
+    common = dict(precision=64, n_sub=10, variant=variant)
+    reps, xs, vs = [], [], []
+    x, v = wl.chains((20, 20, 20), 12, 10, 0.01, 1.0, seed=33, bond=0.97, min_dist=0.95)
+    reps.append(((20, 20, 20), dict(common, kT=0.01, nu=0.3, seed=9, replica=0, n_particles=120,
+                                    friction=2.0, force_model=3, chain_len=10, k_bond=0.3,
+                                    r0_bond=1.5, wca_eps=0.01, wca_sigma=1.0)))
+    xs.append(x)
+    vs.append(v)
+    x, v = wl.chains((16, 16, 12), 6, 8, 1e-3, 1.0, seed=34, bond=0.97, min_dist=0.95)
+    reps.append(((16, 16, 12), dict(common, kT=1e-3, seed=10, replica=1, n_particles=48,
+                                    friction=1.0, force_model=2, chain_len=8, k_bond=0.3,
+                                    r0_bond=1.0, wca_eps=0.01, wca_sigma=1.0)))
+    xs.append(x)
+    vs.append(v)
+    x, v = wl.free_particles((10, 12, 8), 25, 1e-3, 1.0, 35)
+    reps.append(((10, 12, 8), dict(common, kT=1e-3, seed=11, replica=2, n_particles=25,
+                                   friction=1.5)))
+    xs.append(x)
+    vs.append(v)
+    x, v = wl.free_particles((8, 8, 8), 10, 1e-3, 1.0, 36)
+    reps.append(((8, 8, 8), dict(common, kT=1e-3, seed=12, replica=3, n_particles=10,
+                                 friction=0.5, force_model=1, f_ext=(1e-3, -2e-3, 5e-4))))
+    xs.append(x)
+    vs.append(v)
+    B = lb.Batch(reps)
+    B.bind_particles(xs, vs)
+    B.run_cycles(5)
+    for r, (shape, kw) in enumerate(reps):
+        o = orc.Oracle(*shape, **{k: v for k, v in kw.items() if k != "precision"})
+        o.set_particles(xs[r], vs[r])
+        o.cycle(5)
+        assert rel_pop(B.populations(r).cpu().numpy() + w[:, None], o.populations(), w, 1.0) < 1e-12, r
+        assert np.abs(B.particles(r)[1].cpu().numpy() - o.particles()[1]).max() < 1e-11, r
+
+
 def test_batch_nonfinite_replica_is_isolated(lb, orc):
     c, w, e, b = orc.tables()
     reps, xs, vs = make_replicas(5, 64, 2, seed=9)
