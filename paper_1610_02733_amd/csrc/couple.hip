@@ -137,9 +137,10 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 // every lane has one corner, and L = 4 with two corners each in variants 2
 // and 3; three-point stencil: L = 32, one site each).
 //
-// Each lane fetches its sites' cached moments (a particle that left its
-// cube since the refill gathers the new sites itself) and, in variants 2 and
-// 3, the sites' pending transfer; the interpolated fluid velocity (Eq. 5)
+// Each lane fetches its sites' cached moments (in variant 1 a particle that
+// left its cube since the refill gathers the new sites itself; in the direct
+// mode the after-step work of the previous step did that) and, in variants 2
+// and 3, the sites' pending transfer; the interpolated fluid velocity (Eq. 5)
 // is the sum over the lanes (butterfly shuffles, the same order on every
 // lane).  Friction + noise (Eq. 4, 6) and velocity Verlet are evaluated on
 // all lanes alike; lane 0 stores the particle.  Variant 1 then transfers
@@ -156,7 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
-// recorded for the reverse sweep (position NaN: particle skipped).
+// recorded for the reverse sweep (position NaN: particle skipped).  With Bin
+// (position-dependent forces follow), lane 0 also counts the particle into
+// its force cell at the new position.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double pick3(const double v[3], int c) {
   return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
