@@ -314,7 +314,7 @@ static hipError_t lb_adjoint_t(Context* c) {
   a.jbar = (Vec4<T>*)(s.ws + L.jbar);
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.nuacc = (double*)(s.ws + L.nuacc);
-  a.P = S;
+  a.P = (size_t)c->plan.P;
   a.t_lb = (long long)s.t_lb[j];
   const int blocks = (int)std::min<int64_t>(kAdjBlocks, (c->plan.Stot + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_collide_stream_adjoint<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
@@ -378,7 +378,8 @@ static hipError_t fold_t(Context* c) {
   hipLaunchKernelGGL(k_adjoint_fold<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
                      (const RepLB<T>*)at(c, c->plan.lay.rep_lb),
                      (const unsigned long long*)(s.ws + s.lay.mrec) + (size_t)s.slot * (S / 64),
-                     (Vec4<T>*)(s.ws + s.lay.abar), (T*)(s.ws + s.lay.pbar[1 - s.pbar_cur]), S);
+                     (Vec4<T>*)(s.ws + s.lay.abar), (T*)(s.ws + s.lay.pbar[1 - s.pbar_cur]),
+                     (size_t)c->plan.P);
   return hipGetLastError();
 }
 

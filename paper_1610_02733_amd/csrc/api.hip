@@ -90,13 +90,15 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
     pl.any_forces2 = pl.any_forces2 || (p[r].force_model >= 2 && p[r].n_particles > 0);
   }
   pl.item_off.push_back(pl.nitems);
+  pl.P = pop_stride(pl.Stot);
   Layout& L = pl.lay;
   const size_t S = (size_t)pl.Stot, N = (size_t)std::max<int64_t>(pl.Ntot, 1);
   const size_t C = (size_t)std::max<int64_t>(pl.Ctot, 1);
   const size_t t = pl.prec == 32 ? 4 : 8;
   size_t o = 0;
-  L.pop[0] = o; o = up(o + 19 * S * t);
-  L.pop[1] = o; o = up(o + 19 * S * t);
+  const size_t P = (size_t)pl.P;
+  L.pop[0] = o; o = up(o + 19 * P * t);
+  L.pop[1] = o; o = up(o + 19 * P * t);
   L.transfer = o; o = up(o + 4 * S * t);
   L.mark = o; o = up(o + (S / 64) * 8);
   L.rep_lb = o; o = up(o + (size_t)R * (pl.prec == 32 ? sizeof(RepLB<float>) : sizeof(RepLB<double>)));
@@ -591,11 +593,11 @@ struct StateLayout {
 
 StateLayout state_layout(const Context* c) {
   StateLayout s;
-  const size_t S = (size_t)c->plan.Stot, N = (size_t)c->plan.Ntot;
+  const size_t P = (size_t)c->plan.P, N = (size_t)c->plan.Ntot;
   const size_t t = c->plan.prec == 32 ? 4 : 8;
   size_t o = 0;
   s.counters = o; o = up(o + 16);
-  s.pop = o; o = up(o + 19 * S * t);
+  s.pop = o; o = up(o + 19 * P * t);
   s.x = o; o = up(o + 3 * N * 8);
   s.v = o; o = up(o + 3 * N * 8);
   s.img = o; o = up(o + 3 * N * 4);
@@ -609,12 +611,13 @@ AdjLayout adj_layout(const Context* c, int K) {
   const size_t S = (size_t)c->plan.Stot, N = (size_t)std::max<int64_t>(c->plan.Ntot, 1);
   const size_t t = c->plan.prec == 32 ? 4 : 8, n = (size_t)c->plan.n_sub, k = (size_t)K;
   size_t o = 0;
-  L.slots = o; o = up(o + (k - 1) * 19 * S * t);
+  const size_t P = (size_t)c->plan.P;
+  L.slots = o; o = up(o + (k - 1) * 19 * P * t);
   L.jrec = o; o = up(o + k * S * 4 * t);
   L.mrec = o; o = up(o + k * (S / 64) * 8);
   L.prec = o; o = up(o + k * n * kAdjRec * N * 8);
-  L.pbar[0] = o; o = up(o + 19 * S * t);
-  L.pbar[1] = o; o = up(o + 19 * S * t);
+  L.pbar[0] = o; o = up(o + 19 * P * t);
+  L.pbar[1] = o; o = up(o + 19 * P * t);
   L.jbar = o; o = up(o + S * 4 * t);
   L.abar = o; o = up(o + S * 4 * t);
   L.xbar = o; o = up(o + 3 * N * 8);
@@ -685,7 +688,7 @@ int lbmd_save_state(lbmd* c, void* d_dst) {
   const size_t t = c->plan.prec == 32 ? 4 : 8;
   int rc = fail(c, launch_store_counters(c, dst + sl.counters, c->t_lb, c->t_md));
   if (!rc)
-    rc = fail(c, hipMemcpyAsync(dst + sl.pop, c->popv[c->cur], 19 * (size_t)c->plan.Stot * t,
+    rc = fail(c, hipMemcpyAsync(dst + sl.pop, c->popv[c->cur], 19 * (size_t)c->plan.P * t,
                                 hipMemcpyDeviceToDevice, c->stream));
   if (!rc && N > 0) {
     rc = fail(c, hipMemcpyAsync(dst + sl.x, c->x, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -708,7 +711,7 @@ int lbmd_load_state(lbmd* c, const void* d_src) {
   const StateLayout sl = state_layout(c);
   const char* src = (const char*)d_src;
   const size_t t = c->plan.prec == 32 ? 4 : 8;
-  int rc = fail(c, hipMemcpyAsync(c->popv[c->cur], src + sl.pop, 19 * (size_t)c->plan.Stot * t,
+  int rc = fail(c, hipMemcpyAsync(c->popv[c->cur], src + sl.pop, 19 * (size_t)c->plan.P * t,
                                   hipMemcpyDeviceToDevice, c->stream));
   if (rc) return rc;
   return load_common(c, src, sl);
@@ -775,7 +778,8 @@ int lbmd_adjoint_record(lbmd* c, const void* d_state, int32_t ncycles) {
   const size_t t = c->plan.prec == 32 ? 4 : 8;
   const int n = c->plan.Ntot > 0 ? c->plan.n_sub : 0;
   void* base[2] = {at(c, c->plan.lay.pop[0]), at(c, c->plan.lay.pop[1])};
-  auto slot_ptr = [&](int j) { return (void*)(a.ws + L.slots + (size_t)(j - 1) * 19 * S * t); };
+  const size_t P = (size_t)c->plan.P;
+  auto slot_ptr = [&](int j) { return (void*)(a.ws + L.slots + (size_t)(j - 1) * 19 * P * t); };
   a.src.assign(ncycles, nullptr);
   a.t_lb.assign(ncycles, 0);
   a.t_md.assign(ncycles, 0);

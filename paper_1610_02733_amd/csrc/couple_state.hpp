@@ -188,7 +188,7 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.bin_count = (int32_t*)at(c, L.bin_count);
   a.bin = (int32_t*)at(c, L.bin_of);
   a.bin_rank = (int32_t*)at(c, L.bin_rank);
-  a.P = (size_t)c->plan.Stot;
+  a.P = (size_t)c->plan.P;
   a.N = c->plan.Ntot;
   a.substep = substep;
   a.variant = c->p[0].variant;

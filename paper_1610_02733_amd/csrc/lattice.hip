@@ -123,6 +123,13 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
   }
 }
 
+// Stride between the 19 population arrays.  With the arrays a power of two
+// apart (a 256^3 FP32 lattice is 64 MiB per array) the collide-stream
+// kernel measured 3% (256^3) to 16% (128^3) slower than with the stride
+// padded by 65536 + 1024 sites; pads were compared by measurement, the
+// memory-side address hashing being undocumented.
+int64_t pop_stride(int64_t Stot) { return Stot + kPopPad; }
+
 template <typename T>
 static StreamArgs<T> stream_args(Context* c) {
   StreamArgs<T> a;
@@ -136,7 +143,7 @@ static StreamArgs<T> stream_args(Context* c) {
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
   a.clock = (const Clock*)at(c, c->plan.lay.clock);
-  a.P = (size_t)c->plan.Stot;
+  a.P = (size_t)c->plan.P;
   a.R = c->plan.R;
   a.nitems = c->plan.nitems;
   a.varc = c->p[0].variant == 3 ? 1 : 0;
@@ -377,7 +384,7 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
   T* pop = (T*)c->popv[c->cur];
   const bool pend = c->p[0].variant == 3;
   hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
-                     (size_t)c->plan.Stot, site_off, g, (T*)plain, what == 0 ? 1 : 0,
+                     (size_t)c->plan.P, site_off, g, (T*)plain, what == 0 ? 1 : 0,
                      pend ? (const Vec4<T>*)at(c, c->plan.lay.transfer) : nullptr,
                      (const unsigned long long*)at(c, c->plan.lay.mark),
                      (const RepLB<T>*)at(c, c->plan.lay.rep_lb), rep);
@@ -396,10 +403,10 @@ hipError_t launch_get_transfer(Context* c, int rep, void* dst) {
 }
 
 // ---------------------------------------------------------------------------
-// Plain device copy with 16-byte non-temporal loads and stores on a
-// persistent grid: the read+write streaming ceiling the roofline of the
-// collide-stream kernel is set against (and the known-size dispatch the HBM
-// byte counters are calibrated with).
+// Plain device copy with 16-byte non-temporal loads and stores: the
+// read+write streaming ceiling the roofline of the collide-stream kernel is
+// set against (and the known-size dispatch the HBM byte counters are
+// calibrated with).
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -410,14 +417,12 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(const v4f* __restrict__ 
     __builtin_nontemporal_store(__builtin_nontemporal_load(src + t), dst + t);
 }
 
+// One 16-byte element per thread over the whole range (a persistent grid of
+// a few blocks per CU measured 10-20% slower).
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
-  int dev = 0, cu = 256;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cu = 256;
   const size_t n4 = bytes / 16;
   const size_t want = (n4 + kBlock - 1) / kBlock;
-  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)4 * cu));
+  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)1 << 30));
   hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, stream, (const v4f*)src,
                      (v4f*)dst, n4);
   return hipGetLastError();

@@ -23,6 +23,7 @@ using lbmd_dev::Geom;
 
 constexpr int kBlock = 256;  // threads per block; site chunks of the LB kernels
 constexpr int kRedWidth = 16;
+constexpr int64_t kPopPad = 66560;  // population stride pad, in sites (pop_stride)
 
 // Per-replica constants of the LB kernels (run precision T).
 template <typename T>
@@ -62,7 +63,7 @@ struct Clock {
 
 // Offsets (bytes) of the regions carved out of the caller's workspace.
 struct Layout {
-  size_t pop[2];     // [19][Stot] population deviations, pull storage
+  size_t pop[2];     // [19][P] population deviations, pull storage (P >= Stot)
   size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z, unused)
   size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
   size_t rep_lb;     // [R] RepLB<T>
@@ -112,6 +113,7 @@ struct Plan {
   int prec;
   int n_sub;
   int64_t Stot;  // padded total sites
+  int64_t P;     // population stride: Stot plus a pad (see pop_stride)
   int64_t Ntot;  // particles
   int64_t Ctot;  // force cells
   int nitems;    // 256-site work items of the LB kernels
@@ -129,11 +131,11 @@ struct Plan {
 // velocities it interpolated.  The reverse sweep then walks the recorded
 // cycles backwards.
 struct AdjLayout {
-  size_t slots;    // [K-1][19][Stot] T: populations read by cycles 1..K-1
+  size_t slots;    // [K-1][19][P] T: populations read by cycles 1..K-1
   size_t jrec;     // [K][Stot] Vec4<T>: transfer field at the LB step (valid at marked sites)
   size_t mrec;     // [K][Stot/64] uint64: mark words at the LB step
   size_t prec;     // [K][n_sub][kAdjRec][Ntot] double: particle records
-  size_t pbar[2];  // [19][Stot] T: adjoint of the stored (post-collision) populations
+  size_t pbar[2];  // [19][P] T: adjoint of the stored (post-collision) populations
   size_t jbar;     // [Stot] Vec4<T>: adjoint of the transfer field
   size_t abar;     // [Stot] Vec4<T>: adjoint of (j, rho) read by the MD steps
   size_t xbar, vbar, ubar;  // [3][Ntot] double
@@ -188,6 +190,7 @@ struct Context {
 inline void* at(const Context* c, size_t off) { return c->ws + off; }
 
 // Launchers (return hipError_t of the launch).
+int64_t pop_stride(int64_t Stot);
 hipError_t launch_collide_stream(Context* c);
 hipError_t launch_collide_stream_adjoint(Context* c);
 hipError_t launch_couple_adjoint(Context* c);
