@@ -47,7 +47,8 @@ def measured_traffic(launches_bytes_key="traffic_bytes"):
         return None
     rec = json.load(open(f))
     h = hashlib.sha256()
-    for src in ("paper_1610_02733_amd/csrc/lattice.hip", "paper_1610_02733_amd/csrc/lbmd_device.hpp"):
+    for src in ("paper_1610_02733_amd/csrc/lattice.hip", "paper_1610_02733_amd/csrc/lbmd_device.hpp",
+                "paper_1610_02733_amd/csrc/lbmd_internal.hpp", "paper_1610_02733_amd/csrc/forcing.hpp"):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest() != rec.get("source_sha256"):
         return None
