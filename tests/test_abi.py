@@ -47,3 +47,30 @@ def test_host_side_validation_without_gpu():
     out = ctypes.c_void_p()
     assert L.lb_create(ctypes.byref(q), None, 0, None, ctypes.byref(out)) == lbmd.EINVAL
     assert L.lbmd_strerror(lbmd.ESTATE)
+
+
+def test_host_side_validation_of_models_and_batches():
+    """Force models, stencils and batch compatibility are checked on the host
+    (workspace size 0 = rejected), before any device work."""
+    from paper_1610_02733_amd import lbmd
+    L = lbmd.lib()
+    ok = dict(n_particles=10, chain_len=5, force_model=3, r0_bond=1.5, k_bond=0.3,
+              wca_eps=0.01, wca_sigma=1.0)
+    p = lbmd.make_params((16, 16, 16), **ok)
+    assert L.lbmd_workspace_bytes(ctypes.byref(p)) > 0
+    for bad in (dict(ok, r0_bond=0.0), dict(ok, force_model=4), dict(stencil=2),
+                dict(stencil=-1)):
+        q = lbmd.make_params((16, 16, 16), **bad)
+        assert L.lbmd_workspace_bytes(ctypes.byref(q)) == 0, bad
+    three = lbmd.make_params((16, 16, 16), stencil=1, n_particles=4)
+    assert L.lbmd_workspace_bytes(ctypes.byref(three)) > L.lbmd_workspace_bytes(
+        ctypes.byref(lbmd.make_params((16, 16, 16), n_particles=4)))  # 27-site cache
+    # replicas of one batch share n_sub, precision, variant and stencil
+    arr = (lbmd.Params * 2)()
+    arr[0] = lbmd.make_params((8, 8, 8), n_sub=2)
+    arr[1] = lbmd.make_params((12, 10, 8), n_sub=2, force_model=2, n_particles=6, chain_len=3)
+    assert L.lbmd_batch_workspace_bytes(arr, 2) > 0
+    for key, val in (("n_sub", 3), ("variant", 1), ("precision", 64), ("stencil", 1)):
+        arr[1] = lbmd.make_params((12, 10, 8), **dict(dict(n_sub=2), **{key: val}))
+        assert L.lbmd_batch_workspace_bytes(arr, 2) == 0, key
+    assert L.lbmd_batch_workspace_bytes(arr, 0) == 0
