@@ -354,6 +354,44 @@ def test_full_size_sampled_parity(lb, orc, prec, variant):
     o.close()
 
 
+def test_full_size_sampled_parity_bench_launch(lb, orc):
+    """The same 256^3 workload in bench.py's own launch configuration: FP32,
+    variant 2, particles sorted after binding, and the cycle replayed from a
+    captured graph (lbmd_run_cycles).  Sorting only moves particles between
+    slots, so slot t is compared with the oracle's particle perm[t]."""
+    cfg = wl.CONFIGS["c3"]
+    shape = cfg["shape"]
+    x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
+                             cfg["seed"])
+    kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
+              friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
+              particle_mass=cfg["particle_mass"])
+    g = lb.Lattice(shape, precision=32, **kw)
+    g.bind_particles(x, v)
+    perm = g.sort_particles().cpu().numpy()
+    assert (np.sort(perm) == np.arange(cfg["n_particles"])).all()
+    g.run_cycles(1)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    for _ in range(cfg["n_sub"]):
+        o.md_couple_substep()
+    sites = np.random.default_rng(1).choice(int(np.prod(shape)), 2048, replace=False)
+    ref = o.lb_step_sampled(sites)
+    c, w, e, b = orc.tables()
+    dev = g.populations()[:, sites].double().cpu().numpy().T
+    rel = np.abs(dev + w * cfg["rho0"] - ref) / (w * cfg["rho0"])
+    print(f"256^3 fp32 variant 2, sorted, captured cycle, sampled sites: max {rel.max():.3e}")
+    assert rel.max() < TOL[32]
+    xo, vo, io = o.particles()
+    L = np.asarray(shape, float)[:, None]
+    xg = g.x.cpu().numpy() + L * g.img.cpu().numpy()
+    assert np.abs(xg - (xo + L * io)[:, perm]).max() <= TOL[32] * max(shape)
+    vs = max(np.abs(vo).max(), np.sqrt(cfg["kT"] / cfg["particle_mass"]))
+    assert np.abs(g.v.cpu().numpy() - vo[:, perm]).max() <= TOL[32] * vs
+    g.close()
+    o.close()
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_variant3_moments_and_site_update(lb, orc, prec):
     """Variant C mid-interval: after each MD step the populations hold the
