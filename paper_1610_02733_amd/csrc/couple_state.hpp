@@ -146,12 +146,13 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
     const int64_t seg = it - nseg;
     const int n = a.lseg[seg];
     const int64_t base = seg * (int64_t)(kBlock * per);
-    for (int e = threadIdx.x; e < n; e += kBlock) {
-      const Vec4<T> d = a.ldelta[base + e];
-      T* dst = (T*)(a.J + a.lsite[base + e]);
-      atomicAdd(dst + 0, d.x);
-      atomicAdd(dst + 1, d.y);
-      atomicAdd(dst + 2, d.z);
+    // one lane per (entry, component): the three adds to one site sit in
+    // neighbouring lanes of one instruction and reach the memory side as one
+    // request instead of three
+    for (int u = threadIdx.x; u < 3 * n; u += kBlock) {
+      const int e = u / 3, comp = u - 3 * e;
+      const T d = reinterpret_cast<const T*>(a.ldelta + base + e)[comp];
+      atomicAdd(reinterpret_cast<T*>(a.J + a.lsite[base + e]) + comp, d);
     }
   }
 }
