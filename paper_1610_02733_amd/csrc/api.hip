@@ -113,8 +113,6 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.sort_img = o; o = up(o + 3 * N * 4);
   L.fc_held = o; o = up(o + 3 * N * 8);
   L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
-  L.cc_cell = o; o = up(o + N * 4);
-  L.cc_stamp = o; o = up(o + N * 4);
   // direct-mode lists: per segment of kBlock coupling lanes, kBlock * (sites
   // per lane) transfer entries and kBlock / lanes particles; lanes x sites
   // per lane is 8 for the cube (8 x 1 or 4 x 2) and 32 for the three-point

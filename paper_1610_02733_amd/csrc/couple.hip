@@ -33,7 +33,6 @@ __device__ __forceinline__ T quad_sum(T v) {  // over the 4 lanes of a corner
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
   const T* __restrict__ pop = a.pop[a.clock->cur];
-  const int stamp = cache_stamp(a.clock);
   const int64_t lanes = a.N * kRefillLanes;
   // lanes come in whole particles (32 | kBlock), so a particle's lanes stay
   // together in every iteration
@@ -80,10 +79,6 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
     qz = quad_sum(qz);
     const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
     a.cc[(size_t)p * 32 + sl] = mine;
-    if (sl == 0) {
-      a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-      a.cc_stamp[p] = stamp;
-    }
     if (c == 0) claim_site(a, m.site_off + site);
   }
 }
@@ -93,7 +88,6 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
   const T* __restrict__ pop = a.pop[a.clock->cur];
-  const int stamp = cache_stamp(a.clock);
   const int64_t lanes = a.N * 32;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < lanes;
        t += (int64_t)gridDim.x * kBlock) {
@@ -123,37 +117,29 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     T drho, jx, jy, jz;
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-    if (k == 0) {
-      a.cc_cell[p] = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-      a.cc_stamp[p] = stamp;
-    }
     claim_site(a, m.site_off + site);
   }
 }
 
 // ---------------------------------------------------------------------------
 // One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
-// ceil(sites / L) sites of its stencil (cube: L = 8 in variant 1, where
-// every lane has one corner, and L = 4 with two corners each in variants 2
-// and 3; three-point stencil: L = 32, one site each).
+// ceil(sites / L) sites of its stencil (cube: four lanes with two corners
+// each, which halves the redundant per-particle arithmetic, or eight while
+// recording; three-point stencil: 32 lanes, one site each).
 //
-// Each lane fetches its sites' cached moments (in variant 1 a particle that
-// left its cube since the refill gathers the new sites itself; in the direct
-// mode the after-step work of the previous step did that) and, in variants 2
-// and 3, the sites' pending transfer; the interpolated fluid velocity (Eq. 5)
+// Each lane fetches its sites' cached moments (the refill, or for a particle
+// that changed cubes the after-step work of the previous step, filled them)
+// and the sites' pending transfer J; the interpolated fluid velocity (Eq. 5)
 // is the sum over the lanes (butterfly shuffles, the same order on every
-// lane).  Friction + noise (Eq. 4, 6) and velocity Verlet are evaluated on
-// all lanes alike; lane 0 stores the particle.  Variant 1 then transfers
-// the momentum right away (Eq. 7-8): the (site, component) adds of a
-// particle are spread over its lanes in rounds, so the lanes of one atomic
-// instruction share a few sites rather than touching 64 unrelated cache
-// lines (eight lanes measured faster here than four).  In variants 2 and 3
-// every particle must first read the velocities as of the end of the
-// previous MD step (variant 3 sees the same velocities as variant 2 inside
-// an interval; its transfer differs only in how the LB step applies it):
-// the kernel (Direct) writes the transfer at sites it alone claimed and
-// lists the rest for the after-step work (after_step_item).  There four
-// lanes with two corners each halve the redundant per-particle arithmetic.
+// lane) and includes J in variants 2 and 3 (variant 3 sees the same
+// velocities as variant 2 inside an interval; its transfer differs only in
+// how the LB step applies it).  Friction + noise (Eq. 4, 6) and velocity
+// Verlet are evaluated on all lanes alike; lane 0 stores the particle.  The
+// transfer -w_k dP (Eq. 7-8) is then written at once at sites only this
+// particle claimed in the interval, which no other particle reads or writes,
+// and listed for the after-step work (after_step_item) at shared sites,
+// because in variants 2 and 3 every particle must first read J as of the end
+// of the previous MD step.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
@@ -161,14 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 // (position-dependent forces follow), lane 0 also counts the particle into
 // its force cell at the new position.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double pick3(const double v[3], int c) {
-  return c == 0 ? v[0] : (c == 1 ? v[1] : v[2]);
-}
-
 // Lanes of the coupling kernel per particle: L lanes with ceil(sites / L)
-// stencil sites each (8 for the cube in variant 1, whose in-kernel transfer
-// spreads its atomics over the lanes; fewer in variants 2 and 3; 32 for the
-// three-point stencil).
+// stencil sites each.
 template <int L>
 struct CoupleShape {
   static constexpr int kLanes = L;
@@ -179,37 +159,17 @@ struct CoupleShape {
   }
 };
 
-// Transfer -w_k dP of one particle (Eq. 7-8) from its lanes: pair index
-// kLanes r + lane = 3 site + component, over as many rounds as needed.
-template <typename T, int ST, int L>
-__device__ __forceinline__ void transfer_from_lanes(Vec4<T>* __restrict__ J, const RepMD& m,
-                                                    const Cube& q, int lane, const double dp[3]) {
-  constexpr int kL = L, kPairs = 3 * Stencil<ST>::kSites;
-#pragma unroll
-  for (int rnd = 0; rnd < (kPairs + kL - 1) / kL; ++rnd) {
-    const int pair = rnd * kL + lane;
-    if (pair >= kPairs) break;
-    const int kc = pair / 3, c = pair - 3 * kc;
-    int cx, cy, cz, site;
-    double w;
-    Stencil<ST>::site(q, m.g, kc, cx, cy, cz, site, w);
-    atomicAdd(((T*)(J + m.site_off + site)) + c, (T)(-w * pick3(dp, c)));
-  }
-}
-
-template <typename T, bool Rec, int ST, int L, bool Direct, bool Bin>
+template <typename T, bool Rec, int ST, int L, bool Bin>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
   using Sh = CoupleShape<L>;
   constexpr int kPer = (St::kSites + L - 1) / L;
   static_assert(!Rec || ST == 0, "recording (adjoint) exists for the trilinear stencil only");
-  const T* __restrict__ pop = a.pop[a.clock->cur];
-  const int stamp = cache_stamp(a.clock);
   const unsigned long long t_md = (unsigned long long)(a.clock->t_md + a.substep);
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
   const int64_t lanes = N * Sh::kLanes;
-  // direct mode: entries of this block's segment, counted in LDS
+  // entries of this block's segment in the two lists, counted in LDS
   __shared__ int s_l, s_m;
   // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
   // are always active together, as the shuffles require; every thread of a
@@ -218,10 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < lanes; t0 += stride) {
     const int64_t t = t0 + threadIdx.x;
     const int64_t seg = t0 / kBlock;
-    if (Direct) {
-      if (threadIdx.x == 0) s_l = s_m = 0;
-      __syncthreads();
-    }
+    if (threadIdx.x == 0) s_l = s_m = 0;
+    __syncthreads();
     bool moved = false;
     int new_cell = 0;
     int gs_[kPer];
@@ -256,10 +214,6 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       const RepMD& m = a.md[rr];
       Cube q;
       St::locate(X, m.g, q);
-      const int cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
-      // Direct: every live particle's cache covers its current stencil (the
-      // refill, or the previous step's k_after_step for particles that moved)
-      const bool hit = Direct || (a.cc_stamp[p] == stamp && a.cc_cell[p] == cell);
       double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
       for (int jj = 0; jj < kPer; ++jj) {
@@ -271,25 +225,14 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         const int gs = m.site_off + site;
         gs_[jj] = gs;
         w_[jj] = w;
-        Vec4<T> cv;
-        if (hit) {
-          cv = *cache_entry<ST>(a, p, k);
-        } else {
-          // left the cube of the refill: this lane gathers its site
-          cv = gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
-          *cache_entry<ST>(a, p, k) = cv;
-          claim_site(a, gs);
-          if (k == 0) {
-            a.cc_cell[p] = cell;
-            a.cc_stamp[p] = stamp;
-          }
-        }
+        // every live particle's cache covers its current stencil (the
+        // refill, or the previous step's after-step work if it moved)
+        const Vec4<T> cv = *cache_entry<ST>(a, p, k);
         // fluid velocity at the particle (Eq. 5)
         double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-        jv_[jj] = Vec4<T>{T(0), T(0), T(0), T(0)};
-        if (a.variant >= 2) {
-          jv_[jj] = a.J[gs];
-          if (Direct) sh_[jj] = (a.shared_site[gs >> 6] >> (gs & 63)) & 1ull;
+        jv_[jj] = a.J[gs];
+        sh_[jj] = (a.shared_site[gs >> 6] >> (gs & 63)) & 1ull;
+        if (a.variant >= 2) {  // the fluid velocity includes the pending transfer
           jx += (double)jv_[jj].x;
           jy += (double)jv_[jj].y;
           jz += (double)jv_[jj].z;
@@ -357,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.bin[p] = -1;
         }
       }
-      if (Direct && k0 == 0) {
+      if (k0 == 0) {
         // the next MD step needs other sites if the stencil moved (a
         // non-finite new position is caught by that step)
         if (isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
@@ -367,45 +310,42 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           new_cell = qn.base[0] + m.g.nx * (qn.base[1] + m.g.ny * qn.base[2]);
         }
       }
-      if (a.variant == 1) transfer_from_lanes<T, ST, L>(a.J, m, q, k0, dp);
     }
-    if (Direct) {
-      // transfer -w_k dP (Eq. 7-8): a site only this particle claimed in the
-      // interval has no other reader or writer, so it takes the new value
-      // right away; transfers to shared sites wait in the step's list until
-      // every particle has read J (k_after_step)
+    // transfer -w_k dP (Eq. 7-8): a site only this particle claimed in the
+    // interval has no other reader or writer, so it takes the new value right
+    // away; transfers to shared sites wait in the step's list until every
+    // particle has read J (after_step_item)
 #pragma unroll
-      for (int jj = 0; jj < kPer; ++jj) {
-        const int gs = gs_[jj];
-        const double ww = gs >= 0 ? w_[jj] : 0.0;
-        const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
-        if (gs >= 0 && !sh_[jj]) {
-          Vec4<T> nv = jv_[jj];
-          nv.x += ax;
-          nv.y += ay;
-          nv.z += az;
-          a.J[gs] = nv;
-        }
-        if (gs >= 0 && sh_[jj]) {
-          const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
-          a.lsite[e] = gs;
-          a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
-        }
+    for (int jj = 0; jj < kPer; ++jj) {
+      const int gs = gs_[jj];
+      const double ww = gs >= 0 ? w_[jj] : 0.0;
+      const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
+      if (gs >= 0 && !sh_[jj]) {
+        Vec4<T> nv = jv_[jj];
+        nv.x += ax;
+        nv.y += ay;
+        nv.z += az;
+        a.J[gs] = nv;
       }
-      if (moved)
-        reinterpret_cast<int2*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
-            make_int2((int)p, new_cell);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        a.lseg[seg] = s_l;
-        a.mseg[seg] = s_m;
+      if (gs >= 0 && sh_[jj]) {
+        const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
+        a.lsite[e] = gs;
+        a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
       }
+    }
+    if (moved)
+      reinterpret_cast<int2*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
+          make_int2((int)p, new_cell);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.lseg[seg] = s_l;
+      a.mseg[seg] = s_m;
     }
   }
 }
 
-// After an MD step in the direct mode without a force kernel: the
-// after-step work (after_step_item) as a launch of its own.
+// After an MD step without a force kernel: the after-step work
+// (after_step_item) as a launch of its own.
 template <typename T, int ST>
 __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
                                                       int L) {
@@ -436,40 +376,33 @@ static hipError_t couple_st(Context* c, int substep) {
   const int64_t N = a.N;
   // the whole cache is refilled at the first MD step of an interval, and
   // after it was invalidated from outside (new populations, counters or
-  // particles): the direct mode relies on it covering every stencil
+  // particles): the coupling kernel relies on it covering every stencil
   if (substep == 0 || c->cache_dirty) {
     if ((e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
     c->cache_dirty = false;
   }
-  // lanes per particle of the coupling kernel: kL2 in the direct mode
-  // (unless recording), kL1 otherwise
-  constexpr int kL1 = ST == 0 ? 8 : 32, kL2 = DirectShape<ST>::kLanes;
-  const int L = (!a.direct || a.rec) ? kL1 : kL2;
+  // lanes per particle of the coupling kernel (eight while recording)
+  const int L = a.rec ? 8 : DirectShape<ST>::kLanes;
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
   // with position-dependent forces (never recorded) the kernel also bins
   const bool bin = c->plan.any_forces2 && !a.rec;
   const dim3 b(kBlock);
-  if (ST == 0 && a.rec && a.direct)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, true, false>), cgrid, b, 0, c->stream, a);
-  else if (ST == 0 && a.rec)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false, false>), cgrid, b, 0, c->stream, a);
-  else if (!a.direct && bin)
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false, true>), cgrid, b, 0, c->stream, a);
-  else if (!a.direct)
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL1, false, false>), cgrid, b, 0, c->stream, a);
+  if (ST == 0 && a.rec)
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, b, 0, c->stream, a);
   else if (bin)
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true, true>), cgrid, b, 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, DirectShape<ST>::kLanes, true>), cgrid, b, 0,
+                       c->stream, a);
   else
-    hipLaunchKernelGGL((k_couple<T, false, ST, kL2, true, false>), cgrid, b, 0, c->stream, a);
-  // variants 2 and 3: transfers to shared sites wait until every particle
-  // has read J; with position-dependent forces that work rides in extra
-  // blocks of the force kernel's launch, which follows anyway
-  if ((e = hipGetLastError()) != hipSuccess || !a.direct) return e;
+    hipLaunchKernelGGL((k_couple<T, false, ST, DirectShape<ST>::kLanes, false>), cgrid, b, 0,
+                       c->stream, a);
+  // transfers to shared sites wait until every particle has read J; with
+  // position-dependent forces that work rides in extra blocks of the force
+  // kernel's launch, which follows anyway
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (c->plan.any_forces2 && !a.rec) return hipSuccess;
-  const int Ld = (ST == 0 && a.rec) ? 8 : kL2;  // lanes of the direct kernel just launched
-  const int64_t nseg = (N * Ld + kBlock - 1) / kBlock;
+  const int64_t nseg = (N * L + kBlock - 1) / kBlock;
   hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(2 * nseg, c->tune.part_blocks)),
-                     dim3(kBlock), 0, c->stream, a, nseg, (St::kSites + Ld - 1) / Ld, Ld);
+                     dim3(kBlock), 0, c->stream, a, nseg, (St::kSites + L - 1) / L, L);
   return hipGetLastError();
 }
 
@@ -496,13 +429,11 @@ hipError_t launch_couple_refill_only(Context* c) {
   return c->plan.prec == 32 ? refill_t<float>(c) : refill_t<double>(c);
 }
 
-// Forget cached corner moments (after the populations or counters were
-// replaced from outside).
+// Forget cached corner moments (after the populations, counters or
+// particles were replaced from outside): the next MD step refills the cache.
 hipError_t invalidate_corner_cache(Context* c) {
-  if (c->plan.Ntot == 0) return hipSuccess;
-  c->cache_dirty = true;
-  return hipMemsetAsync(at(c, c->plan.lay.cc_stamp), 0, sizeof(int32_t) * c->plan.Ntot,
-                        c->stream);
+  if (c->plan.Ntot > 0) c->cache_dirty = true;
+  return hipSuccess;
 }
 
 }  // namespace lbmd_impl

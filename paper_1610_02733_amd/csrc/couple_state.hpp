@@ -1,7 +1,8 @@
 // State of the particle coupling shared by the coupling kernels and the
 // force kernel: the kernel arguments, the corner cache, site claims, the
 // moments of a site from its pulled populations, and the work that follows
-// an MD step in the direct transfer mode.
+// an MD step (the direct transfer: plain writes at sites one particle
+// claimed, lists for the shared ones).
 #pragma once
 
 #include "particle_geom.hpp"
@@ -22,8 +23,6 @@ struct CoupleArgs {
   unsigned long long* __restrict__ mark;
   double* __restrict__ fc_held;  // coupling force of the step (split kick)
   T* __restrict__ cc;
-  int32_t* __restrict__ cc_cell;
-  int32_t* __restrict__ cc_stamp;
   unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
@@ -31,15 +30,13 @@ struct CoupleArgs {
   const int32_t* __restrict__ pid;  // particle identity of each slot (noise counter)
   const Clock* __restrict__ clock;
   double* __restrict__ rec;  // recording: [kAdjRec][N] state and corner velocities of the step
-  // direct mode, per segment (one block-sized stretch of coupling lanes):
+  // per segment (one block-sized stretch of coupling lanes):
   int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
   Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
   int32_t* __restrict__ lseg;    //   entries in the segment
   int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int2:
                                  //   slot, replica-local index of the new stencil base),
   int32_t* __restrict__ mseg;    //   their number in the segment
-  int direct;  // variants 2 and 3: the coupling kernel itself updates J at sites
-               // only one particle claimed in the interval
   // force cells (position-dependent forces): the coupling kernel bins the
   // particles at their new positions for the force kernel
   int32_t* __restrict__ bin_count;  // [cells] particles per cell (zero on entry)
@@ -56,10 +53,6 @@ struct CoupleArgs {
 template <int ST = 0, typename T>
 __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
   return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
-}
-
-__device__ __forceinline__ int cache_stamp(const Clock* clk) {
-  return (int)(((unsigned long long)clk->t_lb & 0x3FFFFFFFull) + 1);
 }
 
 // Mark a site as a receiver of momentum transfer in this LB interval; a site
@@ -87,11 +80,11 @@ __device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop
   return Vec4<T>{jx, jy, jz, T(1) / (rho0 + drho)};
 }
 
-// After an MD step in the direct mode (variants 2 and 3), once every
-// particle has read J: the particles whose stencil moved gather the moments
-// of their new sites and claim them, one lane per site, before the next
-// step reads them; and the step's transfers to shared sites are applied
-// (atomic adds from the segment lists).  The two jobs are
+// After every MD step, once every particle has read J: the particles whose
+// stencil moved gather the moments of their new sites and claim them, one
+// lane per site, before the next step reads them; and the step's transfers
+// to shared sites are applied (atomic adds from the segment lists).  The
+// two jobs are
 // independent (a claim changes no J, the list was fixed by the coupling
 // kernel), so each segment of the coupling kernel (kBlock * per entries and
 // kBlock / L particles at most) gets one block per job: items [0, nseg)
@@ -99,9 +92,8 @@ __device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop
 // and items [nseg, 2 nseg) the transfers.  One block runs one item; the
 // work runs as a launch of its own (k_after_step) or in extra blocks of
 // the force kernel's launch.
-// Lanes per particle of the direct-mode coupling kernel (outside recording):
-// four with two corners each for the cube, one per site for the three-point
-// stencil.
+// Lanes per particle of the coupling kernel (outside recording): four with
+// two corners each for the cube, one per site for the three-point stencil.
 template <int ST>
 struct DirectShape {
   static constexpr int kLanes = ST == 0 ? 4 : 32;
@@ -117,7 +109,6 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
     const int nm = a.mseg[seg] * St::kLanes;
     if (nm == 0) return;
     const T* __restrict__ pop = a.pop[a.clock->cur];
-    const int stamp = cache_stamp(a.clock);
     const int2* __restrict__ ml = reinterpret_cast<const int2*>(a.mlist) + seg * (kBlock / L);
     for (int u = threadIdx.x; u < nm; u += kBlock) {
       const int k = u % St::kLanes;
@@ -137,10 +128,6 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
       *cache_entry<ST>(a, p, k) =
           gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
       claim_site(a, m.site_off + site);
-      if (k == 0) {
-        a.cc_cell[p] = ent.y;
-        a.cc_stamp[p] = stamp;
-      }
     }
   } else {
     const int64_t seg = it - nseg;
@@ -171,8 +158,6 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.mark = (unsigned long long*)at(c, L.mark);
   a.fc_held = (double*)at(c, L.fc_held);
   a.cc = (T*)at(c, L.cc);
-  a.cc_cell = (int32_t*)at(c, L.cc_cell);
-  a.cc_stamp = (int32_t*)at(c, L.cc_stamp);
   a.shared_site = (unsigned long long*)at(c, L.shared_site);
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
@@ -185,7 +170,6 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.lseg = (int32_t*)at(c, L.seg_count);
   a.mlist = (int32_t*)at(c, L.mlist);
   a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
-  a.direct = c->p[0].variant >= 2 ? 1 : 0;
   a.bin_count = (int32_t*)at(c, L.bin_count);
   a.bin = (int32_t*)at(c, L.bin_of);
   a.bin_rank = (int32_t*)at(c, L.bin_rank);

@@ -130,9 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
 // stores the force and, after an MD step, applies the second half-kick of
 // velocity Verlet (new conservative force + the coupling force held over the
-// step).  In variants 2 and 3 the launch also carries the after-step work of
-// the direct transfer mode in extra blocks: this kernel runs after every
-// particle of the step has read the transfer field.
+// step).  After an MD step the launch also carries the step's after-step
+// work in extra blocks: this kernel runs after every particle of the step
+// has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -163,8 +163,8 @@ struct ForceArgs {
   int64_t ncells;
 };
 
-// Blocks [0, nfb) compute the forces; with AfterST >= 0 (variants 2 and 3,
-// direct transfer mode) blocks [nfb, nfb + 2 nseg) do the after-step work
+// Blocks [0, nfb) compute the forces; with AfterST >= 0 (after an MD step,
+// not recording) blocks [nfb, nfb + 2 nseg) do the after-step work
 // of the MD step just taken (after_step_item), which is independent of the
 // forces: it touches J, the claims and the corner cache only.
 template <typename T, bool Kick, int AfterST>
@@ -370,12 +370,12 @@ hipError_t launch_init_forces(Context* c) {
 }
 
 // After an MD step of replicas with position-dependent forces: binning,
-// forces at the new positions, the second half-kick and, in variants 2 and
-// 3, the after-step work of the direct transfer mode in the same launch (so
-// the coupling step launches no after-step kernel of its own).
+// forces at the new positions, the second half-kick and the step's
+// after-step work in the same launch (so the coupling step launches no
+// after-step kernel of its own).
 template <typename T>
 static hipError_t forces_and_kick_t(Context* c) {
-  if (c->p[0].variant < 2 || c->rec_part) return forces_t<T, true, -1>(c);
+  if (c->rec_part) return forces_t<T, true, -1>(c);
   return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c) : forces_t<T, true, 0>(c);
 }
 

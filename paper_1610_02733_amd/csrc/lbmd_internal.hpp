@@ -79,8 +79,6 @@ struct Layout {
   size_t sort_img;   // [3][Ntot] int32: particle sort scratch (image counters)
   size_t fc_held;    // [3][Ntot] double: coupling force of the MD step (split kick)
   size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
-  size_t cc_cell;    // [Ntot] int32: cube (lower corner, replica-local) cached
-  size_t cc_stamp;   // [Ntot] int32: LB step + 1 at which the cache was filled
   size_t slist_site;  // [sites per stencil * Ntot] int32: shared-site transfers of an MD step
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
   size_t mlist;      // [segments * kBlock / lanes] int2: particles whose stencil moved, new base
