@@ -136,9 +136,9 @@ def test_dense_particles_share_sites(lb, orc, prec):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_cube_changes_into_claimed_sites(lb, orc, prec, variant):
-    """Variants 2 and 3 write the transfer directly at sites only one
+    """Every variant writes the transfer directly at sites only one
     particle claimed in the LB interval; a particle that changes cubes claims
     its new sites between two MD steps, which can turn a site another
     particle owned alone into a shared one.  Fast particles (about 0.3 sites
