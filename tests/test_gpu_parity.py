@@ -156,6 +156,38 @@ def test_cube_changes_into_claimed_sites(lb, orc, prec, variant):
     check_particles(g, o, shape, TOL[prec], 1e-4)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_populations_replaced_mid_interval(lb, orc, variant):
+    """Populations replaced from outside between two MD steps of an interval
+    (the pending transfer is kept): the next MD step refills every particle's
+    corner cache from the new state and claims its sites again, and the run
+    must go on exactly as the oracle's, which reads the populations
+    directly (FP64)."""
+    shape = (12, 10, 8)
+    x, v = wl.free_particles(shape, 60, 1e-3, 1.0, 9)
+    kw = dict(kT=1e-3, seed=4, n_particles=60, friction=2.0, n_sub=4, variant=variant)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=64, **kw)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    rng = np.random.default_rng(21)
+    for cyc in range(3):
+        for s in range(4):
+            if cyc == 1 and s == 2:
+                new = g.populations().cpu().numpy() + 1e-4 * w[:, None] * rng.standard_normal(
+                    (19, int(np.prod(shape))))
+                g.set_populations(new)
+                o.set_populations(new + w[:, None])
+            g.md_couple_substep()
+            o.md_couple_substep()
+        g.lb_step()
+        o.lb_step()
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < 1e-12, err
+    check_particles(g, o, shape, 1e-12, 1e-3)
+
+
 def test_n1_variants_coincide(lb, orc):
     """For n = 1 the two variants are the same algorithm (Sec. 3)."""
     shape = (8, 8, 8)
