@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 // One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
 // ceil(sites / L) sites of its stencil (cube: four lanes with two corners
 // each, which halves the redundant per-particle arithmetic, or eight while
-// recording; three-point stencil: 32 lanes, one site each).
+// recording; three-point stencil: eight lanes with up to four sites each).
 //
 // Each lane fetches its sites' cached moments (the refill, or for a particle
 // that changed cubes the after-step work of the previous step, filled them)

@@ -96,14 +96,17 @@ __device__ __forceinline__ double oct_sum(double v) {  // over the 8 lanes of a 
 // A particle's stencil is described by a Cube: the lowest site index per
 // axis (wrapped) and the offset s of the particle from a reference site.
 //   ST = 0, trilinear: the 8 corners of the cube with lower corner floor(X),
-//     s = X - floor(X); one lane per corner (8 lanes).
+//     s = X - floor(X).
 //   ST = 1, three-point kernel per axis (Roma, Peskin and Berger 1999; the
 //     higher-order scheme the paper mentions, Sec. 4): the 3 sites nearest
 //     along each axis, c - 1, c, c + 1 with c = floor(X + 1/2), s = X - c;
 //     the axis weight of a site at distance r from the particle is
 //       (1 + sqrt(1 - 3 r^2)) / 3                for |r| <= 1/2,
 //       (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6 for 1/2 <= |r| <= 3/2;
-//     27 sites, one lane each in groups of 32 (lanes 27-31 idle).
+//     27 sites.
+// kLanes is the lane count per particle of the kernels that gather a
+// stencil's sites one lane each (refill, re-gather after a cube change):
+// 8, or 32 with lanes 27-31 idle.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double kernel3(double r) {
   const double a = fabs(r);
@@ -125,7 +128,6 @@ struct Stencil<0> {
                                               int& cy, int& cz, int& s, double& w) {
     corner_of(q, g, k, cx, cy, cz, s, w);
   }
-  __device__ static __forceinline__ double lane_sum(double v) { return oct_sum(v); }
 };
 
 template <>
@@ -152,14 +154,6 @@ struct Stencil<1> {
     s = cx + g.nx * (cy + g.ny * cz);
     w = kernel3(q.s[0] - (double)(ox - 1)) * kernel3(q.s[1] - (double)(oy - 1)) *
         kernel3(q.s[2] - (double)(oz - 1));
-  }
-  __device__ static __forceinline__ double lane_sum(double v) {  // over 32 lanes
-    v += __shfl_xor(v, 1, 32);
-    v += __shfl_xor(v, 2, 32);
-    v += __shfl_xor(v, 4, 32);
-    v += __shfl_xor(v, 8, 32);
-    v += __shfl_xor(v, 16, 32);
-    return v;
   }
 };
 
