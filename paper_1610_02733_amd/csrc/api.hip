@@ -115,7 +115,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
   // transfer lists: per segment of kBlock coupling lanes, kBlock * (sites
   // per lane) transfer entries and kBlock / lanes particles; lanes x sites
-  // per lane is 8 for the cube (8 x 1 while recording, 4 x 2) and 32 for the
+  // per lane is 8 for the cube (8 x 1 while recording, 2 x 4) and 32 for the
   // three-point stencil (8 x 4)
   const size_t lanes_max = p[0].stencil == 1 ? 32 : 8;
   pl.nseg = (int64_t)((N * lanes_max + kBlock - 1) / kBlock);

@@ -123,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // One MD step (Sec. 3, Eq. 4-8), L lanes per particle, each with
-// ceil(sites / L) sites of its stencil (cube: four lanes with two corners
-// each, which halves the redundant per-particle arithmetic, or eight while
+// ceil(sites / L) sites of its stencil (cube: two lanes with four corners
+// each, which cuts the redundant per-particle arithmetic, or eight while
 // recording; three-point stencil: eight lanes with up to four sites each).
 //
 // Each lane fetches its sites' cached moments (the refill, or for a particle

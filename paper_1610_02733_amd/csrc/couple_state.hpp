@@ -92,13 +92,14 @@ __device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop
 // and items [nseg, 2 nseg) the transfers.  One block runs one item; the
 // work runs as a launch of its own (k_after_step) or in extra blocks of
 // the force kernel's launch.
-// Lanes per particle of the coupling kernel (outside recording): four with
-// two corners each for the cube, eight with up to four sites each for the
-// three-point stencil (fewer lanes repeat less per-particle arithmetic: 72
-// against 91 us per MD step with one lane per site).
+// Lanes per particle of the coupling kernel (outside recording): two with
+// four corners each for the cube, eight with up to four sites each for the
+// three-point stencil.  Fewer lanes repeat less per-particle arithmetic (72
+// against 91 us per MD step with one lane per site of the three-point
+// stencil) until registers limit the waves in flight.
 template <int ST>
 struct DirectShape {
-  static constexpr int kLanes = ST == 0 ? 4 : 8;
+  static constexpr int kLanes = ST == 0 ? 2 : 8;
   static constexpr int kPer = (Stencil<ST>::kSites + kLanes - 1) / kLanes;
 };
 
