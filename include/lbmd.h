@@ -57,7 +57,11 @@ enum {
   LBMD_TOT_U2FLUID = 11, /* mean over sites of |j/rho|^2 (variant 3: |(j+J)/rho|^2) */
   LBMD_TOT_TLB = 12,     /* LB steps done                                     */
   LBMD_TOT_TMD = 13,     /* MD steps done                                     */
-  LBMD_NTOTALS = 14
+  LBMD_TOT_TPART = 14,   /* particle temperature sum_p m |v_p|^2 / (3 N) with
+                            k_B = 1 (the mean kinetic energy of Sec. 3, no
+                            centre-of-mass subtraction; 0 when N = 0, NaN
+                            once a particle is non-finite)                    */
+  LBMD_NTOTALS = 15
 };
 
 /*

@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "lbmd_oracle.c")
 _LIB = os.path.join(_HERE, "liblbmd_oracle.so")
 
 Q = 19
-NTOTALS = 14
+NTOTALS = 15
 
 
 def build(force: bool = True) -> str:

@@ -808,7 +808,9 @@ int orc_md_couple_substep(orc_ctx *c) {
 /* totals: [0] M = sum rho, [1..3] sum j + sum J, [4..6] momentum seen by the */
 /* coupling (variant A: sum j; variant B: sum j + sum J), [7..9] sum m v,     */
 /* [10] sum m v^2 / 2, [11] mean over sites of |j/rho|^2, [12] t_LB, [13]    */
-/* t_MD.                                                                     */
+/* t_MD, [14] particle temperature T_p = sum m |v|^2 / (3 N) (k_B = 1; the   */
+/* mean kinetic energy per degree of freedom, no centre-of-mass subtraction; */
+/* 0 without particles).                                                     */
 /* ------------------------------------------------------------------------- */
 int orc_moments(const orc_ctx *c, double *rho_out, double *u_out, double *totals) {
   int64_t S = c->nsites, N = c->p.n_particles;
@@ -848,6 +850,7 @@ int orc_moments(const orc_ctx *c, double *rho_out, double *u_out, double *totals
     totals[11] = u2 / (double)S;
     totals[12] = (double)c->t_lb;
     totals[13] = (double)c->t_md;
+    totals[14] = N > 0 ? 2.0 * ke / (3.0 * (double)N) : 0.0;
   }
   return ORC_OK;
 }

@@ -507,6 +507,7 @@ static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* 
     h[LBMD_TOT_U2FLUID] = t[7] / S;
     h[LBMD_TOT_TLB] = (double)c->t_lb;
     h[LBMD_TOT_TMD] = (double)c->t_md;
+    h[LBMD_TOT_TPART] = p.n_particles > 0 ? m * t[11] / (3.0 * p.n_particles) : 0.0;
   }
   return flags[0] ? LBMD_ENONFINITE : LBMD_OK;
 }

@@ -17,9 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmd.so")
 
 OK, EINVAL, ESTATE, EHIP, ENOSPACE, ENONFINITE = 0, -1, -2, -3, -4, -5
-NTOTALS = 14
+NTOTALS = 15
 TOT = dict(mass=0, pfluid=slice(1, 4), pseen=slice(4, 7), ppart=slice(7, 10), ke=10,
-           u2=11, t_lb=12, t_md=13)
+           u2=11, t_lb=12, t_md=13, tpart=14)
 # D3Q19 weights in the library's velocity order (include/lbmd.h): rest,
 # the 6 axis directions, the 12 face diagonals.
 WEIGHTS = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
@@ -400,14 +400,13 @@ class Batch(_System):
         return out
 
     def temperatures(self):
-        """Particle temperature over kT per replica, 2 KE / (3 N kT) (NaN for a
-        replica without particles or whose particles went non-finite)."""
-        tot = self.moments()
+        """Particle temperature T_p of every replica (the library's
+        LBMD_TOT_TPART) in units of its kT; NaN for a replica without
+        particles, with kT = 0, or whose particles went non-finite."""
+        tp = self.moments()[:, TOT["tpart"]]
         kT = np.array([self.params[r].kT for r in range(self.R)])
-        n = np.maximum(np.asarray(self.Ns, float), 1.0)
-        T = 2.0 * tot[:, TOT["ke"]] / (3.0 * n * np.where(kT > 0, kT, np.nan))
-        T[np.asarray(self.Ns) == 0] = np.nan
-        return T
+        ok = (np.asarray(self.Ns) > 0) & (kT > 0)
+        return np.where(ok, tp / np.where(ok, kT, 1.0), np.nan)
 
     def moments(self, allow_nonfinite=True):
         tot = np.zeros((self.R, NTOTALS))

@@ -778,3 +778,81 @@ def test_three_point_stencil_in_the_coupling(orc):
         sites, wts = o.stencil3_weights(R[:, 0])
         assert np.count_nonzero(np.abs(J).sum(0)) == 27
         assert np.allclose(J[:, sites], -wts[None, :] * dP[:, None], rtol=1e-12, atol=1e-20)
+
+
+# ----------------------------------------------------------------------------
+# the sampled LB step and the moments
+# ----------------------------------------------------------------------------
+def test_lb_step_sampled_equals_lb_step(orc):
+    """The sampled-site LB step (the reference of the full-size parity tests)
+    must give, bit for bit, the post-stream populations a full LB step writes
+    at those sites (Eq. 3): the same collision with the site's own transfer,
+    body force and noise counters, pulled along -c_i.  The full step is pinned
+    by the streaming, BGK-Guo, hydrodynamic and fluctuation tests above.
+    Ragged lattice, distinct rates, noise on, a step counter that is not 0."""
+    c, w, e, b = orc.tables()
+    shape = (7, 5, 6)
+    S = int(np.prod(shape))
+    o = orc.Oracle(*shape, nu=0.23, nu_bulk=0.11, gamma_ghost=-0.3, kT=2e-3, seed=9,
+                   body_force=(1e-4, -3e-5, 2e-5))
+    rng = np.random.default_rng(5)
+    f = w[:, None] * (1 + 0.05 * rng.standard_normal((19, S)))
+    J = 1e-3 * rng.standard_normal((3, S))
+    o.set_populations(f)
+    o.set_J(J)
+    o.set_counters(17, 0, 0)
+    corners = [0, shape[0] - 1, S - 1, S - shape[0], shape[0] * shape[1] - 1]
+    sites = np.concatenate([corners, rng.choice(S, 40, replace=False)]).astype(np.int64)
+    got = o.lb_step_sampled(sites)
+    assert o.counters()["t_lb"] == 17  # the sampled step leaves the state alone
+    assert np.array_equal(o.J(), J)
+    o.lb_step()
+    full = o.populations()
+    assert np.array_equal(got, full[:, sites].T)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_moments_fields_and_totals_closed_form(orc, variant):
+    """Eq. 1-2 and the particle temperature of Sec. 3 (mean kinetic energy):
+    populations built here from the second-order polynomial equilibrium of
+    prescribed density and velocity fields have exactly those fields as their
+    zeroth and first moments, so the density and velocity fields, the mass,
+    the fluid momentum (plus a prescribed pending transfer), the momentum the
+    coupling sees, <|u|^2>, the particle momentum, kinetic energy and
+    temperature all have closed forms."""
+    c, w, e, b = orc.tables()
+    shape = (6, 5, 7)
+    nx, ny, nz = shape
+    S = nx * ny * nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()  # site index x + nx (y + ny z)
+    rho = 1.0 + 0.1 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny) + 0.03 * z / nz
+    u = np.stack([0.02 * np.cos(2 * np.pi * y / ny), -0.015 * np.sin(2 * np.pi * z / nz),
+                  0.01 * np.cos(2 * np.pi * (x / nx + y / ny))])
+    f = np.stack([feq_poly(c, w, rho[s], u[:, s]) for s in range(S)], 1)
+    N, m = 7, 2.5
+    rng = np.random.default_rng(8)
+    xp = rng.random((3, N)) * np.array(shape, float)[:, None]
+    vp = 0.3 * rng.standard_normal((3, N))
+    o = orc.Oracle(*shape, variant=variant, n_particles=N, particle_mass=m, n_sub=3)
+    o.set_populations(f)
+    o.set_particles(xp, vp)
+    J = 1e-3 * rng.standard_normal((3, S)) if variant != 3 else np.zeros((3, S))
+    o.set_J(J)
+    tot, rho_o, u_o = o.moments(fields=True)
+    assert np.allclose(rho_o, rho, rtol=0, atol=1e-15)
+    assert np.allclose(u_o, u, rtol=0, atol=1e-16)
+    mom = (rho * u).sum(1)
+    assert abs(tot[0] - rho.sum()) < 1e-12
+    assert np.allclose(tot[1:4], mom + J.sum(1), rtol=0, atol=1e-14)
+    seen = mom + (J.sum(1) if variant == 2 else 0.0)
+    assert np.allclose(tot[4:7], seen, rtol=0, atol=1e-14)
+    assert np.allclose(tot[7:10], m * vp.sum(1), rtol=1e-14, atol=1e-15)
+    ke = 0.5 * m * (vp ** 2).sum()
+    assert abs(tot[10] - ke) < 1e-14 * ke
+    assert abs(tot[11] - (u ** 2).sum(0).mean()) < 1e-17
+    assert abs(tot[14] - m * (vp ** 2).sum() / (3 * N)) < 1e-14 * ke
+    # no particles: the temperature total is 0 by definition
+    o0 = orc.Oracle(*shape, variant=variant)
+    o0.set_populations(f)
+    assert o0.moments()[14] == 0.0
