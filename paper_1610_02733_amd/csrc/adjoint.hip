@@ -29,7 +29,6 @@ struct AdjLBArgs {
   Vec4<T>* __restrict__ jbar;
   const RepLB<T>* __restrict__ rep;
   double* __restrict__ nuacc;                 // [gridDim][4]
-  size_t P;
   long long t_lb;
 };
 
@@ -53,13 +52,14 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream_adjoint(AdjLBArgs<T> 
   for (int r = blockIdx.x * kBlock + threadIdx.x; r < q.g.S; r += gridDim.x * kBlock) {
     int x, y, z;
     site_coords(q.g, r, x, y, z);
-    int sidx[19];
-    pull_sources(q.g, x, y, z, sidx);
+    size_t off[19];
+    pull_offsets(q.g, x, y, z, off);
+    const size_t own = pop_offset(q.g, 0, x, y, z);
     T d[19], dbo[19], dbi[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-      d[i] = __builtin_nontemporal_load(a.src + (size_t)i * a.P + sidx[i]);
-      dbo[i] = __builtin_nontemporal_load(a.pin + (size_t)i * a.P + r);
+      d[i] = __builtin_nontemporal_load(a.src + off[i]);
+      dbo[i] = __builtin_nontemporal_load(a.pin + own + (size_t)i * q.g.A);
     }
     const bool marked = (a.mrec[r >> 6] >> (r & 63)) & 1ull;
     T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream_adjoint(AdjLBArgs<T> 
     collide_deviation_adjoint<T>(d, Fx, Fy, Fz, hw, q.k, dbo, dbi, Fbx, Fby, Fbz, gb);
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-      __builtin_nontemporal_store(dbi[i], a.pout + (size_t)i * a.P + sidx[i]);
+      __builtin_nontemporal_store(dbi[i], a.pout + off[i]);
     if (marked) a.jbar[r] = Vec4<T>{Fbx, Fby, Fbz, T(0)};
     acc[0] += (double)gb[0];
     acc[1] += (double)gb[1];
@@ -112,18 +112,19 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adjoint_fold(const RepLB<T>* __restrict__ rep,
                                                          const unsigned long long* __restrict__ mrec,
                                                          Vec4<T>* __restrict__ abar,
-                                                         T* __restrict__ pout, size_t P) {
+                                                         T* __restrict__ pout) {
   const Geom& g = rep[0].g;
   for (int r = blockIdx.x * kBlock + threadIdx.x; r < g.S; r += gridDim.x * kBlock) {
     if (!((mrec[r >> 6] >> (r & 63)) & 1ull)) continue;
     const Vec4<T> ab = abar[r];
     abar[r] = Vec4<T>{T(0), T(0), T(0), T(0)};
-    int x, y, z, sidx[19];
+    int x, y, z;
+    size_t off[19];
     site_coords(g, r, x, y, z);
-    pull_sources(g, x, y, z, sidx);
+    pull_offsets(g, x, y, z, off);
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-      pout[(size_t)i * P + sidx[i]] +=
+      pout[off[i]] +=
           ab.w + (T)kVel[i][0] * ab.x + (T)kVel[i][1] * ab.y + (T)kVel[i][2] * ab.z;
   }
 }
@@ -314,7 +315,6 @@ static hipError_t lb_adjoint_t(Context* c) {
   a.jbar = (Vec4<T>*)(s.ws + L.jbar);
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.nuacc = (double*)(s.ws + L.nuacc);
-  a.P = (size_t)c->plan.P;
   a.t_lb = (long long)s.t_lb[j];
   const int blocks = (int)std::min<int64_t>(kAdjBlocks, (c->plan.Stot + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_collide_stream_adjoint<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a);
@@ -378,8 +378,7 @@ static hipError_t fold_t(Context* c) {
   hipLaunchKernelGGL(k_adjoint_fold<T>, dim3(blocks), dim3(kBlock), 0, c->stream,
                      (const RepLB<T>*)at(c, c->plan.lay.rep_lb),
                      (const unsigned long long*)(s.ws + s.lay.mrec) + (size_t)s.slot * (S / 64),
-                     (Vec4<T>*)(s.ws + s.lay.abar), (T*)(s.ws + s.lay.pbar[1 - s.pbar_cur]),
-                     (size_t)c->plan.P);
+                     (Vec4<T>*)(s.ws + s.lay.abar), (T*)(s.ws + s.lay.pbar[1 - s.pbar_cur]));
   return hipGetLastError();
 }
 

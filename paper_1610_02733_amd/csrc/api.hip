@@ -77,7 +77,9 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   pl.Stot = pl.Ntot = pl.Ctot = 0;
   pl.nitems = 0;
   pl.any_forces2 = false;
+  pl.row_replicas = 0;
   for (int r = 0; r < R; ++r) {
+    pl.row_replicas += row_path(p[r]) ? 1 : 0;
     const int64_t S = (int64_t)p[r].nx * p[r].ny * p[r].nz;
     pl.site_off.push_back(pl.Stot);
     pl.part_off.push_back(pl.Ntot);
@@ -90,7 +92,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
     pl.any_forces2 = pl.any_forces2 || (p[r].force_model >= 2 && p[r].n_particles > 0);
   }
   pl.item_off.push_back(pl.nitems);
-  pl.P = pop_stride(pl.Stot);
+  pl.P = pl.Stot;  // each buffer holds 19 * Stot values: replica r at 19 * site_off[r]
   Layout& L = pl.lay;
   const size_t S = (size_t)pl.Stot, N = (size_t)std::max<int64_t>(pl.Ntot, 1);
   const size_t C = (size_t)std::max<int64_t>(pl.Ctot, 1);
@@ -151,6 +153,7 @@ Geom geom_of(const lbmd_params& p) {
   g.ny = p.ny;
   g.nz = p.nz;
   g.S = p.nx * p.ny * p.nz;
+  g.A = p.nx * p.ny;
   g.inv_nx = 1.0 / p.nx;
   g.inv_ny = 1.0 / p.ny;
   return g;
@@ -163,6 +166,7 @@ RepLB<T> rep_lb(const Context* c, int r) {
   q.g = geom_of(p);
   q.site_off = (int)c->plan.site_off[r];
   q.item_off = (int)c->plan.item_off[r];
+  q.rows = row_path(p) ? 1 : 0;
   q.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(p.seed >> 32);
   q.tag0 = lbmd_dev::noise_tag(lbmd_dev::kPurposeFluid, p.replica, 0);

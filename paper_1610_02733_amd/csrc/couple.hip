@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
         sx = sx < 0 ? sx + m.g.nx : (sx >= m.g.nx ? sx - m.g.nx : sx);
         sy = sy < 0 ? sy + m.g.ny : (sy >= m.g.ny ? sy - m.g.ny : sy);
         sz = sz < 0 ? sz + m.g.nz : (sz >= m.g.nz ? sz - m.g.nz : sz);
-        const T d = pop[(size_t)i * a.P + m.site_off + sx + m.g.nx * (sy + m.g.ny * sz)];
+        const T d = pop[19 * (size_t)m.site_off + pop_offset(m.g, i, sx, sy, sz)];
         drho += d;
         qx += (T)ex * d;
         qy += (T)ey * d;
@@ -109,11 +109,12 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     int cx, cy, cz, site;
     double w;
     Stencil<1>::site(q, m.g, k, cx, cy, cz, site, w);
-    int sidx[19];
-    pull_sources(m.g, cx, cy, cz, sidx);
+    size_t off[19];
+    pull_offsets(m.g, cx, cy, cz, off);
+    const T* __restrict__ base = pop + 19 * (size_t)m.site_off;
     T d[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * a.P + m.site_off + sidx[i]];
+    for (int i = 0; i < 19; ++i) d[i] = base[off[i]];
     T drho, jx, jy, jz;
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};

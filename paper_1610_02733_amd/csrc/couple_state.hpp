@@ -42,7 +42,6 @@ struct CoupleArgs {
   int32_t* __restrict__ bin_count;  // [cells] particles per cell (zero on entry)
   int32_t* __restrict__ bin;        // [N] cell of each particle (-1: none)
   int32_t* __restrict__ bin_rank;   // [N] slot inside the cell
-  size_t P;     // population stride
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
   int variant;
@@ -67,14 +66,15 @@ __device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
 // (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
 // populations (for a particle whose cached stencil is out of date).
 template <typename T>
-__device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop, size_t P,
-                                                      int site_off, const Geom& g, int cx,
-                                                      int cy, int cz, T rho0) {
-  int sidx[19];
-  pull_sources(g, cx, cy, cz, sidx);
+__device__ __forceinline__ Vec4<T> gather_site_moments(const T* __restrict__ pop, int site_off,
+                                                      const Geom& g, int cx, int cy, int cz,
+                                                      T rho0) {
+  size_t off[19];
+  pull_offsets(g, cx, cy, cz, off);
+  const T* __restrict__ base = pop + 19 * (size_t)site_off;
   T d[19];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
+  for (int i = 0; i < 19; ++i) d[i] = base[off[i]];
   T drho, jx, jy, jz;
   moments_deviation<T>(d, drho, jx, jy, jz);
   return Vec4<T>{jx, jy, jz, T(1) / (rho0 + drho)};
@@ -129,7 +129,7 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
       double w;
       St::site(q, m.g, k, cx, cy, cz, site, w);
       *cache_entry<ST>(a, p, k) =
-          gather_site_moments<T>(pop, a.P, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+          gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
       claim_site(a, m.site_off + site);
     }
   } else {
@@ -176,7 +176,6 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.bin_count = (int32_t*)at(c, L.bin_count);
   a.bin = (int32_t*)at(c, L.bin_of);
   a.bin_rank = (int32_t*)at(c, L.bin_rank);
-  a.P = (size_t)c->plan.P;
   a.N = c->plan.Ntot;
   a.substep = substep;
   a.variant = c->p[0].variant;

@@ -29,18 +29,29 @@ __device__ __forceinline__ int replica_of_item(const int32_t* __restrict__ item_
 // Fused collide-and-stream, one thread per site, pull scheme.
 //
 // The source buffer holds post-collision deviations at the site that produced
-// them; the thread at site r gathers buffer[i][r - c_i] (the post-stream
-// state), adds the pending momentum transfer J(r) as the force density of
-// this LB step, collides and writes its 19 results at r in the other buffer
-// (coalesced).  J is only read where the site's bit in `mark` is set (the
-// coupling sets it when it transfers momentum there), and is cleared with it,
-// so the untouched bulk of the lattice costs no transfer traffic.  In
-// variant 3 (VarC) the interval's transfer already belongs to the state: the
-// collision adds it as the momentum and stress increments of the paper's
-// variant C and relaxes with the body force alone.  A work
-// item is 256 consecutive sites of one replica; replica offsets are
-// multiples of 64, so one wavefront owns exactly one 64-bit mark word.
-// Persistent grid: blocks stride over the items.
+// them; the thread at site r gathers population i from r - c_i (the
+// post-stream state), adds the pending momentum transfer J(r) as the force
+// density of this LB step, collides and writes its 19 results at r in the
+// other buffer (coalesced).  J is only read where the site's bit in `mark` is
+// set (the coupling sets it when it transfers momentum there), and is cleared
+// with it, so the untouched bulk of the lattice costs no transfer traffic.
+// In variant 3 (VarC) the interval's transfer already belongs to the state:
+// the collision adds it as the momentum and stress increments of the paper's
+// variant C and relaxes with the body force alone.  A work item is 256
+// consecutive sites of one replica; replica offsets are multiples of 64, so
+// one wavefront owns exactly one 64-bit mark word.  Persistent grid: blocks
+// stride over the items.
+//
+// Row path (replicas with nx = 64, 128 or 256: a wavefront is 64 sites of
+// one x row and an item holds whole rows).  Every thread loads the 19
+// entries at its own x in the rows that the y and z shifts select, so each
+// wavefront load is an aligned, contiguous 64-value run; the +-x shift of the
+// ten populations with c_x != 0 is then done in registers: a DPP rotation by
+// one lane inside the wavefront, and for the two end lanes of a wavefront the
+// value of the neighbouring wavefront of the same row (periodic) through LDS.
+// Gathering the shifted entries straight from memory instead makes each
+// wavefront touch a partial cache line on either side, which a neighbouring
+// wavefront fetches again (measured 1.06x the algorithmic traffic).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct StreamArgs {
@@ -53,82 +64,166 @@ struct StreamArgs {
   const Clock* __restrict__ clock;
   Vec4<T>* __restrict__ jrec;                 // recording: J consumed at marked sites
   unsigned long long* __restrict__ mrec;      // recording: mark words
-  size_t P;  // population stride (padded total sites)
   int R, nitems;
   int varc;  // variant 3: J belongs to the fluid state (fields read j + J)
 };
 
+// Values of the x neighbours inside a wavefront: lane l receives v of lane
+// l - 1 (from_left; lane 0 receives lane 63) or of lane l + 1 (from_right;
+// lane 63 receives lane 0).  DPP wave_ror:1 / wave_rol:1.
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x13C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x13C, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x134, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x134, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // With Rec, the transfer field and the mark words the step consumes are also
 // copied out for the reverse sweep (the adjoint needs the force density of
 // the step and the set of sites the MD steps touched).
-template <typename T, bool Rec, bool VarC>
+// Mode: 0 every replica takes the general path, 1 every replica the row
+// path, 2 per replica (a batch mixing both).
+template <typename T, bool Rec, bool VarC, int Mode>
 __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
+  // populations pulled from x - 1 (c_x = +1) and from x + 1 (c_x = -1)
+  constexpr int kFromLeft[5] = {1, 7, 9, 11, 13};
+  constexpr int kFromRight[5] = {2, 8, 10, 12, 14};
+  // row path: end-lane values of each wavefront, double-buffered by the
+  // parity of the block's row-path items (one barrier per such item, so a
+  // wavefront writing one buffer has passed the barrier that follows every
+  // read of it)
+  __shared__ T edge[2][2][kBlock / 64][5];
   const int cur = a.clock->cur;
   const long long t = a.clock->t_lb;
   const T* __restrict__ src = a.pop[cur];
   T* __restrict__ dst = a.pop[1 - cur];
   const uint32_t step_lo = (uint32_t)((unsigned long long)t & 0xFFFFFFFFull);
   const uint32_t step_hi = (uint32_t)((unsigned long long)t >> 32);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int par = 0;
   for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-    const int rr = a.R == 1 ? 0 : replica_of_item(a.item_off, a.R, item);
-    const RepLB<T>& q = a.rep[rr];
+    // the replica is uniform across the block: keep its constants in scalar
+    // registers
+    const int rr = __builtin_amdgcn_readfirstlane(
+        a.R == 1 ? 0 : replica_of_item(a.item_off, a.R, item));
+    const RepLB<T> q = scalar_copy(a.rep + rr);
     const int local = (item - q.item_off) * kBlock + threadIdx.x;
-    if (local >= q.g.S) continue;
-    const int gsite = q.site_off + local;
-    const unsigned long long word = a.mark[gsite >> 6];
+    const bool act = local < q.g.S;
+    const T* __restrict__ sbase = src + 19 * (size_t)q.site_off;
     int x, y, z;
-    site_coords(q.g, local, x, y, z);
-    int sidx[19];
-    pull_sources(q.g, x, y, z, sidx);
-    const T* __restrict__ sbase = src + q.site_off;
+    site_coords(q.g, act ? local : 0, x, y, z);
     T d[19];
-    // every population is read once per step: non-temporal loads keep the
-    // stream from evicting the transfer field and the mark words
+    const bool rows = Mode == 2 ? q.rows != 0 : Mode == 1;
+    if (rows) {
+      // aligned loads at this lane's own x.  Offsets are 32-bit here (the
+      // row path is taken only for replicas of fewer than 2^32 / 19 sites):
+      // population i of the row (y', z') is at plane(z') + i A + row(y'),
+      // with i A folded into the scalar base
+      const uint32_t A = (uint32_t)q.g.A;
+      const int ym = y == 0 ? q.g.ny - 1 : y - 1, yp = y == q.g.ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? q.g.nz - 1 : z - 1, zp = z == q.g.nz - 1 ? 0 : z + 1;
+      const uint32_t z0 = (uint32_t)z * 19u * A, zl = (uint32_t)zm * 19u * A,
+                     zh = (uint32_t)zp * 19u * A;
+      const uint32_t r0 = (uint32_t)(y * q.g.nx + x), rl = (uint32_t)(ym * q.g.nx + x),
+                     rh = (uint32_t)(yp * q.g.nx + x);
+      // (plane, row) of each population's source: z - c_z, y - c_y
+      const uint32_t o00 = z0 + r0, o0l = z0 + rl, o0h = z0 + rh;
+      const uint32_t ol0 = zl + r0, olh = zl + rh, oll = zl + rl;
+      const uint32_t oh0 = zh + r0, ohl = zh + rl, ohh = zh + rh;
+      const uint32_t off[19] = {o00, o00, o00, o0l, o0h, ol0, oh0, o0l, o0h, o0h,
+                                o0l, ol0, oh0, oh0, ol0, oll, ohh, ohl, olh};
+      // every population is read once per step: non-temporal loads keep the
+      // stream from evicting the transfer field and the mark words
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(sbase + (size_t)i * a.P + sidx[i]);
-
-    T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
-    T Jx = T(0), Jy = T(0), Jz = T(0);
-    if ((word >> (gsite & 63)) & 1ull) {
-      const Vec4<T> jv = a.J[gsite];
-      if (VarC) {
-        Jx = jv.x;
-        Jy = jv.y;
-        Jz = jv.z;
-      } else {
-        Fx += jv.x;
-        Fy += jv.y;
-        Fz += jv.z;
+      for (int i = 0; i < 19; ++i)
+        d[i] = act ? __builtin_nontemporal_load(sbase + (size_t)i * A + off[i]) : T(0);
+      // the x shift: rotate by one lane; the end lanes take the neighbouring
+      // wavefront's end value (periodic inside the row of nx/64 wavefronts)
+      if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) edge[par][0][wv][j] = d[kFromLeft[j]];
       }
-      a.J[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
-      if (Rec) a.jrec[gsite] = jv;
-    }
-    if (Rec && (gsite & 63) == 0) a.mrec[gsite >> 6] = word;
-    uint32_t hw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (q.k.noise) {
-      const Words4 o0 = philox10(Words4{(uint32_t)local, step_lo, q.tag0, step_hi}, q.key0, q.key1);
-      const Words4 o1 = philox10(Words4{(uint32_t)local, step_lo, q.tag1, step_hi}, q.key0, q.key1);
-      hw[0] = o0.w0; hw[1] = o0.w1; hw[2] = o0.w2; hw[3] = o0.w3;
-      hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
-    }
-    collide_deviation<T, VarC>(d, Fx, Fy, Fz, hw, q.k, Jx, Jy, Jz);
-    // every population is written once per step: stream the stores past the
-    // caches (non-temporal hint)
+      if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], dst + (size_t)i * a.P + gsite);
-    if ((gsite & 63) == 0 && word) {
-      a.mark[gsite >> 6] = 0ull;
-      a.shared_site[gsite >> 6] = 0ull;  // shared bits are a subset of the mark bits
+        for (int j = 0; j < 5; ++j) edge[par][1][wv][j] = d[kFromRight[j]];
+      }
+      __syncthreads();
+      const int wpr = q.g.nx >> 6;  // wavefronts per row: 1, 2 or 4
+      const int wl = wv & (wpr - 1), rb = wv - wl;
+      const int wleft = rb + ((wl + wpr - 1) & (wpr - 1));
+      const int wright = rb + ((wl + 1) & (wpr - 1));
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const T l = from_left(d[kFromLeft[j]]);
+        const T r = from_right(d[kFromRight[j]]);
+        d[kFromLeft[j]] = lane == 0 ? edge[par][0][wleft][j] : l;
+        d[kFromRight[j]] = lane == 63 ? edge[par][1][wright][j] : r;
+      }
+      par ^= 1;
+    } else if (act) {
+      size_t off[19];
+      pull_offsets(q.g, x, y, z, off);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) d[i] = __builtin_nontemporal_load(sbase + off[i]);
+    }
+    if (act) {
+      const int gsite = q.site_off + local;
+      const unsigned long long word = a.mark[gsite >> 6];
+      T Fx = q.k.g[0], Fy = q.k.g[1], Fz = q.k.g[2];
+      T Jx = T(0), Jy = T(0), Jz = T(0);
+      if ((word >> (gsite & 63)) & 1ull) {
+        const Vec4<T> jv = a.J[gsite];
+        if (VarC) {
+          Jx = jv.x;
+          Jy = jv.y;
+          Jz = jv.z;
+        } else {
+          Fx += jv.x;
+          Fy += jv.y;
+          Fz += jv.z;
+        }
+        a.J[gsite] = Vec4<T>{T(0), T(0), T(0), T(0)};
+        if (Rec) a.jrec[gsite] = jv;
+      }
+      if (Rec && (gsite & 63) == 0) a.mrec[gsite >> 6] = word;
+      uint32_t hw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (q.k.noise) {
+        const Words4 o0 = philox10(Words4{(uint32_t)local, step_lo, q.tag0, step_hi}, q.key0, q.key1);
+        const Words4 o1 = philox10(Words4{(uint32_t)local, step_lo, q.tag1, step_hi}, q.key0, q.key1);
+        hw[0] = o0.w0; hw[1] = o0.w1; hw[2] = o0.w2; hw[3] = o0.w3;
+        hw[4] = o1.w0; hw[5] = o1.w1; hw[6] = o1.w2; hw[7] = o1.w3;
+      }
+      collide_deviation<T, VarC>(d, Fx, Fy, Fz, hw, q.k, Jx, Jy, Jz);
+      // every population is written once per step: stream the stores past the
+      // caches (non-temporal hint)
+      T* __restrict__ o = dst + 19 * (size_t)q.site_off;
+      if (rows) {
+        const uint32_t own = ((uint32_t)z * 19u) * (uint32_t)q.g.A + (uint32_t)(y * q.g.nx + x);
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+          __builtin_nontemporal_store(d[i], o + (size_t)i * q.g.A + own);
+      } else {
+        const size_t own = pop_offset(q.g, 0, x, y, z);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], o + own + (size_t)i * q.g.A);
+      }
+      if ((gsite & 63) == 0 && word) {
+        a.mark[gsite >> 6] = 0ull;
+        a.shared_site[gsite >> 6] = 0ull;  // shared bits are a subset of the mark bits
+      }
     }
   }
 }
-
-// Stride between the 19 population arrays.  With the arrays a power of two
-// apart (a 256^3 FP32 lattice is 64 MiB per array) the collide-stream
-// kernel measured 3% (256^3) to 16% (128^3) slower than with the stride
-// padded by 65536 + 1024 sites; pads were compared by measurement, the
-// memory-side address hashing being undocumented.
-int64_t pop_stride(int64_t Stot) { return Stot + kPopPad; }
 
 template <typename T>
 static StreamArgs<T> stream_args(Context* c) {
@@ -143,26 +238,37 @@ static StreamArgs<T> stream_args(Context* c) {
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
   a.clock = (const Clock*)at(c, c->plan.lay.clock);
-  a.P = (size_t)c->plan.P;
   a.R = c->plan.R;
   a.nitems = c->plan.nitems;
   a.varc = c->p[0].variant == 3 ? 1 : 0;
   return a;
 }
 
+template <typename T, int Mode>
+static void collide_stream_mode(Context* c, const StreamArgs<T>& a, int blocks) {
+  if (c->p[0].variant == 3)  // no adjoint for variant 3: never recording
+    hipLaunchKernelGGL((k_collide_stream<T, false, true, Mode>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
+  else if (a.jrec)
+    hipLaunchKernelGGL((k_collide_stream<T, true, false, Mode>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
+  else
+    hipLaunchKernelGGL((k_collide_stream<T, false, false, Mode>), dim3(blocks), dim3(kBlock), 0,
+                       c->stream, a);
+}
+
 template <typename T>
 static hipError_t collide_stream_t(Context* c) {
   StreamArgs<T> a = stream_args<T>(c);
   const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
-  if (c->p[0].variant == 3)  // no adjoint for variant 3: never recording
-    hipLaunchKernelGGL((k_collide_stream<T, false, true>), dim3(blocks), dim3(kBlock), 0,
-                       c->stream, a);
-  else if (a.jrec)
-    hipLaunchKernelGGL((k_collide_stream<T, true, false>), dim3(blocks), dim3(kBlock), 0,
-                       c->stream, a);
+  // the row path's kernel is instantiated on its own when no replica needs
+  // the general one (fewer registers, more waves in flight)
+  if (c->plan.row_replicas == c->plan.R)
+    collide_stream_mode<T, 1>(c, a, blocks);
+  else if (c->plan.row_replicas == 0)
+    collide_stream_mode<T, 0>(c, a, blocks);
   else
-    hipLaunchKernelGGL((k_collide_stream<T, false, false>), dim3(blocks), dim3(kBlock), 0,
-                       c->stream, a);
+    collide_stream_mode<T, 2>(c, a, blocks);
   return hipGetLastError();
 }
 
@@ -222,12 +328,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_r
 #pragma unroll
     for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
     if (local < q.g.S) {
-      int x, y, z, sidx[19];
+      int x, y, z;
+      size_t off[19];
       site_coords(q.g, local, x, y, z);
-      pull_sources(q.g, x, y, z, sidx);
+      pull_offsets(q.g, x, y, z, off);
+      const T* __restrict__ sbase = src + 19 * (size_t)q.site_off;
       T d[19];
 #pragma unroll
-      for (int i = 0; i < 19; ++i) d[i] = src[(size_t)i * a.P + q.site_off + sidx[i]];
+      for (int i = 0; i < 19; ++i) d[i] = sbase[off[i]];
       T drho, jx, jy, jz;
       moments_deviation<T>(d, drho, jx, jy, jz);
       const T rho = q.k.rho0 + drho;
@@ -319,25 +427,27 @@ hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d
 // sites), so that it shows the populations as the paper's variant C holds
 // them after each MD step.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy_pop(T* __restrict__ pop, size_t P, int site_off,
+__global__ __launch_bounds__(kBlock) void k_copy_pop(T* __restrict__ pop, int site_off,
                                                      Geom g, T* __restrict__ plain, int to_plain,
                                                      const Vec4<T>* __restrict__ pend,
                                                      const unsigned long long* __restrict__ mark,
                                                      const RepLB<T>* __restrict__ rep, int rr) {
   const int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= g.S) return;
-  int x, y, z, sidx[19];
+  int x, y, z;
+  size_t off[19];
   site_coords(g, r, x, y, z);
-  pull_sources(g, x, y, z, sidx);
+  pull_offsets(g, x, y, z, off);
   const size_t S = (size_t)g.S;
+  T* __restrict__ base = pop + 19 * (size_t)site_off;
   if (!to_plain) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) pop[(size_t)i * P + site_off + sidx[i]] = plain[(size_t)i * S + r];
+    for (int i = 0; i < 19; ++i) base[off[i]] = plain[(size_t)i * S + r];
     return;
   }
   T d[19];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = pop[(size_t)i * P + site_off + sidx[i]];
+  for (int i = 0; i < 19; ++i) d[i] = base[off[i]];
   const int gs = site_off + r;
   if (pend && ((mark[gs >> 6] >> (gs & 63)) & 1ull)) {
     const Vec4<T> jv = pend[gs];
@@ -372,6 +482,7 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
   g.ny = p.ny;
   g.nz = p.nz;
   g.S = p.nx * p.ny * p.nz;
+  g.A = p.nx * p.ny;
   g.inv_nx = 1.0 / p.nx;
   g.inv_ny = 1.0 / p.ny;
   const int blocks = (g.S + kBlock - 1) / kBlock;
@@ -384,7 +495,7 @@ static hipError_t copy_t(Context* c, int rep, void* plain, int what) {
   T* pop = (T*)c->popv[c->cur];
   const bool pend = c->p[0].variant == 3;
   hipLaunchKernelGGL(k_copy_pop<T>, dim3(blocks), dim3(kBlock), 0, c->stream, pop,
-                     (size_t)c->plan.P, site_off, g, (T*)plain, what == 0 ? 1 : 0,
+                     site_off, g, (T*)plain, what == 0 ? 1 : 0,
                      pend ? (const Vec4<T>*)at(c, c->plan.lay.transfer) : nullptr,
                      (const unsigned long long*)at(c, c->plan.lay.mark),
                      (const RepLB<T>*)at(c, c->plan.lay.rep_lb), rep);

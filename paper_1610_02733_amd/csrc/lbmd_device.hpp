@@ -457,13 +457,26 @@ __host__ __device__ __forceinline__ void moments_deviation(const T d[19], T& drh
 }
 
 // ---------------------------------------------------------------------------
-// Lattice geometry.  Site index r = x + nx*(y + ny*z).  Populations live in
-// "pull" storage: buffer[i][s] holds the post-collision value produced at
-// site s, so the post-stream value at r is buffer[i][r - c_i].
+// Lattice geometry and population storage.  Site index r = x + nx*(y + ny*z).
+//
+// Populations are stored per replica in z-planes: for each z the 19
+// population planes of nx*ny values follow one another, x fastest, so
+// population i of site (x, y, z) sits at offset ((z*19 + i)*ny + y)*nx + x
+// from the replica's base (19 * its first global site).  A wavefront that
+// streams a row of one population touches one contiguous run, and the 19
+// planes of a z-slab lie within 19*nx*ny values: on MI355X this plane
+// interleave streamed faster than 19 separate arrays (measured: 78% against
+// 73-74% of the HBM peak for the bare collide-stream access pattern at
+// 256^3).
+//
+// "Pull" storage: the entry of population i at site s holds the
+// post-collision value produced at s, so the post-stream value at r is the
+// entry of population i at r - c_i.
 // ---------------------------------------------------------------------------
 struct Geom {
   int nx, ny, nz;
   int S;          // nx*ny*nz
+  int A;          // nx*ny, one population plane
   double inv_nx;  // 1/nx, 1/ny for the division helpers
   double inv_ny;
 };
@@ -488,36 +501,41 @@ __host__ __device__ __forceinline__ void site_coords(const Geom& g, int r, int& 
   z = div_fast(row, g.ny, g.inv_ny, y);
 }
 
-// Pull sources of the 19 populations at site (x, y, z): src[i] = r - c_i.
-__host__ __device__ __forceinline__ void pull_sources(const Geom& g, int x, int y, int z,
-                                                      int src[19]) {
+// Offset of population i of site (x, y, z) from the replica's base.
+__host__ __device__ __forceinline__ size_t pop_offset(const Geom& g, int i, int x, int y, int z) {
+  return ((size_t)z * 19 + (size_t)i) * (size_t)g.A + (size_t)(y * g.nx + x);
+}
+
+// Offsets of the pull sources of the 19 populations at site (x, y, z): the
+// entry of population i at r - c_i (periodic).
+__host__ __device__ __forceinline__ void pull_offsets(const Geom& g, int x, int y, int z,
+                                                      size_t off[19]) {
   const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-  const int r00 = g.nx * (y + g.ny * z);
-  const int rm0 = g.nx * (ym + g.ny * z), rp0 = g.nx * (yp + g.ny * z);
-  const int r0m = g.nx * (y + g.ny * zm), r0p = g.nx * (y + g.ny * zp);
-  const int rmm = g.nx * (ym + g.ny * zm), rpp = g.nx * (yp + g.ny * zp);
-  const int rmp = g.nx * (ym + g.ny * zp), rpm = g.nx * (yp + g.ny * zm);
-  src[0] = x + r00;
-  src[1] = xm + r00;   // +x came from x-1
-  src[2] = xp + r00;   // -x
-  src[3] = x + rm0;    // +y
-  src[4] = x + rp0;    // -y
-  src[5] = x + r0m;    // +z
-  src[6] = x + r0p;    // -z
-  src[7] = xm + rm0;   // (1,1,0)
-  src[8] = xp + rp0;   // (-1,-1,0)
-  src[9] = xm + rp0;   // (1,-1,0)
-  src[10] = xp + rm0;  // (-1,1,0)
-  src[11] = xm + r0m;  // (1,0,1)
-  src[12] = xp + r0p;  // (-1,0,-1)
-  src[13] = xm + r0p;  // (1,0,-1)
-  src[14] = xp + r0m;  // (-1,0,1)
-  src[15] = x + rmm;   // (0,1,1)
-  src[16] = x + rpp;   // (0,-1,-1)
-  src[17] = x + rmp;   // (0,1,-1)
-  src[18] = x + rpm;   // (0,-1,1)
+  const size_t A = (size_t)g.A;
+  // plane bases z*19*A (population 0) and row starts y*nx
+  const size_t b0 = (size_t)z * 19 * A, bm = (size_t)zm * 19 * A, bp = (size_t)zp * 19 * A;
+  const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
+  off[0] = b0 + (size_t)(r0 + x);
+  off[1] = b0 + A + (size_t)(r0 + xm);          // +x came from x-1
+  off[2] = b0 + 2 * A + (size_t)(r0 + xp);      // -x
+  off[3] = b0 + 3 * A + (size_t)(rm + x);       // +y
+  off[4] = b0 + 4 * A + (size_t)(rp + x);       // -y
+  off[5] = bm + 5 * A + (size_t)(r0 + x);       // +z
+  off[6] = bp + 6 * A + (size_t)(r0 + x);       // -z
+  off[7] = b0 + 7 * A + (size_t)(rm + xm);      // (1,1,0)
+  off[8] = b0 + 8 * A + (size_t)(rp + xp);      // (-1,-1,0)
+  off[9] = b0 + 9 * A + (size_t)(rp + xm);      // (1,-1,0)
+  off[10] = b0 + 10 * A + (size_t)(rm + xp);    // (-1,1,0)
+  off[11] = bm + 11 * A + (size_t)(r0 + xm);    // (1,0,1)
+  off[12] = bp + 12 * A + (size_t)(r0 + xp);    // (-1,0,-1)
+  off[13] = bp + 13 * A + (size_t)(r0 + xm);    // (1,0,-1)
+  off[14] = bm + 14 * A + (size_t)(r0 + xp);    // (-1,0,1)
+  off[15] = bm + 15 * A + (size_t)(rm + x);     // (0,1,1)
+  off[16] = bp + 16 * A + (size_t)(rp + x);     // (0,-1,-1)
+  off[17] = bp + 17 * A + (size_t)(rm + x);     // (0,1,-1)
+  off[18] = bm + 18 * A + (size_t)(rp + x);     // (0,-1,1)
 }
 
 }  // namespace lbmd_dev

@@ -23,7 +23,6 @@ using lbmd_dev::Geom;
 
 constexpr int kBlock = 256;  // threads per block; site chunks of the LB kernels
 constexpr int kRedWidth = 16;
-constexpr int64_t kPopPad = 66560;  // population stride pad, in sites (pop_stride)
 
 // Per-replica constants of the LB kernels (run precision T).
 template <typename T>
@@ -31,6 +30,8 @@ struct RepLB {
   Geom g;
   int site_off;  // first global site of the replica
   int item_off;  // first 256-site work item of the replica
+  int rows;      // nx is 64, 128 or 256 and 19 S < 2^32: the collide-stream
+                 // kernel's row path
   uint32_t key0, key1, tag0, tag1;
   CollideConsts<T> k;
 };
@@ -63,7 +64,8 @@ struct Clock {
 
 // Offsets (bytes) of the regions carved out of the caller's workspace.
 struct Layout {
-  size_t pop[2];     // [19][P] population deviations, pull storage (P >= Stot)
+  size_t pop[2];     // [19 * Stot] population deviations, pull storage, per replica
+                     // z-plane interleaved (pop_offset in lbmd_device.hpp)
   size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z, unused)
   size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
   size_t rep_lb;     // [R] RepLB<T>
@@ -111,11 +113,12 @@ struct Plan {
   int prec;
   int n_sub;
   int64_t Stot;  // padded total sites
-  int64_t P;     // population stride: Stot plus a pad (see pop_stride)
+  int64_t P;     // sites per population buffer (= Stot; a buffer holds 19 * P values)
   int64_t Ntot;  // particles
   int64_t Ctot;  // force cells
   int nitems;    // 256-site work items of the LB kernels
   int64_t nseg;  // segments (block-sized stretches) of the widest coupling launch
+  int row_replicas;  // replicas on the collide-stream row path (see row_path)
   bool any_forces2;
   std::vector<int64_t> site_off, part_off, cell_off, item_off;
   Layout lay;
@@ -129,11 +132,11 @@ struct Plan {
 // velocities it interpolated.  The reverse sweep then walks the recorded
 // cycles backwards.
 struct AdjLayout {
-  size_t slots;    // [K-1][19][P] T: populations read by cycles 1..K-1
+  size_t slots;    // [K-1][19 * P] T: populations read by cycles 1..K-1
   size_t jrec;     // [K][Stot] Vec4<T>: transfer field at the LB step (valid at marked sites)
   size_t mrec;     // [K][Stot/64] uint64: mark words at the LB step
   size_t prec;     // [K][n_sub][kAdjRec][Ntot] double: particle records
-  size_t pbar[2];  // [19][P] T: adjoint of the stored (post-collision) populations
+  size_t pbar[2];  // [19 * P] T: adjoint of the stored (post-collision) populations
   size_t jbar;     // [Stot] Vec4<T>: adjoint of the transfer field
   size_t abar;     // [Stot] Vec4<T>: adjoint of (j, rho) read by the MD steps
   size_t xbar, vbar, ubar;  // [3][Ntot] double
@@ -187,8 +190,24 @@ struct Context {
 
 inline void* at(const Context* c, size_t off) { return c->ws + off; }
 
+// Copy of a per-replica table entry that the whole block reads, through the
+// constant address space so that it is fetched with scalar loads into
+// scalar registers (a plain load of it through a pointer the kernel could
+// also write to is fetched per lane and occupies vector registers).  The
+// tables are written only by the host between launches.
+template <typename U>
+__device__ __forceinline__ U scalar_copy(const U* p) {
+  static_assert(sizeof(U) % 4 == 0, "table entries are whole 32-bit words");
+  typedef __attribute__((address_space(4))) const int* ConstWords;
+  const ConstWords src = (ConstWords)p;
+  U out;
+  int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(U) / 4); ++w) dst[w] = src[w];
+  return out;
+}
+
 // Launchers (return hipError_t of the launch).
-int64_t pop_stride(int64_t Stot);
 hipError_t launch_collide_stream(Context* c);
 hipError_t launch_collide_stream_adjoint(Context* c);
 hipError_t launch_couple_adjoint(Context* c);
@@ -210,6 +229,12 @@ hipError_t invalidate_corner_cache(Context* c);
 hipError_t launch_forces(Context* c);
 hipError_t launch_forces_and_kick(Context* c);
 int64_t force_cells(const lbmd_params* p);
+// nx is 64, 128 or 256 and the replica's 19 S population entries have 32-bit
+// offsets: the collide-stream kernel's row path (aligned rows, DPP x shift)
+inline bool row_path(const lbmd_params& p) {
+  return (p.nx == 64 || p.nx == 128 || p.nx == 256) &&
+         19.0 * (double)p.nx * p.ny * p.nz < 4294967296.0;
+}
 int cells_per_axis(const lbmd_params* p, int d);
 
 }  // namespace lbmd_impl

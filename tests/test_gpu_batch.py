@@ -253,3 +253,38 @@ def test_batch_sort_keeps_replica_ranges(lb, orc):
         assert rel_pop(B.populations(r).cpu().numpy() + w[:, None], o.populations(), w, 1.0) < 1e-12
         if kw["n_particles"] > 0:
             assert np.abs(B.particles(r)[1].cpu().numpy() - o.particles()[1][:, refs[r]]).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_batch_mixing_row_and_general_lattices(lb, orc, prec):
+    """A batch whose replicas take different collide-stream paths (x rows of
+    64 and 128 sites on the row path, 10 and 12 on the general one): every
+    replica equals its own oracle run, populations and particles."""
+    c, w, e, b = orc.tables()
+    shapes = [(64, 3, 2), (10, 8, 6), (128, 2, 3), (12, 5, 4)]
+    reps, xs, vs, orcs = [], [], [], []
+    for r, shape in enumerate(shapes):
+        n = 6 + 5 * r
+        kw = dict(n_sub=3, variant=2, kT=1e-3, seed=41, replica=r, n_particles=n,
+                  friction=1.0 + 0.5 * r, nu=0.2 + 0.05 * r)
+        x, v = wl.free_particles(shape, n, 1e-3, 1.0, 50 + r)
+        reps.append((shape, dict(precision=prec, **kw)))
+        xs.append(x)
+        vs.append(v)
+        o = orc.Oracle(*shape, **kw)
+        o.set_particles(x, v)
+        o.cycle(6)
+        orcs.append(o)
+    B = lb.Batch(reps)
+    B.bind_particles(xs, vs)
+    B.cycle(3)
+    B.run_cycles(3)
+    tol = 1e-12 if prec == 64 else 1e-5
+    for r, o in enumerate(orcs):
+        err = rel_pop(B.populations(r).cpu().numpy() + w[:, None], o.populations(), w, 1.0)
+        assert err < tol, (r, err)
+        xg, vg, ig = (t.cpu().numpy() for t in B.particles(r))
+        xo, vo, io = o.particles()
+        L = np.asarray(shapes[r], float)[:, None]
+        assert np.abs((xg + L * ig) - (xo + L * io)).max() < tol * max(shapes[r])
+        assert np.abs(vg - vo).max() < tol * max(np.abs(vo).max(), np.sqrt(1e-3))

@@ -82,10 +82,13 @@ def test_fluid_only_c1_shape(lb, orc, prec):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("shape", [(13, 7, 5), (64, 3, 2), (2, 2, 2)])
+@pytest.mark.parametrize("shape", [(13, 7, 5), (64, 3, 2), (2, 2, 2), (128, 3, 3), (256, 3, 2)])
 def test_random_state_rates_force(lb, orc, prec, shape):
     """Ragged lattices (site counts not a multiple of the 64-wide wavefront),
-    distinct shear / bulk / kinetic rates, body force, noise."""
+    distinct shear / bulk / kinetic rates, body force, noise.  x rows of 64,
+    128 and 256 sites take the collide-stream kernel's row path (one, two
+    and four wavefronts per row; 64 x 3 x 2 and 128 x 3 x 3 end in a partial
+    256-site item)."""
     c, w, e, b = orc.tables()
     dt = np.float32 if prec == 32 else np.float64
     d0 = wl.perturbed_deviations(shape, w, 1.3, 0.05, seed=7, dtype=dt)
