@@ -126,7 +126,6 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.slist_delta = o; o = up(o + nent * 4 * t);
   L.mlist = o; o = up(o + nent * 4);
   L.seg_count = o; o = up(o + 2 * (size_t)pl.nseg * 4);
-  L.shared_site = o; o = up(o + (S / 64) * 8);
   L.bin_count = o; o = up(o + C * 4);
   L.bin_start = o; o = up(o + (C + 1) * 4);
   L.bin_tiles = o; o = up(o + ((C + 1023) / 1024 + 1) * 4);
@@ -662,8 +661,6 @@ int load_common(lbmd* c, const char* src, const StateLayout& sl) {
   const size_t t = c->plan.prec == 32 ? 4 : 8;
   rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.transfer), 0, S * 4 * t, c->stream));
   if (!rc) rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.mark), 0, (S / 64) * 8, c->stream));
-  if (!rc)
-    rc = fail(c, hipMemsetAsync(at(c, c->plan.lay.shared_site), 0, (S / 64) * 8, c->stream));
   if (rc) return rc;
   c->t_lb = cnt[0];
   c->t_md = cnt[1];

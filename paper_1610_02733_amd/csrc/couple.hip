@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         // fluid velocity at the particle (Eq. 5)
         double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
         jv_[jj] = a.J[gs];
-        sh_[jj] = (a.shared_site[gs >> 6] >> (gs & 63)) & 1ull;
+        sh_[jj] = jv_[jj].w != T(0);  // shared-site flag (claim_site)
         if (a.variant >= 2) {  // the fluid velocity includes the pending transfer
           jx += (double)jv_[jj].x;
           jy += (double)jv_[jj].y;
@@ -347,11 +347,20 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
 
 // After an MD step without a force kernel: the after-step work
 // (after_step_item) as a launch of its own.
-template <typename T, int ST>
+// With Reduce, the shared-site transfers of each segment are summed per site
+// in LDS first (reduce_segment_transfers; dynamic shared memory of
+// kSiteTable * (4 + 3 sizeof(T)) bytes).
+template <typename T, int ST, bool Reduce>
 __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
                                                       int L) {
+  extern __shared__ int site_table_mem[];
+  SiteTable<T> tab{nullptr, nullptr};
+  if (Reduce) {
+    tab.key = site_table_mem;
+    tab.val = reinterpret_cast<T*>(site_table_mem + kSiteTable);
+  }
   for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x)
-    after_step_item<T, ST>(a, it, nseg, per, L);
+    after_step_item<T, ST>(a, it, nseg, per, L, tab);
 }
 
 static int grid_for(int64_t work_blocks, int tuned) {
@@ -402,8 +411,14 @@ static hipError_t couple_st(Context* c, int substep) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (c->plan.any_forces2 && !a.rec) return hipSuccess;
   const int64_t nseg = (N * L + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_after_step<T, ST>), dim3(grid_for(2 * nseg, c->tune.part_blocks)),
-                     dim3(kBlock), 0, c->stream, a, nseg, (St::kSites + L - 1) / L, L);
+  const dim3 agrid(grid_for(2 * nseg, c->tune.part_blocks));
+  const int per = (St::kSites + L - 1) / L;
+  if (ST == 1)  // 27-site stencils overlap densely: pre-reduce per segment
+    hipLaunchKernelGGL((k_after_step<T, ST, true>), agrid, dim3(kBlock),
+                       kSiteTable * (4 + 3 * sizeof(T)), c->stream, a, nseg, per, L);
+  else
+    hipLaunchKernelGGL((k_after_step<T, ST, false>), agrid, dim3(kBlock), 0, c->stream, a, nseg,
+                       per, L);
   return hipGetLastError();
 }
 

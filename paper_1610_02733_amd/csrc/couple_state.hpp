@@ -23,7 +23,6 @@ struct CoupleArgs {
   unsigned long long* __restrict__ mark;
   double* __restrict__ fc_held;  // coupling force of the step (split kick)
   T* __restrict__ cc;
-  unsigned long long* __restrict__ shared_site;  // sites claimed more than once this interval
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
@@ -55,12 +54,18 @@ __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t 
 }
 
 // Mark a site as a receiver of momentum transfer in this LB interval; a site
-// claimed again (by another particle, or by one that changed cubes) is
-// flagged as shared.
+// claimed again (by another particle, or by one that changed stencils) is
+// flagged as shared in the w word of its transfer entry, which the coupling
+// kernel reads together with the transfer itself.  The flag is written only
+// by claims (refill, after-step work: never while a coupling kernel runs) and
+// cleared with the entry by the LB step; the after-step atomics touch only
+// the x, y, z words.  (Recording the claiming particle instead, so that a
+// particle re-claiming its own sites keeps them unshared, measured slower:
+// the refill's extra compare-and-swap per site cost more than it saved.)
 template <typename T>
 __device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
   const unsigned long long bit = 1ull << (gs & 63);
-  if (atomicOr(a.mark + (gs >> 6), bit) & bit) atomicOr(a.shared_site + (gs >> 6), bit);
+  if (atomicOr(a.mark + (gs >> 6), bit) & bit) reinterpret_cast<T*>(a.J + gs)[3] = T(1);
 }
 
 // (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
@@ -103,9 +108,62 @@ struct DirectShape {
   static constexpr int kPer = (Stencil<ST>::kSites + kLanes - 1) / kLanes;
 };
 
+// Pre-reduction of a segment's shared-site transfers in LDS (the launch of
+// k_after_step provides the table; the force kernel's extra blocks pass
+// none): the entries are summed per distinct site in an open-addressing
+// hash table (LDS atomics), then each distinct site receives one device
+// atomic per component instead of one per entry.  Pays where stencils
+// overlap densely (the 27 sites of the three-point kernel).
+constexpr int kSiteTable = 2048;  // >= 2 x the entries of a segment (kBlock * 4)
+
+template <typename T>
+struct SiteTable {
+  int* key;  // [kSiteTable] global site, -1 = empty
+  T* val;    // [3][kSiteTable]
+};
+
+template <typename T>
+__device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a, int64_t base,
+                                                         int n, SiteTable<T> tab) {
+  // table size: the smallest power of two >= 2 n (block-uniform)
+  int H = 64, lg = 6;
+  while (H < 2 * n) {
+    H <<= 1;
+    ++lg;
+  }
+  for (int h = threadIdx.x; h < H; h += kBlock) {
+    tab.key[h] = -1;
+    tab.val[h] = tab.val[kSiteTable + h] = tab.val[2 * kSiteTable + h] = T(0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += kBlock) {
+    const int site = a.lsite[base + e];
+    const Vec4<T> dv = a.ldelta[base + e];
+    int h = (int)(((uint32_t)site * 2654435761u) >> (32 - lg));
+    for (;;) {  // linear probing; the table is at most half full
+      const int old = atomicCAS(tab.key + h, -1, site);
+      if (old == -1 || old == site) break;
+      h = (h + 1) & (H - 1);
+    }
+    atomicAdd(tab.val + h, dv.x);
+    atomicAdd(tab.val + kSiteTable + h, dv.y);
+    atomicAdd(tab.val + 2 * kSiteTable + h, dv.z);
+  }
+  __syncthreads();
+  // one lane per (slot, component): the three adds to a site in neighbouring
+  // lanes of one instruction
+  for (int u = threadIdx.x; u < 3 * H; u += kBlock) {
+    const int h = u / 3, comp = u - 3 * h;
+    const int site = tab.key[h];
+    if (site >= 0) atomicAdd(reinterpret_cast<T*>(a.J + site) + comp, tab.val[comp * kSiteTable + h]);
+  }
+  __syncthreads();  // the block's next item reuses the table
+}
+
 template <typename T, int ST>
 __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t it, int64_t nseg,
-                                                int per, int L) {
+                                                int per, int L,
+                                                SiteTable<T> tab = SiteTable<T>{nullptr, nullptr}) {
   using St = Stencil<ST>;
   if (it < nseg) {
     const int64_t seg = it;
@@ -136,6 +194,10 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
     const int64_t seg = it - nseg;
     const int n = a.lseg[seg];
     const int64_t base = seg * (int64_t)(kBlock * per);
+    if (tab.key && n > 1) {
+      reduce_segment_transfers(a, base, n, tab);
+      return;
+    }
     // one lane per (entry, component): the three adds to one site sit in
     // neighbouring lanes of one instruction and reach the memory side as one
     // request instead of three
@@ -161,7 +223,6 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.mark = (unsigned long long*)at(c, L.mark);
   a.fc_held = (double*)at(c, L.fc_held);
   a.cc = (T*)at(c, L.cc);
-  a.shared_site = (unsigned long long*)at(c, L.shared_site);
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);

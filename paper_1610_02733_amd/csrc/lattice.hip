@@ -34,7 +34,8 @@ __device__ __forceinline__ int replica_of_item(const int32_t* __restrict__ item_
 // density of this LB step, collides and writes its 19 results at r in the
 // other buffer (coalesced).  J is only read where the site's bit in `mark` is
 // set (the coupling sets it when it transfers momentum there), and is cleared
-// with it, so the untouched bulk of the lattice costs no transfer traffic.
+// with it (the shared-site flag in w too), so the untouched bulk of
+// the lattice costs no transfer traffic.
 // In variant 3 (VarC) the interval's transfer already belongs to the state:
 // the collision adds it as the momentum and stress increments of the paper's
 // variant C and relaxes with the body force alone.  A work item is 256
@@ -58,7 +59,6 @@ struct StreamArgs {
   T* pop[2];
   Vec4<T>* __restrict__ J;
   unsigned long long* __restrict__ mark;
-  unsigned long long* __restrict__ shared_site;
   const RepLB<T>* __restrict__ rep;
   const int32_t* __restrict__ item_off;
   const Clock* __restrict__ clock;
@@ -217,10 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(d[i], o + own + (size_t)i * q.g.A);
       }
-      if ((gsite & 63) == 0 && word) {
-        a.mark[gsite >> 6] = 0ull;
-        a.shared_site[gsite >> 6] = 0ull;  // shared bits are a subset of the mark bits
-      }
+      if ((gsite & 63) == 0 && word) a.mark[gsite >> 6] = 0ull;
     }
   }
 }
@@ -234,7 +231,6 @@ static StreamArgs<T> stream_args(Context* c) {
   a.jrec = (Vec4<T>*)c->rec_J;
   a.mrec = c->rec_mark;
   a.mark = (unsigned long long*)at(c, c->plan.lay.mark);
-  a.shared_site = (unsigned long long*)at(c, c->plan.lay.shared_site);
   a.rep = (const RepLB<T>*)at(c, c->plan.lay.rep_lb);
   a.item_off = (const int32_t*)at(c, c->plan.lay.item_rep);
   a.clock = (const Clock*)at(c, c->plan.lay.clock);

@@ -66,7 +66,9 @@ struct Clock {
 struct Layout {
   size_t pop[2];     // [19 * Stot] population deviations, pull storage, per replica
                      // z-plane interleaved (pop_offset in lbmd_device.hpp)
-  size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z, unused)
+  size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z) and, in w,
+                     // a flag set when the site is claimed more than once in the
+                     // current LB interval (shared site; claim_site)
   size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
   size_t rep_lb;     // [R] RepLB<T>
   size_t rep_md;     // [R] RepMD
@@ -85,7 +87,6 @@ struct Layout {
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
   size_t mlist;      // [segments * kBlock / lanes] int2: particles whose stencil moved, new base
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
-  size_t shared_site; // [Stot/64] uint64: site claimed more than once in this LB interval
   size_t bin_count;  // [Ctot] int32: particles per force cell
   size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
   size_t bin_tiles;  // [ceil(Ctot / 1024) + 1] int32: scan tile totals
