@@ -12,7 +12,7 @@ Prints one JSON line.  value = lattice-site updates per second of the whole
 coupled cycle (MLUPS).  roofline: the fused collide-stream kernel, 152
 algorithmic bytes per FP32 site update (19 populations read, 19 written),
 timed with HIP events around each launch inside the timed region.
-cpu_baseline: the FP64 CPU oracle on a bounded slab of the same workload.
+cpu_baseline: the FP64 CPU oracle (OpenMP) on the same workload, 20 cycles.
 """
 from __future__ import annotations
 
@@ -328,28 +328,37 @@ def adjoint_measure(lbmd, torch, reps=3):
                             "f_ext": [float(t) for t in grads["f_ext"]]})
 
 
-def cpu_baseline(cfg, x_density_seed=3, nz=32, cycles=4):
-    """FP64 oracle, single thread, on a 256 x 256 x nz slab of the workload
-    (same per-site work, same particle density and parameters)."""
+def cpu_baseline(cfg, x, v, cycles=20, warmup=1):
+    """FP64 CPU oracle on the full workload (same lattice, particles, seed and
+    parameters, variant 2): `warmup` untimed cycles (first touch of its ~6 GB),
+    then `cycles` coupled cycles (one LB step each) timed, on the OpenMP
+    threads of the host process (OMP_NUM_THREADS, else every core in its
+    affinity set)."""
     import oracle
-    from paper_1610_02733_amd import workloads as wl
-    shape = (cfg["shape"][0], cfg["shape"][1], nz)
+    oracle.build(force=False)
+    shape = cfg["shape"]
     S = int(np.prod(shape))
-    N = int(round(cfg["n_particles"] * S / np.prod(cfg["shape"])))
-    x, v = wl.free_particles(shape, N, cfg["kT"], cfg["particle_mass"], x_density_seed)
+    N = cfg["n_particles"]
+    if cfg.get("force_model", 0) >= 2:
+        # the oracle's conservative forces are a serial all-pairs sum
+        cycles = min(cycles, 2)
     o = oracle.Oracle(*shape, n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"],
                       rho0=cfg["rho0"], friction=cfg["friction"], n_particles=N,
-                      seed=cfg["seed"], particle_mass=cfg["particle_mass"])
+                      seed=cfg["seed"], particle_mass=cfg["particle_mass"],
+                      **{k: cfg[k] for k in FORCE_KEYS if k in cfg})
     o.set_particles(x, v)
+    o.cycle(warmup)
     t0 = time.perf_counter()
     o.cycle(cycles)
     dt = time.perf_counter() - t0
     o.close()
-    return dict(value=S * cycles / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                substeps_per_s=cycles * cfg["n_sub"] / dt,
-                sample=f"{shape[0]}x{shape[1]}x{shape[2]} slab, {N} particles (same density), "
-                       f"{cycles} coupled cycles of n={cfg['n_sub']}, variant 2, FP64, "
-                       f"1 thread, {dt:.1f} s")
+    threads = oracle.max_threads()
+    return dict(value=round(S * cycles / dt / 1e6, 3), unit="MLUPS", cores=threads, kind="oracle",
+                substeps_per_s=round(cycles * cfg["n_sub"] / dt, 3),
+                affinity_cpus=len(os.sched_getaffinity(0)),
+                sample=f"full workload: {shape[0]}x{shape[1]}x{shape[2]} lattice, {N} particles, "
+                       f"{cycles} coupled cycles (LB steps) of n={cfg['n_sub']} after {warmup} "
+                       f"untimed, variant 2, FP64, {threads} OpenMP threads, {dt:.1f} s")
 
 
 def main():
@@ -362,6 +371,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=20,
+                    help="coupled cycles (LB steps) of the FP64 oracle timed on the host")
     ap.add_argument("--no-error-statement", action="store_true",
                     help="skip the FP32-vs-FP64 comparison on the workload")
     ap.add_argument("--variants", default="1,2,3",
@@ -480,8 +491,8 @@ def main():
         log("error statement: FP32 vs FP64 run of the workload")
         out["error_statement"] = error_statement(lbmd, torch, cfg, x, v)
     if not args.no_cpu_baseline:
-        log("cpu baseline: FP64 oracle on a slab of the workload")
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        log(f"cpu baseline: FP64 oracle on the full workload, {args.cpu_cycles} cycles")
+        out["cpu_baseline"] = cpu_baseline(cfg, x, v, cycles=args.cpu_cycles)
     print(json.dumps(out), flush=True)
 
 

@@ -6,8 +6,9 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 code with the HIP implementation in ``paper_1610_02733_amd``; both are fed the
 same seeded inputs by the tests.
 
-The arithmetic lives in ``lbmd_oracle.c`` (plain C, FP64, single thread);
-this module only marshals numpy arrays through ctypes.
+The arithmetic lives in ``lbmd_oracle.c`` (plain C, FP64; its site and
+particle loops run on OpenMP threads with results independent of the thread
+count); this module only marshals numpy arrays through ctypes.
 """
 from __future__ import annotations
 
@@ -26,11 +27,12 @@ NTOTALS = 15
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction,
+    OpenMP for the parallel loops)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+            ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
              "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -88,6 +90,8 @@ def lib():
         L.orc_cube_weights.argtypes = [P, dp, lp, dp]
         L.orc_stencil3_weights.argtypes = [P, dp, lp, dp]
         L.orc_moments.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_max_threads.restype = C.c_int32
         for name in ("orc_create", "orc_set_particles", "orc_get_particles",
                      "orc_set_populations", "orc_get_populations", "orc_get_J",
                      "orc_set_J", "orc_lb_step", "orc_md_couple_substep",
@@ -106,6 +110,15 @@ def tables():
     b = np.zeros(19)
     lib().orc_tables(c, w, e, b)
     return c.reshape(19, 3), w, e.reshape(19, 19), b
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def philox4x32_10(counter, key):

@@ -21,11 +21,21 @@
  * Parity pins: every function below is pinned by a CPU test (conservation
  * laws, closed forms, textbook special cases, known-answer vectors,
  * statistics); none is "parity unpinned".
+ *
+ * Threads (OpenMP, for timing the CPU baseline only): the loops over sites
+ * (collision, streaming) and over particles (interpolation, friction, kicks)
+ * run in parallel; every result element is computed by the same arithmetic
+ * in the same order whatever the thread count, and the spreading onto the
+ * lattice stays serial in particle order, so results are bitwise independent
+ * of the number of threads (pinned by a test).
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -216,6 +226,7 @@ typedef struct {
                    the last LB step (Eq. 8 summed over the MD steps);
                    variants A and B only                                     */
   double *dJ;   /* [3][nsites] transfer of the current MD step (variant C)   */
+  double *post; /* [Q][nsites] scratch: post-collision populations          */
   double *x, *v, *fcons; /* [3][N]                                          */
   int32_t *img;          /* [3][N] periodic image counters                   */
   int64_t t_lb, t_md;
@@ -278,6 +289,7 @@ int orc_create(const orc_params *p, orc_ctx **out) {
   c->f = (double *)malloc(sizeof(double) * Q * c->nsites);
   c->J = (double *)calloc(3 * c->nsites, sizeof(double));
   c->dJ = (double *)calloc(3 * c->nsites, sizeof(double));
+  c->post = (double *)malloc(sizeof(double) * Q * c->nsites);
   int64_t n = p->n_particles > 0 ? p->n_particles : 1;
   c->x = (double *)calloc(3 * n, sizeof(double));
   c->v = (double *)calloc(3 * n, sizeof(double));
@@ -293,7 +305,8 @@ int orc_create(const orc_params *p, orc_ctx **out) {
 
 void orc_destroy(orc_ctx *c) {
   if (!c) return;
-  free(c->f); free(c->J); free(c->dJ); free(c->x); free(c->v); free(c->fcons); free(c->img);
+  free(c->f); free(c->J); free(c->dJ); free(c->post);
+  free(c->x); free(c->v); free(c->fcons); free(c->img);
   free(c);
 }
 
@@ -484,7 +497,8 @@ static void collide_site(const orc_ctx *c, int64_t site, int64_t step,
 int orc_lb_step(orc_ctx *c) {
   if (c->p.n_particles > 0 && c->subs_since_lb != c->p.n_sub) return ORC_ESTATE;
   int64_t S = c->nsites;
-  double *post = (double *)malloc(sizeof(double) * Q * S);
+  double *post = c->post;
+#pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < S; ++r) {
     double fin[Q], fout[Q], Jr[3];
     for (int i = 0; i < Q; ++i) fin[i] = c->f[i * S + r];
@@ -492,6 +506,7 @@ int orc_lb_step(orc_ctx *c) {
     collide_site(c, r, c->t_lb, fin, Jr, fout);
     for (int i = 0; i < Q; ++i) post[i * S + r] = fout[i];
   }
+#pragma omp parallel for schedule(static)
   for (int64_t z = 0; z < c->p.nz; ++z)
     for (int64_t y = 0; y < c->p.ny; ++y)
       for (int64_t x = 0; x < c->p.nx; ++x) {
@@ -503,7 +518,6 @@ int orc_lb_step(orc_ctx *c) {
           c->f[i * S + site_index(c, xd, yd, zd)] = post[i * S + r];
         }
       }
-  free(post);
   memset(c->J, 0, sizeof(double) * 3 * S);
   c->t_lb += 1;
   c->subs_since_lb = 0;
@@ -731,8 +745,9 @@ int orc_md_couple_substep(orc_ctx *c) {
   double *Fc = (double *)calloc(3 * (N > 0 ? N : 1), sizeof(double));
   int64_t (*sites)[27] = malloc(sizeof(int64_t[27]) * (N > 0 ? N : 1));
   double (*wts)[27] = malloc(sizeof(double[27]) * (N > 0 ? N : 1));
-  int K = 8;  /* sites per particle: 8 (trilinear) or 27 (3-point kernel) */
+  const int K = p->stencil == 1 ? 27 : 8; /* sites per particle (Eq. 5 stencil) */
   char *ok = (char *)calloc(N > 0 ? N : 1, 1);
+#pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < N; ++a) {
     double R[3], v[3];
     int finite = 1;
@@ -741,12 +756,9 @@ int orc_md_couple_substep(orc_ctx *c) {
       v[d] = c->v[d * N + a];
       if (!isfinite(R[d]) || !isfinite(v[d])) finite = 0;
     }
-    if (!finite) {
-      c->nonfinite = 1;
-      continue;
-    }
+    if (!finite) continue;
     ok[a] = 1;
-    K = stencil_weights(c, R, sites[a], wts[a]);
+    stencil_weights(c, R, sites[a], wts[a]);
     double uR[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < K; ++k) {
       double uk[3];
@@ -759,6 +771,9 @@ int orc_md_couple_substep(orc_ctx *c) {
     for (int d = 0; d < 3; ++d)
       Fc[d * N + a] = -p->friction * (v[d] - uR[d]) + amp * xi[d];
   }
+  for (int64_t a = 0; a < N; ++a)
+    if (!ok[a]) c->nonfinite = 1;
+  /* spreading: serial, in particle order */
   double *target = p->variant == 3 ? c->dJ : c->J;
   for (int64_t a = 0; a < N; ++a) {
     if (!ok[a]) continue;
@@ -783,6 +798,7 @@ int orc_md_couple_substep(orc_ctx *c) {
   }
   double L[3] = {p->nx, p->ny, p->nz};
   double h = tau / (2.0 * p->particle_mass);
+#pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < N; ++a) {
     if (!ok[a]) continue;
     for (int d = 0; d < 3; ++d) {
@@ -792,6 +808,7 @@ int orc_md_couple_substep(orc_ctx *c) {
     }
   }
   conservative_forces(c);
+#pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < N; ++a) {
     if (!ok[a]) continue;
     for (int d = 0; d < 3; ++d) c->v[d * N + a] += h * (c->fcons[d * N + a] + Fc[d * N + a]);
@@ -800,6 +817,22 @@ int orc_md_couple_substep(orc_ctx *c) {
   c->t_md += 1;
   c->subs_since_lb += 1;
   return c->nonfinite ? ORC_ENONFINITE : ORC_OK;
+}
+
+/* Threads used by the parallel loops (OpenMP; 1 without it). */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------- */

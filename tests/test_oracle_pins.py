@@ -856,3 +856,23 @@ def test_moments_fields_and_totals_closed_form(orc, variant):
     o0 = orc.Oracle(*shape, variant=variant)
     o0.set_populations(f)
     assert o0.moments()[14] == 0.0
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_threads_do_not_change_results(orc, variant):
+    """The oracle's parallel loops (sites, particles) give bitwise the same
+    populations, transfer and particles with 1 thread as with several."""
+    out = []
+    default = orc.max_threads()
+    try:
+        for nt in (1, 4):
+            orc.set_threads(nt)
+            o = make_c1_like(orc, variant, kT=2e-3, shape=(9, 7, 6), n=40, seed=13)
+            o.cycle(3)
+            for _ in range(2):
+                assert o.md_couple_substep() == 0
+            out.append((o.populations(), o.J(), *o.particles(), o.moments()))
+    finally:
+        orc.set_threads(default)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
