@@ -202,6 +202,22 @@ int lb_step(lbmd *c);
 int lb_moments(lbmd *c, void *d_rho, void *d_u, double *h_totals);
 
 /*
+ * lb_moments without workspace scratch, for callers that cannot allocate
+ * device memory or enlarge a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, results
+ * and errors as lb_moments() for a single system (a batch context: LBMD_EINVAL);
+ * the totals may differ from lb_moments() in the last bits (FP64 sums in
+ * another order).  Its reduction rows live in a fixed array of this library,
+ * one per GPU (131,200 bytes, held until the process ends, located at
+ * lb_create() on the then current device): the call allocates nothing.  The
+ * grid is capped at the array's 1024 rows, so every lattice fits
+ * (LBMD_ENOSPACE is kept for a larger need, which cannot arise).  All calls
+ * on one GPU share the array: calls that overlap on one GPU (several
+ * streams or host threads) race and must be serialised by the caller.
+ */
+int lb_moments_noalloc(lbmd *c, void *d_rho, void *d_u, double *h_totals);
+
+/*
  * Populations of the current post-stream state as deviations
  * df_i(r) = f_i(r) - w_i rho0, device [19][nsites] in the context precision,
  * site index r = x + nx*(y + ny*z), velocity order: 0, +x, -x, +y, -y, +z,

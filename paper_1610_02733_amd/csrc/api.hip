@@ -322,9 +322,13 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->rec_part = nullptr;
   c->rec_J = nullptr;
   c->rec_mark = nullptr;
+  c->scratch_rows = nullptr;
   // fluid at rest (all deviations zero), nothing transferred yet
   hipError_t e = hipMemsetAsync(c->ws, 0, pl.lay.total, c->stream);
   if (e == hipSuccess) e = upload_tables(c);
+  // set-up of lb_moments_noalloc: this GPU's address of the library's fixed
+  // reduction array (looked up once per device)
+  if (e == hipSuccess) e = moments_scratch(&c->scratch_rows);
   if (e != hipSuccess) {
     delete c;
     return LBMD_EHIP;
@@ -476,6 +480,25 @@ int lbmd_run_cycles(lbmd* c, int32_t ncycles) {
   return LBMD_OK;
 }
 
+// Totals of replica r (LBMD_TOT_* layout) from its reduction row t (columns:
+// 0 sum drho, 1-3 sum j, 4-6 sum J, 7 sum |u|^2, 8-10 sum v, 11 sum |v|^2).
+static void fill_totals(const lbmd* c, int r, const double* t, double* h) {
+  const lbmd_params& p = c->p[r];
+  const double m = p.particle_mass;
+  const double S = (double)p.nx * p.ny * p.nz;
+  h[LBMD_TOT_MASS] = p.rho0 * S + t[0];
+  for (int d = 0; d < 3; ++d) {
+    h[LBMD_TOT_PFLUID + d] = t[1 + d] + t[4 + d];
+    h[LBMD_TOT_PSEEN + d] = t[1 + d] + (p.variant >= 2 ? t[4 + d] : 0.0);
+    h[LBMD_TOT_PPART + d] = m * t[8 + d];
+  }
+  h[LBMD_TOT_KEPART] = 0.5 * m * t[11];
+  h[LBMD_TOT_U2FLUID] = t[7] / S;
+  h[LBMD_TOT_TLB] = (double)c->t_lb;
+  h[LBMD_TOT_TMD] = (double)c->t_md;
+  h[LBMD_TOT_TPART] = p.n_particles > 0 ? m * t[11] / (3.0 * p.n_particles) : 0.0;
+}
+
 static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* h_totals,
                           int all) {
   int rc = check_rep(c, rep);
@@ -494,29 +517,37 @@ static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* 
   if (!rc) rc = fail(c, hipStreamSynchronize(c->stream));
   if (rc) return rc;
   const int r0 = all ? 0 : rep, r1 = all ? R : rep + 1;
-  for (int r = r0; r < r1; ++r) {
-    const double* t = &tot[(size_t)r * kRedWidth];
-    double* h = h_totals + (size_t)(all ? r : 0) * LBMD_NTOTALS;
-    const lbmd_params& p = c->p[r];
-    const double m = p.particle_mass;
-    const double S = (double)p.nx * p.ny * p.nz;
-    h[LBMD_TOT_MASS] = p.rho0 * S + t[0];
-    for (int d = 0; d < 3; ++d) {
-      h[LBMD_TOT_PFLUID + d] = t[1 + d] + t[4 + d];
-      h[LBMD_TOT_PSEEN + d] = t[1 + d] + (p.variant >= 2 ? t[4 + d] : 0.0);
-      h[LBMD_TOT_PPART + d] = m * t[8 + d];
-    }
-    h[LBMD_TOT_KEPART] = 0.5 * m * t[11];
-    h[LBMD_TOT_U2FLUID] = t[7] / S;
-    h[LBMD_TOT_TLB] = (double)c->t_lb;
-    h[LBMD_TOT_TMD] = (double)c->t_md;
-    h[LBMD_TOT_TPART] = p.n_particles > 0 ? m * t[11] / (3.0 * p.n_particles) : 0.0;
-  }
+  for (int r = r0; r < r1; ++r)
+    fill_totals(c, r, &tot[(size_t)r * kRedWidth], h_totals + (size_t)(all ? r : 0) * LBMD_NTOTALS);
   return flags[0] ? LBMD_ENONFINITE : LBMD_OK;
 }
 
 int lb_moments(lbmd* c, void* d_rho, void* d_u, double* h_totals) {
   return moments_common(c, 0, d_rho, d_u, h_totals, 0);
+}
+
+int lb_moments_noalloc(lbmd* c, void* d_rho, void* d_u, double* h_totals) {
+  if (!c) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (c->plan.R != 1) return LBMD_EINVAL;  // single system only
+  if (!c->scratch_rows) return LBMD_ESTATE;
+  // the reduction needs min(items, kScratchRows) block rows plus the totals
+  // row; the grid is capped at the array's row count, so any lattice fits
+  const int64_t rows = std::min<int64_t>(c->plan.nitems, kScratchRows) + 1;
+  if (rows * kRedWidth > kScratchDoubles) return LBMD_ENOSPACE;
+  int rc = fail(c, launch_moments_rows(c, d_rho, d_u, c->scratch_rows));
+  if (rc || !h_totals) return rc;
+  double tot[kRedWidth];
+  int32_t flags[16];
+  rc = fail(c, hipMemcpyAsync(tot, c->scratch_rows + (size_t)kScratchRows * kRedWidth,
+                              sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+  if (!rc)
+    rc = fail(c, hipMemcpyAsync(flags, at(c, c->plan.lay.flags), sizeof(flags),
+                                hipMemcpyDeviceToHost, c->stream));
+  if (!rc) rc = fail(c, hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  fill_totals(c, 0, tot, h_totals);
+  return flags[0] ? LBMD_ENONFINITE : LBMD_OK;
 }
 
 int lbmd_batch_moments(lbmd* c, double* h_totals) {

@@ -3,6 +3,7 @@
 // reductions (Eq. 1-2) and population / transfer copies.  All kernels cover
 // every replica of a context in one launch.
 #include <algorithm>
+#include <mutex>
 
 #include "forcing.hpp"
 #include "lbmd_internal.hpp"
@@ -308,21 +309,27 @@ __device__ __forceinline__ void block_reduce_store(double acc[kRedWidth], double
   __syncthreads();
 }
 
-// Per-item partial sums.  Columns: 0 sum drho, 1-3 sum j, 4-6 sum J,
-// 7 sum |j/rho|^2.  Fields (density, velocity) of replica `field_rep`.
-template <typename T>
+// Partial sums, one row per item (PerBlock = false) or, for a single
+// replica, one row per block over all its items (PerBlock = true: a bounded
+// number of rows).  Columns: 0 sum drho, 1-3 sum j, 4-6 sum J, 7 sum
+// |j/rho|^2.  Fields (density, velocity) of replica `field_rep`.
+template <typename T, bool PerBlock>
 __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_rep,
                                                     T* __restrict__ rho_out,
                                                     T* __restrict__ u_out,
                                                     double* __restrict__ partials) {
   const T* __restrict__ src = a.pop[a.clock->cur];
+  double acc[kRedWidth];
+#pragma unroll
+  for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
   for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
     const int rr = a.R == 1 ? 0 : replica_of_item(a.item_off, a.R, item);
     const RepLB<T>& q = a.rep[rr];
     const int local = (item - q.item_off) * kBlock + threadIdx.x;
-    double acc[kRedWidth];
+    if (!PerBlock) {
 #pragma unroll
-    for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+      for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
+    }
     if (local < q.g.S) {
       int x, y, z;
       size_t off[19];
@@ -336,9 +343,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_r
       moments_deviation<T>(d, drho, jx, jy, jz);
       const T rho = q.k.rho0 + drho;
       const Vec4<T> jv = a.J[q.site_off + local];
-      acc[1] = (double)jx;
-      acc[2] = (double)jy;
-      acc[3] = (double)jz;
+      acc[1] += (double)jx;
+      acc[2] += (double)jy;
+      acc[3] += (double)jz;
       if (a.varc) {
         jx += jv.x;
         jy += jv.y;
@@ -353,28 +360,30 @@ __global__ __launch_bounds__(kBlock) void k_moments(StreamArgs<T> a, int field_r
           u_out[2 * S + local] = jz / rho;
         }
       }
-      acc[0] = (double)drho;
-      acc[4] = (double)jv.x;
-      acc[5] = (double)jv.y;
-      acc[6] = (double)jv.z;
+      acc[0] += (double)drho;
+      acc[4] += (double)jv.x;
+      acc[5] += (double)jv.y;
+      acc[6] += (double)jv.z;
       const double ux = (double)jx / (double)rho, uy = (double)jy / (double)rho,
                    uz = (double)jz / (double)rho;
-      acc[7] = ux * ux + uy * uy + uz * uz;
+      acc[7] += ux * ux + uy * uy + uz * uz;
     }
-    block_reduce_store(acc, partials + (size_t)item * kRedWidth);
+    if (!PerBlock) block_reduce_store(acc, partials + (size_t)item * kRedWidth);
   }
+  if (PerBlock) block_reduce_store(acc, partials + (size_t)blockIdx.x * kRedWidth);
 }
 
-// One block per replica: sum its items' partials, then its particles'
+// One block per replica: sum its partial rows (its items' rows, or with
+// nrows > 0, for a single replica, rows [0, nrows)), then its particles'
 // momentum and kinetic energy (columns 8-10 sum v, 11 sum |v|^2).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize(StreamArgs<T> a,
                                                      const RepMD* __restrict__ md,
                                                      const double* __restrict__ partials,
                                                      const double* __restrict__ v, int64_t Ntot,
-                                                     double* __restrict__ totals) {
+                                                     double* __restrict__ totals, int nrows) {
   const int rr = blockIdx.x;
-  const int i0 = a.item_off[rr], i1 = a.item_off[rr + 1];
+  const int i0 = nrows > 0 ? 0 : a.item_off[rr], i1 = nrows > 0 ? nrows : a.item_off[rr + 1];
   double acc[kRedWidth];
 #pragma unroll
   for (int k = 0; k < kRedWidth; ++k) acc[k] = 0.0;
@@ -399,19 +408,73 @@ static hipError_t moments_t(Context* c, int rep, void* d_rho, void* d_u, double*
   StreamArgs<T> a = stream_args<T>(c);
   double* partials = (double*)at(c, c->plan.lay.partials);
   const int blocks = c->tune.lb_blocks > 0 ? std::min(c->tune.lb_blocks, a.nitems) : a.nitems;
-  hipLaunchKernelGGL(k_moments<T>, dim3(blocks), dim3(kBlock), 0, c->stream, a, rep, (T*)d_rho,
-                     (T*)d_u, partials);
+  hipLaunchKernelGGL((k_moments<T, false>), dim3(blocks), dim3(kBlock), 0, c->stream, a, rep,
+                     (T*)d_rho, (T*)d_u, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !d_totals) return e;
   hipLaunchKernelGGL(k_finalize<T>, dim3(c->plan.R), dim3(kBlock), 0, c->stream, a,
                      (const RepMD*)at(c, c->plan.lay.rep_md), partials,
-                     (const double*)(c->bound ? c->v : nullptr), c->plan.Ntot, d_totals);
+                     (const double*)(c->bound ? c->v : nullptr), c->plan.Ntot, d_totals, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals) {
   return c->plan.prec == 32 ? moments_t<float>(c, rep, d_rho, d_u, d_totals)
                             : moments_t<double>(c, rep, d_rho, d_u, d_totals);
+}
+
+// ---------------------------------------------------------------------------
+// Moments without workspace scratch (lb_moments_noalloc): the reduction rows
+// live in a fixed device array of this library instead of the context's
+// workspace.  At most kScratchRows blocks, each summing the items it strides
+// over into one row, then the totals row.  Every call overwrites all the
+// rows it reads, so nothing needs clearing; calls that overlap on one GPU
+// (two streams) race on the array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's copy of the array (current device), looked
+// up once per device; in host code the array's name is not a device address.
+hipError_t moments_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = (double*)p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t moments_rows_t(Context* c, void* d_rho, void* d_u, double* rows) {
+  StreamArgs<T> a = stream_args<T>(c);
+  const int blocks = std::min(kScratchRows, a.nitems);
+  hipLaunchKernelGGL((k_moments<T, true>), dim3(blocks), dim3(kBlock), 0, c->stream, a, 0,
+                     (T*)d_rho, (T*)d_u, rows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(kBlock), 0, c->stream, a,
+                     (const RepMD*)at(c, c->plan.lay.rep_md), rows,
+                     (const double*)(c->bound ? c->v : nullptr), c->plan.Ntot,
+                     rows + (size_t)kScratchRows * kRedWidth, blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_rows(Context* c, void* d_rho, void* d_u, double* rows) {
+  return c->plan.prec == 32 ? moments_rows_t<float>(c, d_rho, d_u, rows)
+                            : moments_rows_t<double>(c, d_rho, d_u, rows);
 }
 
 // ---------------------------------------------------------------------------

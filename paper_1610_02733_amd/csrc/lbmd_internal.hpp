@@ -23,6 +23,11 @@ using lbmd_dev::Geom;
 
 constexpr int kBlock = 256;  // threads per block; site chunks of the LB kernels
 constexpr int kRedWidth = 16;
+// lb_moments_noalloc: reduction rows in a fixed device array of this
+// library, 1024 block rows + the totals row of kRedWidth doubles (131,200
+// bytes per GPU)
+constexpr int kScratchRows = 1024;
+constexpr int kScratchDoubles = (kScratchRows + 1) * kRedWidth;
 
 // Per-replica constants of the LB kernels (run precision T).
 template <typename T>
@@ -187,6 +192,7 @@ struct Context {
   int sticky;
   Tune tune;
   bool graph_ok;
+  double* scratch_rows;  // this GPU's copy of the lb_moments_noalloc array
 };
 
 inline void* at(const Context* c, size_t off) { return c->ws + off; }
@@ -219,6 +225,8 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 size_t sort_temp_bytes(int64_t N);
 hipError_t launch_sort_particles(Context* c, int32_t* d_perm, bool* too_small);
 hipError_t launch_moments(Context* c, int rep, void* d_rho, void* d_u, double* d_totals);
+hipError_t moments_scratch(double** out);
+hipError_t launch_moments_rows(Context* c, void* d_rho, void* d_u, double* rows);
 hipError_t launch_get_populations(Context* c, int rep, void* dst);
 hipError_t launch_set_populations(Context* c, int rep, const void* src);
 hipError_t launch_get_transfer(Context* c, int rep, void* dst);

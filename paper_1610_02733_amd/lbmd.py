@@ -67,6 +67,7 @@ def lib():
         L.md_couple_substep.argtypes = [P]
         L.lb_step.argtypes = [P]
         L.lb_moments.argtypes = [P, P, P, P]
+        L.lb_moments_noalloc.argtypes = [P, P, P, P]
         L.lbmd_get_populations.argtypes = [P, P]
         L.lbmd_set_populations.argtypes = [P, P]
         L.lbmd_get_transfer.argtypes = [P, P]
@@ -101,7 +102,8 @@ def lib():
         L.lbmd_adjoint_result.argtypes = [P, P, P, P]
         L.lbmd_sort_particles.argtypes = [P, P]
         for n in ("lbmd_sort_particles", "lb_create", "lb_destroy", "lbmd_bind_particles", "md_couple_substep",
-                  "lb_step", "lb_moments", "lbmd_get_populations", "lbmd_set_populations",
+                  "lb_step", "lb_moments", "lb_moments_noalloc", "lbmd_get_populations",
+                  "lbmd_set_populations",
                   "lbmd_get_transfer", "lbmd_get_counters", "lbmd_set_counters",
                   "lbmd_run_cycles", "lb_create_batch", "lbmd_replica_count",
                   "lbmd_batch_moments", "lbmd_batch_get_populations",
@@ -299,15 +301,19 @@ class Lattice(_System):
         _check(lib().lbmd_get_transfer(self._h, _ptr(out)), "lbmd_get_transfer")
         return out
 
-    def moments(self, fields=False, allow_nonfinite=False):
+    def moments(self, fields=False, allow_nonfinite=False, noalloc=False):
+        """Totals (LBMD_TOT_* layout) and optionally the density and velocity
+        fields; noalloc=True calls lb_moments_noalloc (reduction scratch in
+        the library's fixed device array instead of the workspace)."""
         tot = np.zeros(NTOTALS)
         rho = u = None
         if fields:
             rho = torch.empty(self.nsites, dtype=self.dtype, device=self.device)
             u = torch.empty((3, self.nsites), dtype=self.dtype, device=self.device)
-        rc = lib().lb_moments(self._h, _ptr(rho), _ptr(u), tot.ctypes.data_as(C.c_void_p))
+        fn = lib().lb_moments_noalloc if noalloc else lib().lb_moments
+        rc = fn(self._h, _ptr(rho), _ptr(u), tot.ctypes.data_as(C.c_void_p))
         if rc != OK and not (allow_nonfinite and rc == ENONFINITE):
-            raise LbmdError(rc, "lb_moments")
+            raise LbmdError(rc, "lb_moments_noalloc" if noalloc else "lb_moments")
         return (tot, rho, u) if fields else tot
 
 
