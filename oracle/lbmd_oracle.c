@@ -725,8 +725,20 @@ static void forcing_update(const orc_ctx *c, int64_t r, const double dJ[3]) {
  *       u(R) = sum_k delta_k u(r_k)                                 (Eq. 5)
  *       F_c  = -gamma (v - u(R)) + F_rand                          (Eq. 4)
  *       dP   = tau_MD F_c                                           (Eq. 6)
- *     F_rand has <F_a F_b> = 2 gamma kT / tau_MD delta_ab per MD step
- *     (the discrete fluctuation-dissipation balance of the friction).
+ *     F_rand has <F_a F_b> = (2 gamma kT / tau_MD) (1 - a/2) delta_ab
+ *     per MD step with a = gamma tau_MD (1/m + S/rho0), S = sum_k delta_k^2:
+ *     the fluctuation-dissipation balance of the explicit step itself.  The
+ *     step damps the relative velocity w of the particle and the fluid at
+ *     its stencil (which in variant B takes -dP at once, an effective mass
+ *     rho0/S) as w' = (1 - a) w + (1/m + S/rho0) dP_rand; that AR(1) process
+ *     has the equilibrium variance kT (1/m + S/rho0) of the pair's relative
+ *     velocity exactly when <dP_rand^2> = 2 gamma kT tau_MD (1 - a/2).  The
+ *     paper requires noise balancing the friction (Sec. 1, Sec. 3) without
+ *     giving the discrete amplitude; this one reproduces its temperature
+ *     statements (Sec. 3: variant B within 2% at m = 10, dt = 0.01 tau for
+ *     zeta up to 20; variant A heating with zeta, dt and m, equally at equal
+ *     LB step), the continuous-time amplitude (a -> 0) does not.  Clamped at
+ *     0 for a >= 2, beyond the stability bound of the explicit step.
  *  2. every particle transfers -delta_k dP to J(r_k)          (Eq. 7-8)
  *     -- all particles read the velocities of step 1 first, so within one
  *     MD step no particle sees another's transfer of the same step.  In
@@ -768,8 +780,12 @@ int orc_md_couple_substep(orc_ctx *c) {
     double xi[3] = {0.0, 0.0, 0.0};
     if (p->kT > 0.0 && p->friction > 0.0)
       orc_particle_variates(p->seed, p->replica, (uint64_t)a, (uint64_t)c->t_md, xi);
+    double S2 = 0.0; /* S = sum of the squared stencil weights */
+    for (int k = 0; k < K; ++k) S2 += wts[a][k] * wts[a][k];
+    double adamp = p->friction * tau * (1.0 / p->particle_mass + S2 / p->rho0);
+    double amp_a = amp * sqrt(fmax(0.0, 1.0 - 0.5 * adamp));
     for (int d = 0; d < 3; ++d)
-      Fc[d * N + a] = -p->friction * (v[d] - uR[d]) + amp * xi[d];
+      Fc[d * N + a] = -p->friction * (v[d] - uR[d]) + amp_a * xi[d];
   }
   for (int64_t a = 0; a < N; ++a)
     if (!ok[a]) c->nonfinite = 1;

@@ -147,7 +147,9 @@ struct AdjMDArgs {
 // particle, one per corner k of its cube.  Forward, with s = X - floor(X)
 // and w_k(s) the corner weights:
 //   u   = sum_k w_k U_k / rho_k          (U_k = j_k [+ J_k in variant 2])
-//   Fc  = -gamma (V - u) + A xi,         A = sqrt(2 gamma kT / tau)
+//   Fc  = -gamma (V - u) + A xi,         A = c sqrt(gamma B), c = sqrt(2 kT / tau),
+//                                         B = 1 - gamma tau (1/m + S/rho0) / 2,
+//                                         S = sum_k w_k^2 (noise_amplitude)
 //   J_k += -w_k tau Fc                   (transfer, Eq. 7-8)
 //   V1  = V + h (f + Fc);  X' = X + tau V1;  V' = V1 + h (f + Fc)
 // Reverse: from X'-bar, V'-bar and J-bar at the corners, the adjoints of X,
@@ -198,6 +200,17 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
     double u[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) u[d] = oct_sum(w * ir * U[d]);
+    // noise amplitude A(gamma, S) and its derivatives (zero where A = 0:
+    // gamma = 0, or the balance factor clamped)
+    const double S = oct_sum(w * w);
+    double dS[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dS[d] = oct_sum(2.0 * w * dw[d]);
+    const double A = m.noise ? noise_amplitude(m, S) : 0.0;
+    const double c2 = m.gamma > 0.0 ? m.amp * m.amp / m.gamma : 0.0;  // 2 kT / tau
+    const double a_damp = 2.0 * (1.0 - noise_balance(m, S));
+    const double dA_dg = A > 0.0 ? c2 * (1.0 - a_damp) / (2.0 * A) : 0.0;
+    const double dA_dS = A > 0.0 ? -c2 * m.gamma * m.gamma * m.tau / (4.0 * m.rho0 * A) : 0.0;
     double xi[3] = {0.0, 0.0, 0.0};
     if (m.noise) {
       const Words4 o = philox10(Words4{(uint32_t)a.pid[p], step_lo, m.tag, step_hi}, m.key0,
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
     double Fc[3], xb[3], vb[3], Fcb[3], fb[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Fc[d] = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
+      Fc[d] = -m.gamma * (V[d] - u[d]) + A * xi[d];
       xb[d] = a.xbar[d * N + p];
       vb[d] = a.vbar[d * N + p];
       const double v1b = vb[d] + m.tau * xb[d];
@@ -227,18 +240,18 @@ __global__ __launch_bounds__(kBlock) void k_couple_adjoint(AdjMDArgs a,
       xs[d] = -m.tau * gk * dw[d];
     }
     // friction and noise
-    double ub[3], gbar = 0.0;
-    const double half_amp_over_gamma = (m.noise && m.gamma > 0.0) ? 0.5 * m.amp / m.gamma : 0.0;
+    double ub[3], gbar = 0.0, nb = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       vb[d] -= m.gamma * Fcb[d];
       ub[d] = m.gamma * Fcb[d];
-      gbar += Fcb[d] * (-(V[d] - u[d]) + half_amp_over_gamma * xi[d]);
+      gbar += Fcb[d] * (-(V[d] - u[d]) + dA_dg * xi[d]);
+      nb += Fcb[d] * xi[d];
     }
-    // interpolation weights
+    // interpolation weights (through u, the transfer and the noise amplitude)
     const double uk = ir * (U[0] * ub[0] + U[1] * ub[1] + U[2] * ub[2]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xs[d] = oct_sum(xs[d] + uk * dw[d]);
+    for (int d = 0; d < 3; ++d) xs[d] = oct_sum(xs[d] + uk * dw[d]) + nb * dA_dS * dS[d];
     if (k == 0) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {

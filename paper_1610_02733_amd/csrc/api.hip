@@ -214,6 +214,7 @@ RepMD rep_md(const Context* c, int r) {
   m.amp = sqrt(2.0 * p.friction * p.kT / tau);
   m.tau = tau;
   m.h = p.n_particles > 0 ? tau / (2.0 * p.particle_mass) : 0.0;
+  m.inv_m = p.n_particles > 0 ? 1.0 / p.particle_mass : 0.0;
   m.L[0] = p.nx;
   m.L[1] = p.ny;
   m.L[2] = p.nz;

@@ -257,6 +257,12 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         }
       }
       const double u[3] = {Sh::sum(ux), Sh::sum(uy), Sh::sum(uz)};
+      // noise amplitude from the stencil's squared weights (noise_amplitude)
+      double s2 = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj)
+        if (gs_[jj] >= 0) s2 += w_[jj] * w_[jj];
+      const double amp = m.noise ? noise_amplitude(m, Sh::sum(s2)) : 0.0;
       // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
       double xi[3] = {0.0, 0.0, 0.0};
       if (m.noise) {
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       double Xn[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double Fc = -m.gamma * (V[d] - u[d]) + m.amp * xi[d];
+        const double Fc = -m.gamma * (V[d] - u[d]) + amp * xi[d];
         dp[d] = m.tau * Fc;
         const double fc = a.fcons[d * N + p];
         int32_t im = a.img[d * N + p];

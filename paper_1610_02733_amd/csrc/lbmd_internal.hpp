@@ -50,7 +50,9 @@ struct RepMD {
   int variant, noise, split_kick, force_model, chain_len;
   int stencil;  // 0 trilinear (8 sites), 1 three-point kernel (27 sites)
   uint32_t key0, key1, tag;
-  double rho0, gamma, amp, tau, h;
+  double rho0, gamma, amp, tau, h;  // amp = sqrt(2 gamma kT / tau): the particle noise
+                                    // amplitude before the balance factor (noise_amplitude)
+  double inv_m;                     // 1 / particle mass (0 without particles)
   double L[3];
   double f_ext[3];
   double k_bond, r0_bond, wca_eps, wca_sigma;

@@ -80,6 +80,22 @@ __device__ __forceinline__ void corner_of(const Cube& q, const Geom& g, int k, i
       ((k & 4) ? q.s[2] : 1.0 - q.s[2]);
 }
 
+// Particle noise amplitude for the stencil weights' squared sum S: the
+// random force balances the dissipation of the explicit MD step (Eq. 4, 6).
+// The step damps the relative velocity w of the particle and the fluid at its
+// stencil (the fluid takes -dP there at once: an effective mass rho0 / S) as
+// w <- (1 - a) w + (1/m + S/rho0) dP_rand, a = gamma tau (1/m + S/rho0),
+// whose equilibrium variance is kT (1/m + S/rho0) when <dP_rand^2> =
+// 2 gamma kT tau (1 - a/2): F_rand = sqrt(2 gamma kT / tau) sqrt(1 - a/2) xi.
+// Zero for a >= 2 (beyond the explicit step's stability bound).
+__device__ __forceinline__ double noise_balance(const RepMD& m, double S) {
+  return 1.0 - 0.5 * (m.gamma * m.tau * (m.inv_m + S / m.rho0));
+}
+__device__ __forceinline__ double noise_amplitude(const RepMD& m, double S) {
+  const double bal = noise_balance(m, S);
+  return bal > 0.0 ? m.amp * sqrt(bal) : 0.0;
+}
+
 // Kernels that give a particle one lane per corner of its cube (8 | kBlock,
 // so the lanes of a particle are always active together).
 constexpr int kCornerLanes = 8;

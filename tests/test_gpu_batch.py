@@ -99,7 +99,12 @@ def test_batch_replicas_match_single_runs(lb, orc, prec, variant):
         ts = s.moments()
         mtol = 1e-9 if prec == 64 else 1e-6
         assert abs(tot[r, 0] - ts[0]) < mtol * ts[0]
-        assert np.allclose(tot[r, 7:11], ts[7:11], rtol=mtol, atol=1e-12)
+        # particle momentum: a sum that cancels, compared on the scale of its
+        # terms; kinetic energy relative to itself
+        pscale = kw.get("particle_mass", 1.0) * np.abs(s.v.cpu().numpy()).sum(1) + 1e-300 \
+            if kw["n_particles"] > 0 else np.ones(3)
+        assert (np.abs(tot[r, 7:10] - ts[7:10]) <= mtol * pscale + 1e-15).all(), r
+        assert abs(tot[r, 10] - ts[10]) <= mtol * abs(ts[10]) + 1e-15, r
 
 
 @pytest.mark.parametrize("variant,stencil", [(2, 0), (3, 0), (2, 1)])
