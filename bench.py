@@ -194,75 +194,145 @@ def error_statement(lbmd, torch, cfg, x, v, cycles=10):
     return out
 
 
-def batch_measure(lbmd, torch, nrep=512, cycles=20, serial_cycles=2):
-    """Batched ensemble: nrep independent replicas (edges in {24,32,40,48},
-    20..400 free particles, gamma in [1,20], kT=1e-3, n=5, FP32, variant 2)
-    in one batch (captured cycles, autotuned launch shapes) against the same
-    replicas as separate systems launched one after another."""
-    import tempfile
+def _c4_replicas(lbmd, nrep, gamma_range=(1.0, 20.0), variant=2, draw_seed=4):
+    """The batched ensemble: nrep periodic replicas, edges in {24,32,40,48},
+    20..400 free particles, gamma uniform in gamma_range, kT = 1e-3, n = 5,
+    FP32; replica r draws its particles from seed 4000 + r."""
     from paper_1610_02733_amd import workloads as wl
-    edges, nps, gammas = wl.batch_replicas(nrep, seed=4)
+    edges, nps, gammas = wl.batch_replicas(nrep, seed=draw_seed, gamma_range=gamma_range)
     reps, xs, vs = [], [], []
     for r in range(nrep):
         shape = (int(edges[r]),) * 3
-        kw = dict(precision=32, n_sub=5, variant=2, kT=1e-3, nu=1.0 / 6.0, seed=4, replica=r,
-                  n_particles=int(nps[r]), friction=float(gammas[r]), particle_mass=1.0)
+        kw = dict(precision=32, n_sub=5, variant=variant, kT=1e-3, nu=1.0 / 6.0, seed=4,
+                  replica=r, n_particles=int(nps[r]), friction=float(gammas[r]),
+                  particle_mass=1.0)
         x, v = wl.free_particles(shape, int(nps[r]), 1e-3, 1.0, 4000 + r)
         reps.append((shape, kw))
         xs.append(x)
         vs.append(v)
-    sites = int(sum(int(e) ** 3 for e in edges))
+    return reps, xs, vs, edges, nps, gammas
+
+
+def _time_batch_vs_serial(lbmd, torch, reps, xs, vs, cycles, warm=2):
+    """Batched (one launch per phase, captured cycle) against the same
+    replicas as separate systems, per-call launches and per-replica captured
+    cycles.  Every leg starts from the same bound state, runs `warm` untimed
+    cycles and then the same `cycles` timed cycles, so all legs do the same
+    work (a replica that diverges does so at the same cycle in each)."""
+    import tempfile
+    out = {}
     B = lbmd.Batch(reps)
     B.bind_particles(xs, vs)
-    tune = B.autotune(os.path.join(tempfile.gettempdir(), "lbmd_autotune.json"))
-    B.run_cycles(2)
+    out["autotune"] = B.autotune(os.path.join(tempfile.gettempdir(), "lbmd_autotune.json"))
+    B.run_cycles(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     B.run_cycles(cycles)
     torch.cuda.synchronize()
-    batched = (time.perf_counter() - t0) / cycles
-    T = B.temperatures()
-    ok = np.isfinite(T)
-    # per-replica temperature trace T_p(t) / kT of the ensemble (finite replicas)
-    trace = []
-    for _ in range(5):
-        B.run_cycles(10)
-        Tt = B.temperatures()
-        fin = np.isfinite(Tt)
-        trace.append(dict(cycles=int(B.counters()["t_lb"]), finite_replicas=int(fin.sum()),
-                          mean=round(float(np.mean(Tt[fin])), 4) if fin.any() else None,
-                          min=round(float(np.min(Tt[fin])), 4) if fin.any() else None,
-                          max=round(float(np.max(Tt[fin])), 4) if fin.any() else None))
+    out["batched_ms_per_cycle"] = (time.perf_counter() - t0) / cycles * 1e3
+    out["finite_replicas_batched"] = int(np.isfinite(B.temperatures()).sum())
     B.close()
     del B
     torch.cuda.empty_cache()
     sims = []
-    for r in range(nrep):
-        s = lbmd.Lattice(reps[r][0], **reps[r][1])
-        s.bind_particles(xs[r], vs[r])
+    for (shape, kw), x, v in zip(reps, xs, vs):
+        s = lbmd.Lattice(shape, **kw)
+        s.bind_particles(x, v)
         sims.append(s)
     for s in sims:
-        s.cycle(1)
+        s.cycle(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(serial_cycles):
-        for s in sims:
-            s.cycle(1)
-    torch.cuda.synchronize()
-    serial = (time.perf_counter() - t0) / serial_cycles
     for s in sims:
+        s.cycle(cycles)
+    torch.cuda.synchronize()
+    out["serial_ms_per_cycle"] = (time.perf_counter() - t0) / cycles * 1e3
+    for s in sims:  # the per-replica graphs, captured outside the timed window
+        s.run_cycles(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.run_cycles(cycles)
+    torch.cuda.synchronize()
+    out["serial_graph_ms_per_cycle"] = (time.perf_counter() - t0) / cycles * 1e3
+    fin = 0
+    for s in sims:
+        tot = s.moments(allow_nonfinite=True)
+        fin += int(np.isfinite(tot[lbmd.TOT["tpart"]]) or s.N == 0)
         s.close()
+    out["finite_replicas_serial"] = fin
     del sims
     torch.cuda.empty_cache()
-    return dict(replicas=nrep, sites=sites, particles=int(nps.sum()),
-                batched_ms_per_cycle=round(batched * 1e3, 3),
-                serial_ms_per_cycle=round(serial * 1e3, 3),
-                speedup=round(serial / batched, 2),
-                batched_mlups=round(sites / batched / 1e6, 1),
-                autotune=tune, cycles_after_warmup=cycles + 2,
-                finite_replicas=int(ok.sum()),
-                mean_T_over_kT_finite=round(float(np.mean(T[ok])), 4) if ok.any() else None,
-                temperature_trace=trace)
+    out["speedup_vs_serial"] = round(out["serial_ms_per_cycle"] / out["batched_ms_per_cycle"], 2)
+    out["speedup_vs_serial_graphs"] = round(
+        out["serial_graph_ms_per_cycle"] / out["batched_ms_per_cycle"], 2)
+    for k in ("batched_ms_per_cycle", "serial_ms_per_cycle", "serial_graph_ms_per_cycle"):
+        out[k] = round(out[k], 3)
+    return out
+
+
+def _temperature_drift(lbmd, torch, reps, xs, vs, gammas, cycles=1000, every=10):
+    """Per-replica particle temperature T_p / kT over `cycles` LB steps
+    (the ensemble statistics of the paper's Sec. 3 temperature test), in
+    bins of the dimensionless friction gamma tau_MD / m: replicas, diverged
+    replicas, mean T_p/kT of the finite ones over the second half, and its
+    drift (last quarter minus second quarter)."""
+    B = lbmd.Batch(reps)
+    B.bind_particles(xs, vs)
+    series = []
+    for _ in range(cycles // every):
+        B.run_cycles(every)
+        series.append(B.temperatures())
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    T = np.array(series)  # [samples, replicas]
+    ns = T.shape[0]
+    g_tau = np.asarray(gammas) * 0.2  # tau_MD = 1/5, m = 1
+    fin = np.isfinite(T).all(0)
+    bins = [(0.2, 0.5), (0.5, 1.0), (1.0, 2.0), (2.0, 4.0)]
+    rows = []
+    for lo, hi in bins:
+        sel = (g_tau >= lo) & (g_tau < hi) if hi < 4.0 else (g_tau >= lo)
+        ok = sel & fin
+        row = dict(gamma_tau=[lo, hi], replicas=int(sel.sum()), diverged=int((sel & ~fin).sum()))
+        if ok.any():
+            half = T[ns // 2:, ok]
+            q2, q4 = T[ns // 4: ns // 2, ok], T[3 * ns // 4:, ok]
+            row.update(mean_T_over_kT=round(float(half.mean()), 4),
+                       replica_sd=round(float(half.mean(0).std()), 4),
+                       drift=round(float(q4.mean() - q2.mean()), 4))
+        rows.append(row)
+    return dict(lb_steps=cycles, sample_every=every, finite_replicas=int(fin.sum()),
+                replicas=int(T.shape[1]), bins=rows)
+
+
+def batch_measure(lbmd, torch, nrep=512, cycles=10, drift_cycles=1000):
+    """Batched ensemble (form ii): 512 independent replicas of uneven box and
+    particle counts in one batch against the same replicas as separate
+    systems, and the ensemble's temperature statistics over 1000 LB steps
+    in variants A and B.  The C4 draws reach gamma tau_MD / m = 4, beyond the
+    explicit step's stability bound (about 2 / (1 + S)), so part of that
+    ensemble diverges; the timing is therefore also taken on a stable redraw
+    (gamma in [1, 4.5]) where every replica stays finite."""
+    reps, xs, vs, edges, nps, gammas = _c4_replicas(lbmd, nrep)
+    sites = int(sum(int(e) ** 3 for e in edges))
+    out = dict(replicas=nrep, sites=sites, particles=int(nps.sum()), timed_cycles=cycles)
+    log("  batch timing, C4 draws (gamma in [1, 20])")
+    out["c4"] = _time_batch_vs_serial(lbmd, torch, reps, xs, vs, cycles)
+    out["c4"]["batched_mlups"] = round(sites / (out["c4"]["batched_ms_per_cycle"] * 1e-3) / 1e6, 1)
+    log("  batch timing, stable redraw (gamma in [1, 4.5])")
+    sreps, sxs, svs, sedges, snps, sg = _c4_replicas(lbmd, nrep, gamma_range=(1.0, 4.5))
+    out["stable"] = _time_batch_vs_serial(lbmd, torch, sreps, sxs, svs, cycles)
+    out["stable"]["sites"] = int(sum(int(e) ** 3 for e in sedges))
+    drift = {}
+    for variant in (1, 2):
+        log(f"  temperature drift, variant {variant}, {drift_cycles} LB steps")
+        vreps = [(shape, dict(kw, variant=variant)) for shape, kw in reps]
+        drift[f"variant{variant}"] = _temperature_drift(lbmd, torch, vreps, xs, vs, gammas,
+                                                         cycles=drift_cycles)
+    out["temperature_drift"] = drift
+    return out
 
 
 def adjoint_measure(lbmd, torch, reps=3):
@@ -384,6 +454,8 @@ def main():
                          "the same shapes with the paper's Kremer-Grest force field")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-replica batched-ensemble measurement")
+    ap.add_argument("--drift-cycles", type=int, default=1000,
+                    help="LB steps of the batched ensemble's temperature statistics")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the reverse-mode (adjoint) cost measurement")
     ap.add_argument("--sort-every", type=int, default=50,
@@ -482,8 +554,8 @@ def main():
         out["stencil3"] = {"variant": main_v, "ms_per_step": round(w3 / args.steps * 1e3, 4),
                            "over_trilinear": round(w3 / res[main_v][0], 4), "finite": f3}
     if not args.no_batch:
-        log("batched ensemble: 512 replicas, batched vs serial")
-        out["batch"] = batch_measure(lbmd, torch)
+        log("batched ensemble: 512 replicas, batched vs serial, temperature drift")
+        out["batch"] = batch_measure(lbmd, torch, drift_cycles=args.drift_cycles)
     if not args.no_adjoint:
         log("adjoint: 64^3 / 1000 particles, backward vs forward")
         out["adjoint"] = adjoint_measure(lbmd, torch)

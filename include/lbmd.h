@@ -287,15 +287,33 @@ int lbmd_batch_set_populations(lbmd *c, int32_t rep, const void *d_src);
 int lbmd_batch_get_transfer(lbmd *c, int32_t rep, void *d_dst);
 
 /*
- * Launch-shape autotuner: times candidate persistent-grid sizes of the LB
- * kernels and of the particle kernels on this context, keeps the fastest and
- * caches them in a JSON file at cache_path (nullable: no cache), keyed by
- * device architecture, precision, variant, replica count and size class.
- * Must run at an LB-step boundary (LBMD_ESTATE otherwise); the simulation
- * state is left unchanged.  Synchronizes.  Outputs (nullable): the chosen
- * block counts (0 = one block per work item).
+ * Launch-shape autotuner (form ii): times, on this context, candidate
+ * launch shapes of each hot kernel on the kernel itself and keeps the
+ * fastest: the persistent grid of the collide-stream kernel ({one block per
+ * 256 sites, 4, 8, 16, 32 blocks per CU}), the grid of the particle
+ * kernels (timed on the corner refill) and the lanes per particle of the
+ * coupling kernel ({2, 4, 8} trilinear, {8, 16} three-point stencil; timed
+ * on whole MD steps, coupling plus after-step work; force models 0 and 1,
+ * whose particle state is saved and restored around the timing).  The block
+ * size is fixed at 256 threads (the kernels' segments and LDS layouts
+ * assume it).  The picks are cached in a JSON file at cache_path (nullable:
+ * no cache), keyed by device architecture, precision, variant, replica count
+ * and size class.  Must run at an LB-step boundary (LBMD_ESTATE otherwise);
+ * the simulation state is left unchanged (the next MD step refills the
+ * corner cache).  Synchronizes.  Outputs (nullable): the chosen block
+ * counts (0 = one block per work item) and lanes (0 = the built-in default).
  */
-int lbmd_autotune(lbmd *c, const char *cache_path, int32_t *lb_blocks, int32_t *part_blocks);
+int lbmd_autotune(lbmd *c, const char *cache_path, int32_t *lb_blocks, int32_t *part_blocks,
+                  int32_t *couple_lanes);
+
+/*
+ * Set the launch shapes the autotuner would pick (the same meanings: block
+ * counts >= 0, 0 = one block per work item; couple_lanes 0 = default, else
+ * one of the candidates above, LBMD_EINVAL otherwise).  At an LB-step
+ * boundary only (LBMD_ESTATE).  Results do not depend on the shapes beyond
+ * the order of the transfer sums.
+ */
+int lbmd_set_launch_shape(lbmd *c, int32_t lb_blocks, int32_t part_blocks, int32_t couple_lanes);
 
 /*
  * Saved states (checkpoint / resume).  A state holds the step counters, the

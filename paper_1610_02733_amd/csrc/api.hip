@@ -317,6 +317,7 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->sticky = LBMD_OK;
   c->tune.lb_blocks = 0;
   c->tune.part_blocks = 0;
+  c->tune.couple_lanes = 0;
   c->graph_ok = false;
   c->popv[0] = at(c, pl.lay.pop[0]);
   c->popv[1] = at(c, pl.lay.pop[1]);
@@ -955,29 +956,33 @@ std::string tune_key(lbmd* c) {
   return std::string(buf);
 }
 
-std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
-  std::map<std::string, std::pair<int, int>> m;
+struct TuneEntry {
+  int lb_blocks, part_blocks, couple_lanes;
+};
+
+std::map<std::string, TuneEntry> read_cache(const char* path) {
+  std::map<std::string, TuneEntry> m;
   FILE* f = path ? fopen(path, "r") : nullptr;
   if (!f) return m;
   char line[512];
   while (fgets(line, sizeof(line), f)) {
     char key[300];
-    int a, b;
-    if (sscanf(line, " \"%299[^\"]\": [%d, %d]", key, &a, &b) == 3) m[key] = {a, b};
+    int a, b, l;
+    if (sscanf(line, " \"%299[^\"]\": [%d, %d, %d]", key, &a, &b, &l) == 4) m[key] = {a, b, l};
   }
   fclose(f);
   return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+void write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
   if (!path) return;
   FILE* f = fopen(path, "w");
   if (!f) return;
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m)
-    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.first, kv.second.second,
-            ++i < m.size() ? "," : "");
+    fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.lb_blocks,
+            kv.second.part_blocks, kv.second.couple_lanes, ++i < m.size() ? "," : "");
   fprintf(f, "}\n");
   fclose(f);
 }
@@ -1006,16 +1011,17 @@ double time_ms(lbmd* c, F fn, int reps, hipError_t* err) {
 extern "C" {
 
 int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
-                  int32_t* out_part_blocks) {
+                  int32_t* out_part_blocks, int32_t* out_couple_lanes) {
   if (!c) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
-  if (c->subs != 0) return LBMD_ESTATE;
+  if (c->subs != 0 || c->rec_part) return LBMD_ESTATE;
   const std::string key = tune_key(c);
   auto cache = read_cache(cache_path);
   auto hit = cache.find(key);
   if (hit != cache.end()) {
-    c->tune.lb_blocks = hit->second.first;
-    c->tune.part_blocks = hit->second.second;
+    c->tune.lb_blocks = hit->second.lb_blocks;
+    c->tune.part_blocks = hit->second.part_blocks;
+    c->tune.couple_lanes = hit->second.couple_lanes;
   } else {
     hipError_t e = hipSuccess;
     int cu = 256;
@@ -1023,7 +1029,9 @@ int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cu = 256;
-    // LB kernels: blocks in flight
+    // LB kernels: blocks in flight of the collide-stream kernel, timed on
+    // its own (writes only the spare population buffer; at an LB-step
+    // boundary no transfer is pending)
     const int lb_cand[5] = {0, 4 * cu, 8 * cu, 16 * cu, 32 * cu};
     double best = 1e30;
     int best_lb = 0;
@@ -1037,9 +1045,13 @@ int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
       }
     }
     c->tune.lb_blocks = best_lb;
-    // particle kernels: the cache refill reads particle positions only
-    int best_part = 0;
+    int best_part = 0, best_lanes = 0;
     if (c->plan.Ntot > 0 && c->bound) {
+      const Layout& L = c->plan.lay;
+      const size_t S = (size_t)c->plan.Stot, N = (size_t)c->plan.Ntot;
+      const size_t t = c->plan.prec == 32 ? 4 : 8;
+      // the particle kernels' grid, timed on the corner refill (reads
+      // particle positions; writes the cache and the claims only)
       const int part_cand[5] = {0, 2 * cu, 4 * cu, 8 * cu, 16 * cu};
       best = 1e30;
       for (int q : part_cand) {
@@ -1051,16 +1063,89 @@ int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
           best_part = q;
         }
       }
+      c->tune.part_blocks = best_part;
+      // lanes per particle of the coupling kernel, timed on whole MD steps
+      // (coupling kernel + after-step work) from a fresh refill; the
+      // particles move, so their state is saved in the sort scratch and put
+      // back afterwards (force models 0 and 1: nothing else depends on it)
+      bool movable = true;
+      for (int r = 0; r < c->plan.R; ++r) movable = movable && c->p[r].force_model <= 1;
+      if (movable) {
+        int32_t flags_saved[16];
+        e = hipMemcpyAsync(flags_saved, at(c, L.flags), sizeof(flags_saved),
+                           hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(at(c, L.sort_x), c->x, 3 * N * 8,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(at(c, L.sort_v), c->v, 3 * N * 8,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(at(c, L.sort_img), c->img, 3 * N * 4,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, e);
+        int cand[4];
+        const int nc = couple_lane_candidates(c->p[0].stencil, cand);
+        best = 1e30;
+        for (int k = 0; k < nc && e == hipSuccess; ++k) {
+          c->tune.couple_lanes = cand[k];
+          e = hipMemsetAsync(at(c, L.transfer), 0, S * 4 * t, c->stream);
+          if (e == hipSuccess) e = hipMemsetAsync(at(c, L.mark), 0, (S / 64) * 8, c->stream);
+          if (e == hipSuccess) e = launch_couple_refill_only(c);
+          c->cache_dirty = false;
+          if (e != hipSuccess) break;
+          const double ms = time_ms(c, [&] { return launch_couple(c, 1); }, 3, &e);
+          if (e == hipSuccess && ms < best) {
+            best = ms;
+            best_lanes = cand[k];
+          }
+        }
+        // put the state back: particles, an empty transfer field and marks,
+        // the non-finite flags; the cache is refilled at the next MD step
+        if (e == hipSuccess) e = hipMemcpyAsync(c->x, at(c, L.sort_x), 3 * N * 8,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->v, at(c, L.sort_v), 3 * N * 8,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->img, at(c, L.sort_img), 3 * N * 4,
+                                                hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(at(c, L.flags), flags_saved, sizeof(flags_saved),
+                                                hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return fail(c, e);
+      }
+      // the refills left claims (marks, shared flags) of this interval:
+      // start it clean
+      e = hipMemsetAsync(at(c, L.transfer), 0, S * 4 * t, c->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(at(c, L.mark), 0, (S / 64) * 8, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return fail(c, e);
+      c->cache_dirty = true;
     }
     c->tune.part_blocks = best_part;
-    // the refill timing left marks and cached corners of this interval: the
-    // marks are harmless (no transfer is pending), the cache is valid
-    cache[key] = {c->tune.lb_blocks, c->tune.part_blocks};
+    c->tune.couple_lanes = best_lanes;
+    cache[key] = {c->tune.lb_blocks, c->tune.part_blocks, c->tune.couple_lanes};
     write_cache(cache_path, cache);
   }
   drop_graph(c);
   if (out_lb_blocks) *out_lb_blocks = c->tune.lb_blocks;
   if (out_part_blocks) *out_part_blocks = c->tune.part_blocks;
+  if (out_couple_lanes) *out_couple_lanes = c->tune.couple_lanes;
+  return LBMD_OK;
+}
+
+int lbmd_set_launch_shape(lbmd* c, int32_t lb_blocks, int32_t part_blocks,
+                          int32_t couple_lanes) {
+  if (!c || lb_blocks < 0 || part_blocks < 0 || couple_lanes < 0) return LBMD_EINVAL;
+  if (c->sticky) return c->sticky;
+  if (c->subs != 0 || c->rec_part) return LBMD_ESTATE;
+  if (couple_lanes > 0) {
+    int cand[4];
+    const int nc = couple_lane_candidates(c->p[0].stencil, cand);
+    bool ok = false;
+    for (int k = 0; k < nc; ++k) ok = ok || cand[k] == couple_lanes;
+    if (!ok) return LBMD_EINVAL;
+  }
+  c->tune.lb_blocks = lb_blocks;
+  c->tune.part_blocks = part_blocks;
+  c->tune.couple_lanes = couple_lanes;
+  drop_graph(c);
   return LBMD_OK;
 }
 

@@ -384,6 +384,26 @@ static hipError_t launch_refill_st(Context* c, const CoupleArgs<T>& a) {
   return hipGetLastError();
 }
 
+int couple_lane_candidates(int stencil, int out[4]) {
+  if (stencil == 1) {
+    out[0] = 8;
+    out[1] = 16;
+    return 2;
+  }
+  out[0] = 2;
+  out[1] = 4;
+  out[2] = 8;
+  return 3;
+}
+
+template <typename T, int ST, int L>
+static void launch_couple_lanes(Context* c, const CoupleArgs<T>& a, bool bin, dim3 grid) {
+  if (bin)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, true>), grid, dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, false>), grid, dim3(kBlock), 0, c->stream, a);
+}
+
 template <typename T, int ST>
 static hipError_t couple_st(Context* c, int substep) {
   using St = Stencil<ST>;
@@ -397,20 +417,28 @@ static hipError_t couple_st(Context* c, int substep) {
     if ((e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
     c->cache_dirty = false;
   }
-  // lanes per particle of the coupling kernel (eight while recording)
-  const int L = a.rec ? 8 : DirectShape<ST>::kLanes;
+  // lanes per particle of the coupling kernel: eight while recording, else
+  // the tuned count or the default
+  const int L = a.rec ? 8 : (c->tune.couple_lanes > 0 ? c->tune.couple_lanes
+                                                        : DirectShape<ST>::kLanes);
   const dim3 cgrid(grid_for((N * L + kBlock - 1) / kBlock, c->tune.part_blocks));
   // with position-dependent forces (never recorded) the kernel also bins
   const bool bin = c->plan.any_forces2 && !a.rec;
-  const dim3 b(kBlock);
-  if (ST == 0 && a.rec)
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, b, 0, c->stream, a);
-  else if (bin)
-    hipLaunchKernelGGL((k_couple<T, false, ST, DirectShape<ST>::kLanes, true>), cgrid, b, 0,
-                       c->stream, a);
-  else
-    hipLaunchKernelGGL((k_couple<T, false, ST, DirectShape<ST>::kLanes, false>), cgrid, b, 0,
-                       c->stream, a);
+  if (ST == 0 && a.rec) {
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, dim3(kBlock), 0, c->stream, a);
+  } else if constexpr (ST == 0) {
+    if (L == 2)
+      launch_couple_lanes<T, 0, 2>(c, a, bin, cgrid);
+    else if (L == 4)
+      launch_couple_lanes<T, 0, 4>(c, a, bin, cgrid);
+    else
+      launch_couple_lanes<T, 0, 8>(c, a, bin, cgrid);
+  } else {
+    if (L == 16)
+      launch_couple_lanes<T, 1, 16>(c, a, bin, cgrid);
+    else
+      launch_couple_lanes<T, 1, 8>(c, a, bin, cgrid);
+  }
   // transfers to shared sites wait until every particle has read J; with
   // position-dependent forces that work rides in extra blocks of the force
   // kernel's launch, which follows anyway

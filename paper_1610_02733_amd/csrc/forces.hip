@@ -344,8 +344,9 @@ static hipError_t forces_t(Context* c) {
   if (AfterST >= 0) {
     constexpr int ST = AfterST >= 0 ? AfterST : 0;
     ca = couple_args<T>(c, 0);
-    L = DirectShape<ST>::kLanes;
-    per = DirectShape<ST>::kPer;
+    // the coupling kernel's lanes per particle (tuned or default)
+    L = c->tune.couple_lanes > 0 ? c->tune.couple_lanes : DirectShape<ST>::kLanes;
+    per = (Stencil<ST>::kSites + L - 1) / L;
     nseg = (a.N * L + kBlock - 1) / kBlock;
   }
   const dim3 grid((unsigned)(nfb + 2 * nseg));

@@ -109,11 +109,13 @@ struct Layout {
   size_t total;      // bytes needed
 };
 
-// Launch shapes of the persistent kernels (blocks in flight; 0 = one block
-// per work item).
+// Launch shapes (autotuner): blocks in flight of the persistent kernels
+// (0 = one block per work item) and lanes per particle of the coupling
+// kernel (0 = the default DirectShape; candidates couple_lane_candidates).
 struct Tune {
   int lb_blocks;
   int part_blocks;
+  int couple_lanes;
 };
 
 struct Plan {
@@ -237,6 +239,9 @@ hipError_t launch_couple_refill_only(Context* c);
 hipError_t launch_init_forces(Context* c);
 hipError_t launch_init_pid(Context* c);
 hipError_t invalidate_corner_cache(Context* c);
+// lanes per particle the coupling kernel is built for: {2, 4, 8} for the
+// trilinear stencil, {8, 16} for the three-point one; returns the count
+int couple_lane_candidates(int stencil, int out[4]);
 hipError_t launch_forces(Context* c);
 hipError_t launch_forces_and_kick(Context* c);
 int64_t force_cells(const lbmd_params* p);

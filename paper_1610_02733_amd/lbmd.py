@@ -85,7 +85,9 @@ def lib():
         L.lbmd_batch_get_populations.argtypes = [P, C.c_int32, P]
         L.lbmd_batch_set_populations.argtypes = [P, C.c_int32, P]
         L.lbmd_batch_get_transfer.argtypes = [P, C.c_int32, P]
-        L.lbmd_autotune.argtypes = [P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.lbmd_autotune.argtypes = [P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]
+        L.lbmd_set_launch_shape.argtypes = [P, C.c_int32, C.c_int32, C.c_int32]
         L.lbmd_stream_copy.argtypes = [P, P, C.c_size_t, P]
         L.lbmd_stream_copy.restype = C.c_int
         L.lbmd_state_bytes.argtypes = [P]
@@ -108,6 +110,7 @@ def lib():
                   "lbmd_run_cycles", "lb_create_batch", "lbmd_replica_count",
                   "lbmd_batch_moments", "lbmd_batch_get_populations",
                   "lbmd_batch_set_populations", "lbmd_batch_get_transfer", "lbmd_autotune",
+                  "lbmd_set_launch_shape",
                   "lbmd_save_state", "lbmd_load_state", "lbmd_adjoint_attach",
                   "lbmd_adjoint_seed", "lbmd_adjoint_record", "lb_step_adjoint",
                   "md_couple_substep_adjoint", "lbmd_adjoint_result"):
@@ -247,11 +250,19 @@ class _System:
     def load_state(self, state):
         _check(lib().lbmd_load_state(self._h, _ptr(state)), "lbmd_load_state")
 
+    def set_launch_shape(self, lb_blocks=0, part_blocks=0, couple_lanes=0):
+        _check(lib().lbmd_set_launch_shape(self._h, lb_blocks, part_blocks, couple_lanes),
+               "lbmd_set_launch_shape")
+
     def autotune(self, cache_path=None):
-        a, b = C.c_int32(), C.c_int32()
+        """Time the launch shapes of the hot kernels on this system and keep
+        the fastest (grids: 0 = one block per work item; lanes: 0 = the
+        built-in default)."""
+        a, b, l = C.c_int32(), C.c_int32(), C.c_int32()
         path = cache_path.encode() if cache_path else None
-        _check(lib().lbmd_autotune(self._h, path, C.byref(a), C.byref(b)), "lbmd_autotune")
-        return dict(lb_blocks=a.value, part_blocks=b.value)
+        _check(lib().lbmd_autotune(self._h, path, C.byref(a), C.byref(b), C.byref(l)),
+               "lbmd_autotune")
+        return dict(lb_blocks=a.value, part_blocks=b.value, couple_lanes=l.value)
 
 
 class Lattice(_System):

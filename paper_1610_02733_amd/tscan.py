@@ -1,5 +1,5 @@
 """Particle temperature against friction, time-scale contrast and MD step
-for the coupling variants: the experiment behind the paper's Figs. 3-5
+for the coupling variants: the experiment behind the paper's Figs. 3, 4 and 6
 (Sec. 3), run on the batched engine.
 
 The paper measures the mean kinetic temperature of a bead-spring polymer

@@ -93,19 +93,30 @@ def drift(x, x0):
     return (x - x0)[0].mean()
 
 
+def msd(x, x0):
+    d = x - x0
+    return (d * d).sum(0).mean()
+
+
+OBSERVABLES = (("drift", drift), ("msd", msd))
+
+
 def c5_directions(lb, kT):
-    """Adjoint drift gradients on the 64^3 case and a loss function for
+    """Adjoint gradients of the drift and of the mean-square displacement on
+    the 64^3 case, and the two observables of a perturbed forward run for
     central differences along the same directions (FP64, same noise)."""
     from paper_1610_02733_amd.adjoint import coupled_run
     shape, x0, v0, cfg, kw = c5_setup(64)
     kw["kT"] = kT
     gamma, nu, fext = cfg["friction"], cfg["nu"], list(cfg["f_ext"])
     cycles = cfg["lb_steps"]
-    leaves, x, v = run_gpu(shape, x0, v0, gamma, nu, fext, cycles, 10, **kw)
     x0c = torch.tensor(x0, dtype=torch.float64, device="cuda")
-    drift(x, x0c).backward()
-    g_gamma, g_nu = leaves[0].grad.item(), leaves[1].grad.item()
-    g_f, g_v0 = leaves[2].grad.cpu().numpy(), leaves[4].grad.cpu().numpy()
+    grads = {}
+    for oname, obs in OBSERVABLES:
+        leaves, x, v = run_gpu(shape, x0, v0, gamma, nu, fext, cycles, 10, **kw)
+        obs(x, x0c).backward()
+        grads[oname] = (leaves[0].grad.item(), leaves[1].grad.item(),
+                        leaves[2].grad.cpu().numpy(), leaves[4].grad.cpu().numpy())
 
     def L(dgamma=0.0, dnu=0.0, df=(0.0, 0.0, 0.0), dv0=0.0):
         with torch.no_grad():
@@ -113,77 +124,99 @@ def c5_directions(lb, kT):
                                 torch.tensor(np.add(fext, df), dtype=torch.float64, device="cuda"),
                                 x0c, torch.tensor(v0 + dv0, dtype=torch.float64, device="cuda"),
                                 shape=shape, cycles=cycles, checkpoint=10, **kw)
-            return drift(xx, x0c).item()
+            return {oname: obs(xx, x0c).item() for oname, obs in OBSERVABLES}
 
-    dirs = [("gamma", g_gamma, lambda h: L(dgamma=h)), ("nu", g_nu, lambda h: L(dnu=h))]
+    dirs = []  # (name, {observable: adjoint gradient along it}, L along it)
+    dirs.append(("gamma", {o: g[0] for o, g in grads.items()}, lambda h: L(dgamma=h)))
+    dirs.append(("nu", {o: g[1] for o, g in grads.items()}, lambda h: L(dnu=h)))
     for d in range(3):
         e = np.eye(3)[d]
-        dirs.append((f"f{d}", g_f[d], lambda h, e=e: L(df=h * e)))
+        dirs.append((f"f{d}", {o: g[2][d] for o, g in grads.items()},
+                     lambda h, e=e: L(df=h * e)))
     rng = np.random.default_rng(55)
     for q in range(10):  # 10 random components of v0 and one random direction
         d, p = int(rng.integers(0, 3)), int(rng.integers(0, x0.shape[1]))
         e = np.zeros_like(v0)
         e[d, p] = 1.0
-        dirs.append((f"v0[{d},{p}]", g_v0[d, p], lambda h, e=e: L(dv0=h * e)))
+        dirs.append((f"v0[{d},{p}]", {o: g[3][d, p] for o, g in grads.items()},
+                     lambda h, e=e: L(dv0=h * e)))
     u = rng.standard_normal(v0.shape)
     u /= np.linalg.norm(u)
-    dirs.append(("v0.u", float((g_v0 * u).sum()), lambda h, u=u: L(dv0=h * u)))
+    dirs.append(("v0.u", {o: float((g[3] * u).sum()) for o, g in grads.items()},
+                 lambda h, u=u: L(dv0=h * u)))
     return dirs
 
 
-def central(Lh, h):
-    return (Lh(h) - Lh(-h)) / (2 * h)
+LADDER = [1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8]
 
 
 @pytest.mark.parametrize("kT", [0.0, 1e-4])
 def test_c5_adjoint_matches_central_differences(lb, kT):
     """64^3, 1000 particles under f = 1e-3 x, n = 5, 50 LB steps, checkpoints
-    every 10, FP64, along gamma, nu, f (3 components), 10 random components
-    of v0 and one random direction.
+    every 10, FP64; gradients of the mean x-displacement (drift) and of the
+    mean-square displacement along gamma, nu, f (3 components), 10 random
+    components of v0 and one random direction.
 
-    The drift is only piecewise smooth in every parameter: the trilinear
-    weights change slope where a particle crosses a lattice plane, and a
-    perturbed run whose trajectories cross such a kink differs from the
-    linearisation at first order in h.  Central differences are therefore
-    taken on a ladder of steps starting at h = 1e-4; a step counts once
-    dividing it by ten changes the estimate by less than 1e-6 of the
-    gradient's scale (no kink inside the stencil: crossing one shifts the
-    estimate far more).
-    The error bound is 1e-6 relative per gradient: for gamma and nu, for the
-    3-vector f and for the sampled v0 gradient, the largest deviation over
-    the group's components against the group's largest component.  Without
-    noise the along-force directions (gamma, nu, f_x) resolve at h = 1e-4
-    itself."""
+    Both observables are only piecewise smooth in every parameter: the
+    trilinear weights change slope where a particle crosses a lattice plane,
+    and a perturbed run whose trajectories cross such a kink differs from
+    the linearisation at first order in h.  Central differences are
+    therefore taken on a ladder of steps from h = 1e-4 down to 1e-8; a step
+    counts once the next smaller one changes the estimate by less than 1e-6
+    of the gradient's scale (no kink inside the stencil: crossing one shifts
+    the estimate far more).  A direction whose ladder never settles fails
+    the test.  The error bound is 1e-6 relative per gradient: for gamma and
+    nu, for the 3-vector f and for the sampled v0 gradient, the largest
+    deviation over the group's components against the group's largest
+    component.  Without noise the along-force directions (gamma, nu, f_x)
+    of the drift resolve at h = 1e-4 itself.
+
+    The one exception, stated: the mean-square displacement with noise.  Its
+    derivative weighs each particle's perturbation by its whole thermal
+    displacement, so the kinks the 1000 noisy trajectories cross keep the
+    central differences off by up to 5e-5 of the group scale along the
+    force (measured: gamma 2.5e-6, nu 8.5e-6, f 4.7e-5, v0 < 1e-7), while
+    the same directions agree to < 1e-6 without noise and for the drift with
+    noise; the adjoint itself equals autograd through the FP64 reference to
+    1e-10 with noise (test_adjoint_matches_oracle_autograd).  There the ladder
+    must settle to 1e-4 and the adjoint agree to 1e-4."""
     dirs = c5_directions(lb, kT)
-    ladder = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9]
-    groups = {}
-    gscale = {}  # scale of each gradient, from the adjoint
-    for name, ad, _ in dirs:
-        group = name[0] if name[0] in "fv" else name
-        gscale[group] = max(gscale.get(group, 0.0), abs(ad))
-    for name, ad, Lh in dirs:
-        group = name[0] if name[0] in "fv" else name
-        prev = central(Lh, ladder[0])
-        used = None
-        for h in ladder[1:]:
-            cur = central(Lh, h)
-            if abs(cur - prev) <= 1e-6 * max(abs(cur), gscale[group]):
-                used = (h * 10, prev)
-                break
-            prev = cur
-        if used is None:  # a tiny component: the last, smallest-step estimate
-            used = (ladder[-1], prev)
-        h, f = used
-        print(f"kT={kT:g} {name}: adjoint {ad:.10e} fd {f:.10e} (h = {h:g})")
-        groups.setdefault(group, []).append((name, ad, f, h))
-        if kT == 0.0 and name in ("gamma", "nu", "f0"):
-            assert h == 1e-4, (name, h)
-    # relative error of each gradient (scalar, 3-vector f, sampled v0)
-    for group, rows in groups.items():
-        scale = max(abs(r[2]) for r in rows)
-        err = max(abs(r[1] - r[2]) for r in rows)
-        print(f"kT={kT:g} group {group}: max |adjoint - fd| / max |fd| = {err / scale:.2e}")
-        assert err <= 1e-6 * scale, (group, rows)
+    for oname, _ in OBSERVABLES:
+        tol = 1e-4 if (oname == "msd" and kT > 0.0) else 1e-6
+        groups, gscale = {}, {}
+        for name, ad, _ in dirs:  # scale of each gradient, from the adjoint
+            group = name[0] if name[0] in "fv" else name
+            gscale[group] = max(gscale.get(group, 0.0), abs(ad[oname]))
+        cache = {}
+        for name, ad, Lh in dirs:
+            group = name[0] if name[0] in "fv" else name
+
+            def fd(h, Lh=Lh, name=name):
+                if (name, h) not in cache:
+                    cache[(name, h)] = (Lh(h), Lh(-h))
+                lp, lm = cache[(name, h)]
+                return (lp[oname] - lm[oname]) / (2 * h)
+
+            prev, used = fd(LADDER[0]), None
+            for hp, h in zip(LADDER[:-1], LADDER[1:]):
+                cur = fd(h)
+                if abs(cur - prev) <= tol * max(abs(cur), gscale[group]):
+                    used = (hp, prev)
+                    break
+                prev = cur
+            assert used is not None, (oname, name, "finite differences did not settle",
+                                      [fd(h) for h in LADDER], ad[oname])
+            h, f = used
+            print(f"kT={kT:g} {oname} {name}: adjoint {ad[oname]:.10e} fd {f:.10e} (h = {h:g})")
+            groups.setdefault(group, []).append((name, ad[oname], f, h))
+            if kT == 0.0 and oname == "drift" and name in ("gamma", "nu", "f0"):
+                assert h == 1e-4, (name, h)
+        for group, rows in groups.items():
+            scale = max(abs(r[2]) for r in rows)
+            err = max(abs(r[1] - r[2]) for r in rows)
+            print(f"kT={kT:g} {oname} group {group}: max |adjoint - fd| / max |fd| = "
+                  f"{err / scale:.2e}")
+            assert err <= tol * scale, (oname, group, rows)
 
 
 def test_c5_fp32_adjoint_error_vs_fp64(lb):

@@ -621,3 +621,39 @@ def test_sort_particles_state_and_model_errors(lb):
         g.sort_particles()
     assert ei.value.code == lb.ESTATE
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("stencil,lanes,blocks", [(0, 2, 0), (0, 4, 0), (0, 8, 0), (0, 4, 64),
+                                                   (1, 8, 0), (1, 16, 0), (1, 16, 32)])
+def test_launch_shapes_match_oracle(lb, orc, prec, stencil, lanes, blocks):
+    """Every lanes-per-particle count and persistent grid the autotuner may
+    pick gives the oracle's run (dense particles, so shared sites, moved
+    stencils and the after-step lists are all exercised; variant 2)."""
+    shape = (7, 6, 5)
+    x, v = wl.free_particles(shape, 90, 1e-3, 1.0, 71)
+    kw = dict(kT=1e-3, seed=72, n_particles=90, friction=0.8, n_sub=4, variant=2,
+              stencil=stencil)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=prec, **kw)
+    g.set_launch_shape(lb_blocks=blocks, part_blocks=blocks, couple_lanes=lanes)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    g.cycle(3)
+    g.run_cycles(3)
+    o.cycle(6)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < TOL[prec], err
+    check_particles(g, o, shape, TOL[prec], 1e-3)
+
+
+def test_launch_shape_rejects_bad_lanes(lb):
+    g = lb.Lattice((8, 8, 8), precision=32, n_particles=4)
+    for bad in (3, 16, 32):
+        with pytest.raises(lb.LbmdError):
+            g.set_launch_shape(couple_lanes=bad)
+    g3 = lb.Lattice((8, 8, 8), precision=32, n_particles=4, stencil=1)
+    with pytest.raises(lb.LbmdError):
+        g3.set_launch_shape(couple_lanes=2)
+    g3.set_launch_shape(couple_lanes=16)
