@@ -12,7 +12,8 @@ not reproducible, so these stand in for it):
 * ``c1``: 16^3, FP64, 32 free particles, n = 5, 100 LB steps (parity case).
 * ``c2``: 128^3, FP32, 200 chains x 50 beads, harmonic bonds + WCA, n = 10.
 * ``c2p``: the same shapes at stable dimensionless parameters (companion of c2).
-* ``c3``: 256^3, FP32, 1e5 free particles, n = 10 (bandwidth-roofline case).
+* ``c3``: 256^3, FP32, 1e5 free particles at least 2 sites apart, n = 10
+  (bandwidth-roofline case).
 * ``c4``: 512 replicas, edges in {24,32,40,48}, 20..400 particles each.
 * ``c5``: 64^3, 1000 particles under a constant force, n = 5 (adjoint case).
 """
@@ -45,9 +46,13 @@ CONFIGS = {
                  kT=0.01, n_particles=10_000, chain_len=50, particle_mass=1.0, friction=2.0,
                  n_sub=10, lb_steps=1000, seed=2, precision=32, variant=2, force_model=3,
                  k_bond=0.3, r0_bond=1.5, wca_eps=0.01, wca_sigma=1.0, min_dist=0.9),
+    # gamma tau_MD / m = 1: two particles near one site exceed the explicit
+    # step's stability bound in variant B, and a uniform draw holds ~280
+    # same-cube pairs, so the particles are placed at least 2 sites apart
+    # (with kT / gamma = 1e-5 they diffuse ~0.1 site in 1000 LB steps)
     "c3": dict(shape=(256, 256, 256), rho0=1.0, nu=NU_1_6, nu_bulk=-1.0, gamma_ghost=0.0,
                kT=1e-4, n_particles=100_000, particle_mass=1.0, friction=10.0, n_sub=10,
-               lb_steps=200, seed=3, precision=32),
+               lb_steps=200, seed=3, precision=32, min_dist=2.0),
     "c5": dict(shape=(64, 64, 64), rho0=1.0, nu=NU_1_6, nu_bulk=-1.0, gamma_ghost=0.0,
                kT=1e-4, n_particles=1000, particle_mass=1.0, friction=5.0, n_sub=5,
                lb_steps=50, seed=5, precision=32, force_model=1, f_ext=(1e-3, 0.0, 0.0)),
@@ -64,6 +69,44 @@ def free_particles(shape, n, kT, mass, seed):
     x = np.minimum(x, np.nextafter(L, 0))  # keep strictly inside [0, L)
     v = rng.normal(0.0, np.sqrt(kT / mass) if kT > 0 else 0.0, (3, n))
     return x, v
+
+
+def separated_particles(shape, n, kT, mass, seed, min_dist):
+    """Homogeneous random positions with no two particles closer than min_dist
+    (periodic minimum image): uniform positions, then, until no pair is too
+    close, the higher-indexed particle of every close pair is drawn again
+    uniformly; Maxwell velocities N(0, kT/m).
+
+    Returns x[3,N], v[3,N] as float64 arrays."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    Ls = np.asarray(shape, np.float64)
+    x = rng.random((n, 3)) * Ls
+    x = np.minimum(x, np.nextafter(Ls, 0))
+    for _ in range(1000):
+        pairs = cKDTree(x, boxsize=Ls).query_pairs(min_dist, output_type="ndarray")
+        if len(pairs) == 0:
+            break
+        redo = np.unique(pairs.max(1))
+        x[redo] = np.minimum(rng.random((len(redo), 3)) * Ls, np.nextafter(Ls, 0))
+    else:
+        raise RuntimeError("could not separate the particles")
+    v = rng.normal(0.0, np.sqrt(kT / mass) if kT > 0 else 0.0, (3, n))
+    return np.ascontiguousarray(x.T), v
+
+
+def workload_particles(cfg):
+    """The particles of a named configuration: bead-spring chains when it has
+    chains, separated free particles when it sets min_dist, else uniform free
+    particles."""
+    shape = cfg["shape"]
+    if cfg.get("chain_len", 0) > 1 and cfg.get("force_model", 0) >= 2:
+        return chains(shape, cfg["n_particles"] // cfg["chain_len"], cfg["chain_len"], cfg["kT"],
+                      cfg["particle_mass"], cfg["seed"], min_dist=cfg.get("min_dist", 0.0))
+    if cfg.get("min_dist", 0.0) > 0.0:
+        return separated_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
+                                   cfg["seed"], cfg["min_dist"])
+    return free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"], cfg["seed"])
 
 
 def chains(shape, n_chains, chain_len, kT, mass, seed, bond=1.0, min_dist=0.0):

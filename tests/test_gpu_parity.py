@@ -357,14 +357,14 @@ def test_fast_particles_wrap(lb, orc):
 
 @pytest.mark.parametrize("prec,variant", [(32, 2), (64, 2), (32, 3)])
 def test_full_size_sampled_parity(lb, orc, prec, variant):
-    """The 256^3 workload as bench.py times it (1e5 free particles, n = 10,
+    """The 256^3 workload as bench.py times it (1e5 free particles at least 2
+    sites apart, n = 10,
     gamma = 10, kT = 1e-4, variant 2 (and 3), default launch shapes): one
     coupled cycle from the seeded start, every particle and 2048 random sites
     against the FP64 oracle (which evaluates the sampled sites one by one)."""
     cfg = wl.CONFIGS["c3"]
     shape = cfg["shape"]
-    x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
-                             cfg["seed"])
+    x, v = wl.workload_particles(cfg)
     kw = dict(n_sub=cfg["n_sub"], variant=variant, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
               friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
               particle_mass=cfg["particle_mass"])
@@ -396,8 +396,7 @@ def test_full_size_sampled_parity_bench_launch(lb, orc):
     slots, so slot t is compared with the oracle's particle perm[t]."""
     cfg = wl.CONFIGS["c3"]
     shape = cfg["shape"]
-    x, v = wl.free_particles(shape, cfg["n_particles"], cfg["kT"], cfg["particle_mass"],
-                             cfg["seed"])
+    x, v = wl.workload_particles(cfg)
     kw = dict(n_sub=cfg["n_sub"], variant=2, kT=cfg["kT"], nu=cfg["nu"], rho0=cfg["rho0"],
               friction=cfg["friction"], n_particles=cfg["n_particles"], seed=cfg["seed"],
               particle_mass=cfg["particle_mass"])
