@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
     qz = quad_sum(qz);
     const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
     a.cc[(size_t)p * 32 + sl] = mine;
-    if (c == 0) claim_site(a, m.site_off + site, p, stencil_fits<0>(m.g));
+    if (c == 0) claim_site(a, m.site_off + site);
   }
 }
 
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     T drho, jx, jy, jz;
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-    claim_site(a, m.site_off + site, p, stencil_fits<1>(m.g));
+    claim_site(a, m.site_off + site);
   }
 }
 
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         // fluid velocity at the particle (Eq. 5)
         double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
         jv_[jj] = a.J[gs];
-        sh_[jj] = owner_of(jv_[jj]) != owner_id<T>(p);  // not claimed by p alone
+        sh_[jj] = jv_[jj].w != T(0);  // shared-site flag (claim_site)
         if (a.variant >= 2) {  // the fluid velocity includes the pending transfer
           jx += (double)jv_[jj].x;
           jy += (double)jv_[jj].y;

@@ -53,65 +53,19 @@ __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t 
   return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
 }
 
-// Claims.  The w word of a site's transfer entry, read as an unsigned
-// integer of the entry's width, records who claimed the site in the current
-// LB interval: 0 nobody, p + 1 particle slot p alone, all ones (kShared) more
-// than one particle.  A claim also sets the site's bit in the mark bitmap
-// (the LB step reads J only at marked sites and clears the entry, w
-// included).  A particle re-claiming a site it claimed alone (it left the
-// stencil and came back, or the cache was refilled) keeps it unshared.  In a
-// replica narrower than the stencil, two sites of one stencil can be the
-// same site: there any second claim marks the site shared.  The coupling
-// kernel reads the owner together with the transfer (same 16 or 32 bytes)
-// and writes the transfer with a plain store where it is the owner.  Claims
-// run only in the refill and in the after-step work, never while a coupling
-// kernel reads or writes J; the after-step atomics touch only the x, y, z
-// words.
+// Mark a site as a receiver of momentum transfer in this LB interval; a site
+// claimed again (by another particle, or by one that changed stencils) is
+// flagged as shared in the w word of its transfer entry, which the coupling
+// kernel reads together with the transfer itself.  The flag is written only
+// by claims (refill, after-step work: never while a coupling kernel runs) and
+// cleared with the entry by the LB step; the after-step atomics touch only
+// the x, y, z words.  (Recording the claiming particle instead, so that a
+// particle re-claiming its own sites keeps them unshared, measured slower:
+// the refill's extra compare-and-swap per site cost more than it saved.)
 template <typename T>
-struct OwnerWord;
-template <>
-struct OwnerWord<float> {
-  using W = unsigned int;
-};
-template <>
-struct OwnerWord<double> {
-  using W = unsigned long long;
-};
-
-template <typename T>
-__device__ __forceinline__ typename OwnerWord<T>::W owner_of(const Vec4<T>& jv) {
-  typename OwnerWord<T>::W w;
-  __builtin_memcpy(&w, &jv.w, sizeof(w));
-  return w;
-}
-
-template <typename T>
-__device__ __forceinline__ typename OwnerWord<T>::W owner_id(int64_t p) {
-  return (typename OwnerWord<T>::W)(p + 1);
-}
-
-template <typename T>
-constexpr typename OwnerWord<T>::W kShared = ~(typename OwnerWord<T>::W)0;
-
-// A stencil of ST fits without repeated sites in a replica whose edges are
-// all at least its width.
-template <int ST>
-__device__ __forceinline__ bool stencil_fits(const Geom& g) {
-  const int wdt = ST == 0 ? 2 : 3;
-  return g.nx >= wdt && g.ny >= wdt && g.nz >= wdt;
-}
-
-// Claim global site gs for particle slot p; returns the previous owner word.
-template <typename T>
-__device__ __forceinline__ typename OwnerWord<T>::W claim_site(const CoupleArgs<T>& a, int gs,
-                                                               int64_t p, bool fits) {
-  using W = typename OwnerWord<T>::W;
-  atomicOr(a.mark + (gs >> 6), 1ull << (gs & 63));
-  W* w = reinterpret_cast<W*>(a.J + gs) + 3;
-  const W id = owner_id<T>(p);
-  const W old = atomicCAS(w, (W)0, id);
-  if (old != 0 && old != kShared<T> && (old != id || !fits)) *w = kShared<T>;
-  return old;
+__device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
+  const unsigned long long bit = 1ull << (gs & 63);
+  if (atomicOr(a.mark + (gs >> 6), bit) & bit) reinterpret_cast<T*>(a.J + gs)[3] = T(1);
 }
 
 // (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
@@ -234,7 +188,7 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
       St::site(q, m.g, k, cx, cy, cz, site, w);
       *cache_entry<ST>(a, p, k) =
           gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
-      claim_site(a, m.site_off + site, p, stencil_fits<ST>(m.g));
+      claim_site(a, m.site_off + site);
     }
   } else {
     const int64_t seg = it - nseg;

@@ -74,8 +74,8 @@ struct Layout {
   size_t pop[2];     // [19 * Stot] population deviations, pull storage, per replica
                      // z-plane interleaved (pop_offset in lbmd_device.hpp)
   size_t transfer;   // [Stot] Vec4<T>: pending momentum transfer J (x, y, z) and, in w,
-                     // the site's claimant in the current LB interval (0 none, slot + 1
-                     // of a single claiming particle, all ones: shared; claim_site)
+                     // a flag set when the site is claimed more than once in the
+                     // current LB interval (shared site; claim_site)
   size_t mark;       // [Stot/64] uint64: bit set <=> J may be non-zero at the site
   size_t rep_lb;     // [R] RepLB<T>
   size_t rep_md;     // [R] RepMD
