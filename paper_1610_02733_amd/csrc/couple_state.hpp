@@ -114,7 +114,10 @@ struct DirectShape {
 // hash table (LDS atomics), then each distinct site receives one device
 // atomic per component instead of one per entry.  Pays where stencils
 // overlap densely (the 27 sites of the three-point kernel).
-constexpr int kSiteTable = 2048;  // >= 2 x the entries of a segment (kBlock * 4)
+// The table holds up to kSiteTable / 2 entries at a time (a longer list is
+// taken in chunks); its 16 bytes per slot are dynamic LDS of every block of
+// the after-step launch, so its size bounds the blocks resident per CU.
+constexpr int kSiteTable = 512;
 
 template <typename T>
 struct SiteTable {
@@ -123,8 +126,8 @@ struct SiteTable {
 };
 
 template <typename T>
-__device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a, int64_t base,
-                                                         int n, SiteTable<T> tab) {
+__device__ __forceinline__ void reduce_chunk(const CoupleArgs<T>& a, int64_t base, int n,
+                                             SiteTable<T> tab) {
   // table size: the smallest power of two >= 2 n (block-uniform)
   int H = 64, lg = 6;
   while (H < 2 * n) {
@@ -158,6 +161,13 @@ __device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a,
     if (site >= 0) atomicAdd(reinterpret_cast<T*>(a.J + site) + comp, tab.val[comp * kSiteTable + h]);
   }
   __syncthreads();  // the block's next item reuses the table
+}
+
+template <typename T>
+__device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a, int64_t base,
+                                                         int n, SiteTable<T> tab) {
+  for (int c0 = 0; c0 < n; c0 += kSiteTable / 2)
+    reduce_chunk(a, base + c0, n - c0 < kSiteTable / 2 ? n - c0 : kSiteTable / 2, tab);
 }
 
 template <typename T, int ST>
