@@ -389,6 +389,28 @@ def test_full_size_sampled_parity(lb, orc, prec, variant):
     o.close()
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_full_size_workload_stays_finite(lb, variant):
+    """The 256^3 workload as bench.py times it (FP32, sorted, captured
+    cycles) stays finite over 30 coupled cycles in every variant, with the
+    particle temperature T_p (returned by the library) at kT within 5%: the
+    placement at least 2 sites apart keeps every particle inside the explicit
+    step's stability bound (gamma tau_MD / m = 1)."""
+    cfg = wl.CONFIGS["c3"]
+    x, v = wl.workload_particles(cfg)
+    g = lb.Lattice(cfg["shape"], precision=32, n_sub=cfg["n_sub"], variant=variant, kT=cfg["kT"],
+                   nu=cfg["nu"], friction=cfg["friction"], n_particles=cfg["n_particles"],
+                   seed=cfg["seed"], particle_mass=cfg["particle_mass"])
+    g.bind_particles(x, v)
+    g.sort_particles()
+    g.run_cycles(30)
+    tot = g.moments()  # raises on a non-finite particle
+    T = tot[lb.TOT["tpart"]] / cfg["kT"]
+    print(f"256^3 variant {variant}: T_p/kT after 30 cycles {T:.4f}")
+    assert abs(T - 1.0) < 0.05
+    g.close()
+
+
 def test_full_size_sampled_parity_bench_launch(lb, orc):
     """The same 256^3 workload in bench.py's own launch configuration: FP32,
     variant 2, particles sorted after binding, and the cycle replayed from a
