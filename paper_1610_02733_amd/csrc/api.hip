@@ -115,6 +115,9 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.sort_img = o; o = up(o + 3 * N * 4);
   L.fc_held = o; o = up(o + 3 * N * 8);
   L.cc = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);  // site cache
+  L.own = o; o = up(o + (p[0].stencil == 1 ? 4 * 27 : 4 * 8) * N * t);
+  L.owner = o; o = up(o + S * 4);
+  L.moved_at = o; o = up(o + N * 8);
   // transfer lists: per segment of kBlock coupling lanes, kBlock * (sites
   // per lane) transfer entries and kBlock / lanes particles; lanes x sites
   // per lane is 8 for the cube (8 x 1 while recording, 2 x 4) and 32 for the
@@ -124,7 +127,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   const size_t nent = (size_t)pl.nseg * kBlock;  // >= every launch's lanes x sites per lane
   L.slist_site = o; o = up(o + nent * 4);
   L.slist_delta = o; o = up(o + nent * 4 * t);
-  L.mlist = o; o = up(o + nent * 4);
+  L.mlist = o; o = up(o + nent * 8);  // kBlock / lanes int4 per segment, lanes >= 2
   L.seg_count = o; o = up(o + 2 * (size_t)pl.nseg * 4);
   L.bin_count = o; o = up(o + C * 4);
   L.bin_start = o; o = up(o + (C + 1) * 4);
@@ -294,6 +297,19 @@ void drop_graph(lbmd* c) {
   c->graph_def = nullptr;
 }
 
+// No particle has changed stencils at the current MD step count and no
+// stencil records a particle (owner_of_shared): at creation, at a new
+// binding, and where the step counters or the particles are set from
+// outside.  The next MD step refills the cache, which records every
+// particle's stencil again.
+hipError_t reset_stencil_records(Context* c) {
+  hipError_t e = hipMemsetAsync(at(c, c->plan.lay.owner), 0xFF, (size_t)c->plan.Stot * 4,
+                                c->stream);
+  if (e == hipSuccess && c->plan.Ntot > 0)
+    e = hipMemsetAsync(at(c, c->plan.lay.moved_at), 0xFF, (size_t)c->plan.Ntot * 8, c->stream);
+  return e;
+}
+
 int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* hip_stream,
            lbmd** out) {
   if (!out) return LBMD_EINVAL;
@@ -311,6 +327,7 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->img = nullptr;
   c->bound = false;
   c->cache_dirty = true;
+  c->retag = false;
   c->t_lb = c->t_md = 0;
   c->subs = 0;
   c->cur = 0;
@@ -327,6 +344,7 @@ int create(const lbmd_params* p, int32_t R, void* d_ws, size_t ws_bytes, void* h
   c->scratch_rows = nullptr;
   // fluid at rest (all deviations zero), nothing transferred yet
   hipError_t e = hipMemsetAsync(c->ws, 0, pl.lay.total, c->stream);
+  if (e == hipSuccess) e = reset_stencil_records(c);
   if (e == hipSuccess) e = upload_tables(c);
   // set-up of lb_moments_noalloc: this GPU's address of the library's fixed
   // reduction array (looked up once per device)
@@ -347,7 +365,7 @@ int check_rep(lbmd* c, int32_t rep) {
 // One MD step of every replica (no host-side checks).
 hipError_t substep_launches(Context* c, int substep) {
   hipError_t e = launch_couple(c, substep);
-  if (e == hipSuccess && c->plan.any_forces2) e = launch_forces_and_kick(c);
+  if (e == hipSuccess && c->plan.any_forces2) e = launch_forces_and_kick(c, substep);
   return e;
 }
 
@@ -388,12 +406,16 @@ int lbmd_bind_particles(lbmd* c, void* d_x, void* d_v, int32_t* d_img) {
   if (!c) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
   if (c->plan.Ntot > 0 && (!d_x || !d_v || !d_img)) return LBMD_EINVAL;
+  // the pending transfer is kept: the bound particles' own transfers go to J
+  int rc0 = fail(c, launch_leave_transfers(c));
+  if (rc0) return rc0;
   c->x = d_x;
   c->v = d_v;
   c->img = d_img;
   c->bound = c->plan.Ntot > 0;
   drop_graph(c);
   int rc = fail(c, launch_init_pid(c));
+  if (!rc) rc = fail(c, reset_stencil_records(c));
   if (rc) return rc;
   return fail(c, launch_init_forces(c));
 }
@@ -507,7 +529,8 @@ static int moments_common(lbmd* c, int32_t rep, void* d_rho, void* d_u, double* 
   if (rc) return rc;
   const int R = c->plan.R;
   double* d_tot = h_totals ? (double*)at(c, c->plan.lay.totals) : nullptr;
-  rc = fail(c, launch_moments(c, rep, d_rho, d_u, d_tot));
+  rc = fail(c, launch_leave_transfers(c));
+  if (!rc) rc = fail(c, launch_moments(c, rep, d_rho, d_u, d_tot));
   if (rc || !h_totals) return rc;
   std::vector<double> tot((size_t)R * kRedWidth);
   int32_t flags[16];
@@ -537,7 +560,8 @@ int lb_moments_noalloc(lbmd* c, void* d_rho, void* d_u, double* h_totals) {
   // row; the grid is capped at the array's row count, so any lattice fits
   const int64_t rows = std::min<int64_t>(c->plan.nitems, kScratchRows) + 1;
   if (rows * kRedWidth > kScratchDoubles) return LBMD_ENOSPACE;
-  int rc = fail(c, launch_moments_rows(c, d_rho, d_u, c->scratch_rows));
+  int rc = fail(c, launch_leave_transfers(c));
+  if (!rc) rc = fail(c, launch_moments_rows(c, d_rho, d_u, c->scratch_rows));
   if (rc || !h_totals) return rc;
   double tot[kRedWidth];
   int32_t flags[16];
@@ -560,13 +584,18 @@ int lbmd_batch_moments(lbmd* c, double* h_totals) {
 int lbmd_batch_get_populations(lbmd* c, int32_t rep, void* d_dst) {
   int rc = check_rep(c, rep);
   if (rc || !d_dst) return rc ? rc : LBMD_EINVAL;
+  rc = fail(c, launch_leave_transfers(c));  // variant 3 reads J
+  if (rc) return rc;
   return fail(c, launch_get_populations(c, rep, d_dst));
 }
 
 int lbmd_batch_set_populations(lbmd* c, int32_t rep, const void* d_src) {
   int rc = check_rep(c, rep);
   if (rc || !d_src) return rc ? rc : LBMD_EINVAL;
-  rc = fail(c, launch_set_populations(c, rep, d_src));
+  // the pending transfer is kept (variants 1, 2) and the cache is refilled
+  // from J: the particles' own transfers first go there
+  rc = fail(c, launch_leave_transfers(c));
+  if (!rc) rc = fail(c, launch_set_populations(c, rep, d_src));
   if (rc) return rc;
   if (c->p[0].variant == 3) {
     // the transfer received in the current interval is part of the
@@ -583,6 +612,8 @@ int lbmd_batch_set_populations(lbmd* c, int32_t rep, const void* d_src) {
 int lbmd_batch_get_transfer(lbmd* c, int32_t rep, void* d_dst) {
   int rc = check_rep(c, rep);
   if (rc || !d_dst) return rc ? rc : LBMD_EINVAL;
+  rc = fail(c, launch_leave_transfers(c));
+  if (rc) return rc;
   return fail(c, launch_get_transfer(c, rep, d_dst));
 }
 
@@ -603,10 +634,13 @@ int lbmd_get_counters(lbmd* c, int64_t* t_lb, int64_t* t_md, int32_t* subs) {
 int lbmd_set_counters(lbmd* c, int64_t t_lb, int64_t t_md, int32_t subs) {
   if (!c || t_lb < 0 || t_md < subs || subs < 0 || subs > c->plan.n_sub) return LBMD_EINVAL;
   if (c->sticky) return c->sticky;
+  int rc0 = fail(c, launch_leave_transfers(c));  // J complete before the cache is rebuilt
+  if (rc0) return rc0;
   c->t_lb = t_lb;
   c->t_md = t_md;
   c->subs = subs;
   int rc = fail(c, write_clock(c));
+  if (!rc) rc = fail(c, reset_stencil_records(c));
   if (rc) return rc;
   return fail(c, invalidate_corner_cache(c));
 }
@@ -699,6 +733,7 @@ int load_common(lbmd* c, const char* src, const StateLayout& sl) {
   c->t_md = cnt[1];
   c->subs = 0;
   rc = fail(c, write_clock(c));
+  if (!rc) rc = fail(c, reset_stencil_records(c));
   if (!rc) rc = fail(c, invalidate_corner_cache(c));
   if (!rc && c->bound) rc = fail(c, launch_init_forces(c));
   return rc;
@@ -1110,10 +1145,12 @@ int lbmd_autotune(lbmd* c, const char* cache_path, int32_t* out_lb_blocks,
                                                 hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return fail(c, e);
       }
-      // the refills left claims (marks, shared flags) of this interval:
-      // start it clean
+      // the refills left claims (marks, shared flags) of this interval and
+      // the trial steps stencil records and stencil-change steps: start it
+      // clean
       e = hipMemsetAsync(at(c, L.transfer), 0, S * 4 * t, c->stream);
       if (e == hipSuccess) e = hipMemsetAsync(at(c, L.mark), 0, (S / 64) * 8, c->stream);
+      if (e == hipSuccess) e = reset_stencil_records(c);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) return fail(c, e);
       c->cache_dirty = true;

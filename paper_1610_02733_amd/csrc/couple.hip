@@ -19,7 +19,8 @@ using namespace lbmd_dev;
 // pulled populations; the state does not change until the next LB step, so
 // the MD steps of the interval read 8 contiguous vectors per particle instead
 // of 8 x 19 scattered populations.  Also marks the 8 sites as receivers of
-// momentum transfer for the LB step.
+// momentum transfer for the LB step and records the particle at its cube's
+// base (owner_of_shared).
 // ---------------------------------------------------------------------------
 constexpr int kRefillLanes = 32;
 
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
     const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
     a.cc[(size_t)p * 32 + sl] = mine;
     if (c == 0) claim_site(a, m.site_off + site);
+    if (sl == 0) a.owner[m.site_off + site] = (int32_t)p;  // corner 0: the cube's base
   }
 }
 
@@ -119,6 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
     claim_site(a, m.site_off + site);
+    if (k == 0) a.owner[m.site_off + site] = (int32_t)p;  // the stencil's base
   }
 }
 
@@ -130,17 +133,19 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
 //
 // Each lane fetches its sites' cached moments (the refill, or for a particle
 // that changed cubes the after-step work of the previous step, filled them)
-// and the sites' pending transfer J; the interpolated fluid velocity (Eq. 5)
-// is the sum over the lanes (butterfly shuffles, the same order on every
-// lane) and includes J in variants 2 and 3 (variant 3 sees the same
-// velocities as variant 2 inside an interval; its transfer differs only in
-// how the LB step applies it).  Friction + noise (Eq. 4, 6) and velocity
-// Verlet are evaluated on all lanes alike; lane 0 stores the particle.  The
-// transfer -w_k dP (Eq. 7-8) is then written at once at sites only this
-// particle claimed in the interval, which no other particle reads or writes,
-// and listed for the after-step work (after_step_item) at shared sites,
-// because in variants 2 and 3 every particle must first read J as of the end
-// of the previous MD step.
+// and the sites' pending transfer: the particle's own entry at sites it
+// claimed alone, J at shared ones (couple_state.hpp, own transfers); the
+// interpolated fluid velocity (Eq. 5) is the sum over the lanes (butterfly
+// shuffles, the same order on every lane) and includes the pending transfer
+// in variants 2 and 3 (variant 3 sees the same velocities as variant 2
+// inside an interval; its transfer differs only in how the LB step applies
+// it).  Friction + noise (Eq. 4, 6) and velocity Verlet are evaluated on all
+// lanes alike; lane 0 stores the particle.  The transfer -w_k dP (Eq. 7-8)
+// is then added at once at sites only this particle claimed in the interval,
+// which no other particle reads or writes (to its own entry, and to J when
+// it leaves the site or the interval ends), and listed for the after-step
+// work (after_step_item) at shared sites, because in variants 2 and 3 every
+// particle must first read J as of the end of the previous MD step.
 //
 // With Rec, the particle's position and velocity before the step and the
 // corner velocities (j [+ J]) and inverse densities it interpolated are
@@ -181,17 +186,17 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     const int64_t seg = t0 / kBlock;
     if (threadIdx.x == 0) s_l = s_m = 0;
     __syncthreads();
-    bool moved = false;
-    int new_cell = 0;
+    bool moved = false, leave = false;
+    int new_cell = 0, old_cell = 0;
     int gs_[kPer];
     double w_[kPer];
     Vec4<T> jv_[kPer];
-    bool sh_[kPer];
+    bool sh_[kPer], dec_[kPer];
     double dp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int jj = 0; jj < kPer; ++jj) {
       gs_[jj] = -1;
-      sh_[jj] = false;
+      sh_[jj] = dec_[jj] = false;
     }
     const int64_t p = t / Sh::kLanes;
     const int k0 = (int)(t & (Sh::kLanes - 1));
@@ -231,8 +236,20 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         const Vec4<T> cv = *cache_entry<ST>(a, p, k);
         // fluid velocity at the particle (Eq. 5)
         double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-        jv_[jj] = a.J[gs];
-        sh_[jj] = jv_[jj].w != T(0);  // shared-site flag (claim_site)
+        // the site's pending transfer: the particle's own one where it
+        // claimed the site alone, else J; after a refill the w word of J
+        // tells which (claim_site)
+        bool decide = a.retag != 0;
+        if (!decide) {
+          jv_[jj] = *own_entry<ST>(a, p, k);
+          decide = jv_[jj].w == T(2);  // a site claimed after a stencil change
+          sh_[jj] = jv_[jj].w != T(0);
+        }
+        if (decide || sh_[jj]) {
+          jv_[jj] = a.J[gs];
+          sh_[jj] = jv_[jj].w != T(0);
+        }
+        dec_[jj] = decide;
         if (a.variant >= 2) {  // the fluid velocity includes the pending transfer
           jx += (double)jv_[jj].x;
           jy += (double)jv_[jj].y;
@@ -307,16 +324,24 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.bin[p] = -1;
         }
       }
-      if (k0 == 0) {
-        // the next MD step needs other sites if the stencil moved (a
-        // non-finite new position is caught by that step)
-        if (isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
-          Cube qn;
-          St::locate(Xn, m.g, qn);
-          moved = qn.base[0] != q.base[0] || qn.base[1] != q.base[1] || qn.base[2] != q.base[2];
-          new_cell = qn.base[0] + m.g.nx * (qn.base[1] + m.g.ny * qn.base[2]);
-        }
+      // the next MD step needs other sites if the stencil moved (a
+      // non-finite new position is caught by that step); every lane of the
+      // particle sees the same new position
+      const bool fin = isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2]);
+      if (fin) {
+        Cube qn;
+        St::locate(Xn, m.g, qn);
+        moved = qn.base[0] != q.base[0] || qn.base[1] != q.base[1] || qn.base[2] != q.base[2];
+        new_cell = qn.base[0] + m.g.nx * (qn.base[1] + m.g.ny * qn.base[2]);
       }
+      // the particle's own transfers go to J when it leaves its sites (a
+      // non-finite particle is skipped from the next step on) and at the
+      // interval's last MD step
+      leave = a.last || moved || !fin;
+      if (moved && k0 == 0) a.moved_at[p] = (long long)t_md;
+      old_cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
+      // the record of the stencil it leaves (owner_of_shared)
+      if ((moved || !fin) && k0 == 0) a.owner[m.site_off + old_cell] = -1;
     }
     // transfer -w_k dP (Eq. 7-8): a site only this particle claimed in the
     // interval has no other reader or writer, so it takes the new value right
@@ -328,21 +353,20 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       const double ww = gs >= 0 ? w_[jj] : 0.0;
       const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
       if (gs >= 0 && !sh_[jj]) {
-        Vec4<T> nv = jv_[jj];
-        nv.x += ax;
-        nv.y += ay;
-        nv.z += az;
-        a.J[gs] = nv;
+        const Vec4<T> nv{jv_[jj].x + ax, jv_[jj].y + ay, jv_[jj].z + az, T(0)};
+        *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = nv;
+        if (leave) a.J[gs] = nv;
       }
       if (gs >= 0 && sh_[jj]) {
         const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
         a.lsite[e] = gs;
         a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
+        if (dec_[jj]) *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = Vec4<T>{T(0), T(0), T(0), T(1)};
       }
     }
-    if (moved)
-      reinterpret_cast<int2*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
-          make_int2((int)p, new_cell);
+    if (moved && k0 == 0)
+      reinterpret_cast<int4*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
+          make_int4((int)p, new_cell, old_cell, 0);
     __syncthreads();
     if (threadIdx.x == 0) {
       a.lseg[seg] = s_l;
@@ -416,7 +440,12 @@ static hipError_t couple_st(Context* c, int substep) {
   if (substep == 0 || c->cache_dirty) {
     if ((e = launch_refill_st<T, ST>(c, a)) != hipSuccess) return e;
     c->cache_dirty = false;
+    c->retag = true;
   }
+  // the first coupling step after a refill takes the sharing of the sites
+  // from J's w words and sets up the own-transfer entries
+  a.retag = c->retag ? 1 : 0;
+  c->retag = false;
   // lanes per particle of the coupling kernel: eight while recording, else
   // the tuned count or the default
   const int L = a.rec ? 8 : (c->tune.couple_lanes > 0 ? c->tune.couple_lanes
@@ -466,6 +495,65 @@ hipError_t launch_couple(Context* c, int substep) {
   return c->plan.prec == 32 ? couple_t<float>(c, substep) : couple_t<double>(c, substep);
 }
 
+// ---------------------------------------------------------------------------
+// Own transfers into J (couple_state.hpp): between two MD steps of an
+// interval, J lacks the transfers particles keep in their own entries at
+// sites they claimed alone.  This writes them there (J = the particle's own
+// transfer, the whole transfer of such a site), for calls that read or
+// replace J, the populations or the cache in mid-interval.  The entries are
+// those of each particle's current stencil (the after-step work rebuilt
+// them if it moved); a particle that became non-finite left its transfers
+// in J at that step.  32 lanes per particle, one per stencil site.
+// ---------------------------------------------------------------------------
+template <typename T, int ST>
+__global__ __launch_bounds__(kBlock) void k_leave_transfers(CoupleArgs<T> a) {
+  using St = Stencil<ST>;
+  const int64_t N = a.N;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * 32;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = t / 32;
+    const int k = (int)(t & 31);
+    if (k >= St::kSites) continue;
+    const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
+    if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) continue;
+    const Vec4<T> e = *own_entry<ST>(a, p, k);
+    if (e.w != T(0)) continue;
+    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    Cube q;
+    St::locate(X, m.g, q);
+    int cx, cy, cz, site;
+    double w;
+    St::site(q, m.g, k, cx, cy, cz, site, w);
+    T* j = reinterpret_cast<T*>(a.J + m.site_off + site);
+    j[0] = e.x;
+    j[1] = e.y;
+    j[2] = e.z;
+  }
+}
+
+template <typename T>
+static hipError_t leave_t(Context* c) {
+  const CoupleArgs<T> a = couple_args<T>(c, c->subs);
+  const dim3 grid(grid_for((a.N * 32 + kBlock - 1) / kBlock, c->tune.part_blocks));
+  if (c->p[0].stencil == 1)
+    hipLaunchKernelGGL((k_leave_transfers<T, 1>), grid, dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_leave_transfers<T, 0>), grid, dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError();
+}
+
+// J complete between two MD steps of an interval (nothing to do at an
+// LB-step boundary, nor after the interval's last MD step, which left every
+// transfer in J).
+hipError_t launch_leave_transfers(Context* c) {
+  // the entries are valid from the coupling step after a refill until the
+  // cache is invalidated (which callers do after leaving the transfers)
+  if (c->plan.Ntot == 0 || !c->bound || c->subs <= 0 || c->subs >= c->plan.n_sub ||
+      c->retag || c->cache_dirty)
+    return hipSuccess;
+  return c->plan.prec == 32 ? leave_t<float>(c) : leave_t<double>(c);
+}
+
 template <typename T>
 static hipError_t refill_t(Context* c) {
   CoupleArgs<T> a = couple_args<T>(c, 0);
@@ -476,6 +564,7 @@ static hipError_t refill_t(Context* c) {
 // cache and the marks of this LB interval): used to time launch shapes.
 hipError_t launch_couple_refill_only(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
+  c->retag = true;
   return c->plan.prec == 32 ? refill_t<float>(c) : refill_t<double>(c);
 }
 

@@ -23,6 +23,12 @@ struct CoupleArgs {
   unsigned long long* __restrict__ mark;
   double* __restrict__ fc_held;  // coupling force of the step (split kick)
   T* __restrict__ cc;
+  // the particle's own transfer at each site of its stencil in this LB
+  // interval (x, y, z) and, in w, whether the site is shared (non-zero: the
+  // transfer of the site is read from and added to J), [N][sites per stencil]
+  Vec4<T>* __restrict__ own;
+  int32_t* __restrict__ owner;     // [Stot] at a stencil's lowest site: its particle (owner_of_shared)
+  long long* __restrict__ moved_at;  // [N] MD step (global count) of the last stencil change
   int32_t* __restrict__ flags;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
@@ -33,8 +39,9 @@ struct CoupleArgs {
   int32_t* __restrict__ lsite;   // transfers of the MD step to shared sites: global site,
   Vec4<T>* __restrict__ ldelta;  //   momentum (x, y, z, -),
   int32_t* __restrict__ lseg;    //   entries in the segment
-  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int2:
-                                 //   slot, replica-local index of the new stencil base),
+  int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int4:
+                                 //   slot, replica-local indices of the new and old
+                                 //   stencil bases, -),
   int32_t* __restrict__ mseg;    //   their number in the segment
   // force cells (position-dependent forces): the coupling kernel bins the
   // particles at their new positions for the force kernel
@@ -43,6 +50,8 @@ struct CoupleArgs {
   int32_t* __restrict__ bin_rank;   // [N] slot inside the cell
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
+  int retag;    // the cache was refilled for this step: sharing comes from the w words of J
+  int last;     // the interval's last MD step: every transfer is left in J
   int variant;
   int single;   // one replica: its constants are uniform across the grid
 };
@@ -53,19 +62,112 @@ __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t 
   return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
 }
 
+// Own-transfer entry k of particle p (see CoupleArgs::own).
+template <int ST = 0, typename T>
+__device__ __forceinline__ Vec4<T>* own_entry(const CoupleArgs<T>& a, int64_t p, int k) {
+  return a.own + (size_t)p * Stencil<ST>::kSites + k;
+}
+
 // Mark a site as a receiver of momentum transfer in this LB interval; a site
 // claimed again (by another particle, or by one that changed stencils) is
-// flagged as shared in the w word of its transfer entry, which the coupling
-// kernel reads together with the transfer itself.  The flag is written only
-// by claims (refill, after-step work: never while a coupling kernel runs) and
-// cleared with the entry by the LB step; the after-step atomics touch only
-// the x, y, z words.  (Recording the claiming particle instead, so that a
-// particle re-claiming its own sites keeps them unshared, measured slower:
-// the refill's extra compare-and-swap per site cost more than it saved.)
+// flagged as shared in the w word of its transfer entry.  The flag is
+// written only by claims (refill, after-step work: never while a coupling
+// kernel runs) and cleared with the entry by the LB step; the after-step
+// atomics touch only the x, y, z words.  Returns whether the site was
+// claimed before.  (Recording the claimant with a compare-and-swap in the w
+// word instead measured slower.)
 template <typename T>
-__device__ __forceinline__ void claim_site(const CoupleArgs<T>& a, int gs) {
+__device__ __forceinline__ bool claim_site(const CoupleArgs<T>& a, int gs) {
   const unsigned long long bit = 1ull << (gs & 63);
-  if (atomicOr(a.mark + (gs >> 6), bit) & bit) reinterpret_cast<T*>(a.J + gs)[3] = T(1);
+  if (atomicOr(a.mark + (gs >> 6), bit) & bit) {
+    reinterpret_cast<T*>(a.J + gs)[3] = T(1);
+    return true;
+  }
+  return false;
+}
+
+// Own transfers (CoupleArgs::own).  A site that a particle claimed alone in
+// the refill has that particle as its only reader and writer until another
+// particle claims it, so the particle keeps its transfer there in its own
+// entry (read and written with its cache, contiguous) instead of J
+// (scattered lines), and leaves it in J only when it leaves the site, at the
+// interval's last MD step, or when the library needs J complete in between
+// (launch_leave_transfers).  For sites claimed after a stencil change, the
+// particle's next MD step takes the decision from J, as after a refill.
+//
+// Finding the particle that holds a site alone: every particle records
+// itself at the lowest site of its stencil (the refill, and the after-step
+// work when its stencil moved; a plain store, last writer wins), and the
+// coupling kernel clears the record of a stencil its particle leaves.  A
+// particle q that holds site s alone is the only one whose stencil held s in
+// this interval, so no other particle wrote or cleared the records of the
+// W^3 stencil bases that contain s, and q wrote its own base's record: that
+// record names q.  (A cleared or overwritten record belonged to a stencil
+// two particles held in the interval, which holds no site alone.)  Records
+// are -1 where no particle has been; any other record naming a particle
+// whose current stencil does not start there (an earlier binding, a
+// particle that stopped) is stale and skipped.
+//
+// owner_of_shared runs when particle p's claim found site gs claimed before,
+// in the after-step work between coupling kernels: the holder q's transfer
+// so far goes to J and q's entry is marked shared, so that from the next MD
+// step on both read and add to J.  A q that left its stencil in this very
+// step has left its transfers in J already; an undecided entry takes its
+// flag from J.
+// The records of the W^3 stencil bases that contain site (sx, sy, sz) of a
+// replica (owner_of_shared), loaded together.
+template <int ST>
+struct BaseRecords {
+  static constexpr int W = ST == 0 ? 2 : 3;  // sites per axis
+  int bx[W], by[W], bz[W];                   // the bases per axis (wrapped)
+  int32_t rec[W * W * W];                    // base (ox, oy, oz) at ox + W (oy + W oz)
+};
+
+template <int ST, typename T>
+__device__ __forceinline__ void load_base_records(const CoupleArgs<T>& a, const RepMD& m, int sx,
+                                                  int sy, int sz, BaseRecords<ST>& r) {
+  constexpr int W = BaseRecords<ST>::W;
+#pragma unroll
+  for (int o = 0; o < W; ++o) {
+    r.bx[o] = cell_of(sx - o, m.g.nx);
+    r.by[o] = cell_of(sy - o, m.g.ny);
+    r.bz[o] = cell_of(sz - o, m.g.nz);
+  }
+#pragma unroll
+  for (int d = 0; d < W * W * W; ++d)
+    r.rec[d] = a.owner[m.site_off + r.bx[d % W] +
+                       m.g.nx * (r.by[(d / W) % W] + m.g.ny * r.bz[d / (W * W)])];
+}
+
+template <typename T, int ST>
+__device__ __forceinline__ void owner_of_shared(const CoupleArgs<T>& a, const RepMD& m, int rep,
+                                                int gs, int64_t p, const BaseRecords<ST>& r) {
+  using St = Stencil<ST>;
+  constexpr int W = BaseRecords<ST>::W;
+  const long long now = (long long)(a.clock->t_md + a.substep);
+  const int64_t N = a.N;
+#pragma unroll
+  for (int d = 0; d < W * W * W; ++d) {
+    const int64_t q = r.rec[d];
+    if (q == p || q < 0 || q >= N) continue;
+    const int ox = d % W, oy = (d / W) % W, oz = d / (W * W);
+    Vec4<T>* e = own_entry<ST>(a, q, ox + W * (oy + W * oz));
+    // everything that decides, in one round of loads
+    const int rq = a.single ? 0 : a.part_rep[q];
+    const long long mv = a.moved_at[q];
+    const double X[3] = {a.x[q], a.x[N + q], a.x[2 * N + q]};
+    const Vec4<T> ev = *e;
+    if (rq != rep || mv == now || ev.w != T(0)) continue;  // (undecided: the flag is in J)
+    if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) continue;
+    Cube c;
+    St::locate(X, m.g, c);
+    if (c.base[0] != r.bx[ox] || c.base[1] != r.by[oy] || c.base[2] != r.bz[oz]) continue;
+    T* j = reinterpret_cast<T*>(a.J + gs);
+    j[0] = ev.x;
+    j[1] = ev.y;
+    j[2] = ev.z;
+    e->w = T(1);
+  }
 }
 
 // (j, 1/rho) of the post-stream state at site (cx, cy, cz): the 19 pulled
@@ -170,52 +272,98 @@ __device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a,
     reduce_chunk(a, base + c0, n - c0 < kSiteTable / 2 ? n - c0 : kSiteTable / 2, tab);
 }
 
+// The after-step work of one coupling segment (kBlock coupling lanes), in
+// two parts: the particles of the segment whose stencil moved (the new
+// stencil's cache entries, claims and records) and the segment's transfers
+// to shared sites.
+template <typename T, int ST>
+__device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_t seg, int nmv,
+                                                  int L) {
+  using St = Stencil<ST>;
+  const T* __restrict__ pop = a.pop[a.clock->cur];
+  const int nm = nmv * St::kLanes;
+  const int4* __restrict__ ml = reinterpret_cast<const int4*>(a.mlist) + seg * (kBlock / L);
+  for (int u = threadIdx.x; u < nm; u += kBlock) {
+    const int k = u % St::kLanes;
+    if (k >= St::kSites) continue;
+    // (particle, replica-local indices of its new and old stencil bases)
+    const int4 ent = ml[u / St::kLanes];
+    const int64_t p = ent.x;
+    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    Cube q;
+    q.base[0] = ent.y % m.g.nx;
+    q.base[1] = (ent.y / m.g.nx) % m.g.ny;
+    q.base[2] = ent.y / (m.g.nx * m.g.ny);
+    q.s[0] = q.s[1] = q.s[2] = 0.0;
+    int cx, cy, cz, site;
+    double w;
+    St::site(q, m.g, k, cx, cy, cz, site, w);
+    // a site of the old stencil was claimed by this particle already, so
+    // no other particle holds it alone; for the others, the records of the
+    // stencils that may hold it are loaded along with the gather
+    constexpr int W = ST == 0 ? 2 : 3;
+    int ox = cx - ent.z % m.g.nx, oy = cy - (ent.z / m.g.nx) % m.g.ny,
+        oz = cz - ent.z / (m.g.nx * m.g.ny);
+    ox += ox < 0 ? m.g.nx : 0;
+    oy += oy < 0 ? m.g.ny : 0;
+    oz += oz < 0 ? m.g.nz : 0;
+    const bool was_mine = ox < W && oy < W && oz < W;
+    const int rec_site = m.site_off + ent.y;
+    BaseRecords<ST> recs;
+    // (the 27 records of the three-point stencil wait for the claim: loaded
+    // with the gather they cost more registers than the round trip they save)
+    if (ST == 0 && !was_mine) load_base_records<ST>(a, m, cx, cy, cz, recs);
+    *cache_entry<ST>(a, p, k) =
+        gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
+    // whether the particle holds the new site alone is read from J at its
+    // next MD step (w = 2: undecided): another particle that changed
+    // stencils in the same step may claim the same site in this very
+    // launch, after this claim
+    *own_entry<ST>(a, p, k) = Vec4<T>{T(0), T(0), T(0), T(2)};
+    if (claim_site(a, m.site_off + site) && !was_mine) {
+      if (ST != 0) load_base_records<ST>(a, m, cx, cy, cz, recs);
+      owner_of_shared<T, ST>(a, m, a.single ? 0 : a.part_rep[p], m.site_off + site, p, recs);
+    }
+    // the particle's record at its new base, after every lane of its wave
+    // has read the records (one of them may be this very one): the lanes
+    // of one wavefront share one in-order memory stream, so a compiler
+    // barrier at wavefront scope suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (k == 0) a.owner[rec_site] = (int32_t)p;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void after_step_lists(const CoupleArgs<T>& a, int64_t seg, int n,
+                                                 int per, SiteTable<T> tab) {
+  const int64_t base = seg * (int64_t)(kBlock * per);
+  if (tab.key && n > 1) {
+    reduce_segment_transfers(a, base, n, tab);
+    return;
+  }
+  // one lane per (entry, component): the three adds to one site sit in
+  // neighbouring lanes of one instruction and reach the memory side as one
+  // request instead of three
+  for (int u = threadIdx.x; u < 3 * n; u += kBlock) {
+    const int e = u / 3, comp = u - 3 * e;
+    const T d = reinterpret_cast<const T*>(a.ldelta + base + e)[comp];
+    atomicAdd(reinterpret_cast<T*>(a.J + a.lsite[base + e]) + comp, d);
+  }
+}
+
+// Items [0, nseg) are the segments' moved particles, [nseg, 2 nseg) their
+// shared-site transfers (one block each in k_after_step and in the force
+// kernel's extra blocks).
 template <typename T, int ST>
 __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t it, int64_t nseg,
                                                 int per, int L,
                                                 SiteTable<T> tab = SiteTable<T>{nullptr, nullptr}) {
-  using St = Stencil<ST>;
   if (it < nseg) {
-    const int64_t seg = it;
-    const int nm = a.mseg[seg] * St::kLanes;
-    if (nm == 0) return;
-    const T* __restrict__ pop = a.pop[a.clock->cur];
-    const int2* __restrict__ ml = reinterpret_cast<const int2*>(a.mlist) + seg * (kBlock / L);
-    for (int u = threadIdx.x; u < nm; u += kBlock) {
-      const int k = u % St::kLanes;
-      if (k >= St::kSites) continue;
-      // (particle, replica-local index of its new stencil base)
-      const int2 ent = ml[u / St::kLanes];
-      const int64_t p = ent.x;
-      const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
-      Cube q;
-      q.base[0] = ent.y % m.g.nx;
-      q.base[1] = (ent.y / m.g.nx) % m.g.ny;
-      q.base[2] = ent.y / (m.g.nx * m.g.ny);
-      q.s[0] = q.s[1] = q.s[2] = 0.0;
-      int cx, cy, cz, site;
-      double w;
-      St::site(q, m.g, k, cx, cy, cz, site, w);
-      *cache_entry<ST>(a, p, k) =
-          gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
-      claim_site(a, m.site_off + site);
-    }
+    const int nmv = a.mseg[it];
+    if (nmv > 0) after_step_movers<T, ST>(a, it, nmv, L);
   } else {
-    const int64_t seg = it - nseg;
-    const int n = a.lseg[seg];
-    const int64_t base = seg * (int64_t)(kBlock * per);
-    if (tab.key && n > 1) {
-      reduce_segment_transfers(a, base, n, tab);
-      return;
-    }
-    // one lane per (entry, component): the three adds to one site sit in
-    // neighbouring lanes of one instruction and reach the memory side as one
-    // request instead of three
-    for (int u = threadIdx.x; u < 3 * n; u += kBlock) {
-      const int e = u / 3, comp = u - 3 * e;
-      const T d = reinterpret_cast<const T*>(a.ldelta + base + e)[comp];
-      atomicAdd(reinterpret_cast<T*>(a.J + a.lsite[base + e]) + comp, d);
-    }
+    const int n = a.lseg[it - nseg];
+    if (n > 0) after_step_lists<T>(a, it - nseg, n, per, tab);
   }
 }
 
@@ -233,6 +381,9 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.mark = (unsigned long long*)at(c, L.mark);
   a.fc_held = (double*)at(c, L.fc_held);
   a.cc = (T*)at(c, L.cc);
+  a.own = (Vec4<T>*)at(c, L.own);
+  a.owner = (int32_t*)at(c, L.owner);
+  a.moved_at = (long long*)at(c, L.moved_at);
   a.flags = (int32_t*)at(c, L.flags);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
@@ -249,6 +400,8 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.bin_rank = (int32_t*)at(c, L.bin_rank);
   a.N = c->plan.Ntot;
   a.substep = substep;
+  a.retag = 0;
+  a.last = substep == c->plan.n_sub - 1 ? 1 : 0;
   a.variant = c->p[0].variant;
   a.single = c->plan.R == 1 ? 1 : 0;
   return a;

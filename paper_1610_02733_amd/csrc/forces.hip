@@ -335,7 +335,7 @@ static hipError_t launch_binning(Context* c, bool counted) {
 }
 
 template <typename T, bool Kick, int AfterST>
-static hipError_t forces_t(Context* c) {
+static hipError_t forces_t(Context* c, int substep = 0) {
   const ForceArgs<T> a = force_args<T>(c);
   const int64_t nfb = (a.N * kForceLanes + kBlock - 1) / kBlock;
   CoupleArgs<T> ca{};
@@ -343,7 +343,7 @@ static hipError_t forces_t(Context* c) {
   int per = 0, L = 0;
   if (AfterST >= 0) {
     constexpr int ST = AfterST >= 0 ? AfterST : 0;
-    ca = couple_args<T>(c, 0);
+    ca = couple_args<T>(c, substep);
     // the coupling kernel's lanes per particle (tuned or default)
     L = c->tune.couple_lanes > 0 ? c->tune.couple_lanes : DirectShape<ST>::kLanes;
     per = (Stencil<ST>::kSites + L - 1) / L;
@@ -375,16 +375,18 @@ hipError_t launch_init_forces(Context* c) {
 // after-step work in the same launch (so the coupling step launches no
 // after-step kernel of its own).
 template <typename T>
-static hipError_t forces_and_kick_t(Context* c) {
-  if (c->rec_part) return forces_t<T, true, -1>(c);
-  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c) : forces_t<T, true, 0>(c);
+static hipError_t forces_and_kick_t(Context* c, int substep) {
+  if (c->rec_part) return forces_t<T, true, -1>(c, substep);
+  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c, substep)
+                              : forces_t<T, true, 0>(c, substep);
 }
 
-hipError_t launch_forces_and_kick(Context* c) {
+hipError_t launch_forces_and_kick(Context* c, int substep) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e = launch_binning(c, !c->rec_part);
   if (e != hipSuccess) return e;
-  return c->plan.prec == 32 ? forces_and_kick_t<float>(c) : forces_and_kick_t<double>(c);
+  return c->plan.prec == 32 ? forces_and_kick_t<float>(c, substep)
+                            : forces_and_kick_t<double>(c, substep);
 }
 
 }  // namespace lbmd_impl

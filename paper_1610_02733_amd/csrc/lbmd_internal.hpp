@@ -90,9 +90,12 @@ struct Layout {
   size_t sort_img;   // [3][Ntot] int32: particle sort scratch (image counters)
   size_t fc_held;    // [3][Ntot] double: coupling force of the MD step (split kick)
   size_t cc;         // [Ntot][32] T: corner cache, per corner k: jx, jy, jz, 1/rho
+  size_t own;        // [Ntot][sites per stencil] Vec4<T>: own transfers (couple_state.hpp)
+  size_t owner;      // [Stot] int32: at a stencil's lowest site, a particle whose stencil starts there (-1: none)
+  size_t moved_at;   // [Ntot] int64: MD step of each particle's last stencil change
   size_t slist_site;  // [sites per stencil * Ntot] int32: shared-site transfers of an MD step
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
-  size_t mlist;      // [segments * kBlock / lanes] int2: particles whose stencil moved, new base
+  size_t mlist;      // [segments * kBlock / lanes] int4: particles whose stencil moved, new and old base
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
   size_t bin_count;  // [Ctot] int32: particles per force cell
   size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
@@ -190,6 +193,7 @@ struct Context {
   int32_t* img;
   bool bound;
   bool cache_dirty;  // the corner cache was invalidated since the last refill
+  bool retag;        // a refill ran: the next coupling step sets up the own-transfer entries
   int64_t t_lb, t_md;
   int32_t subs;
   int cur;  // population buffer holding the current state (mirrors Clock::cur)
@@ -239,11 +243,13 @@ hipError_t launch_couple_refill_only(Context* c);
 hipError_t launch_init_forces(Context* c);
 hipError_t launch_init_pid(Context* c);
 hipError_t invalidate_corner_cache(Context* c);
+// the particles' own transfers into J, between two MD steps of an interval
+hipError_t launch_leave_transfers(Context* c);
 // lanes per particle the coupling kernel is built for: {2, 4, 8} for the
 // trilinear stencil, {8, 16} for the three-point one; returns the count
 int couple_lane_candidates(int stencil, int out[4]);
 hipError_t launch_forces(Context* c);
-hipError_t launch_forces_and_kick(Context* c);
+hipError_t launch_forces_and_kick(Context* c, int substep);
 int64_t force_cells(const lbmd_params* p);
 // nx is 64, 128 or 256 and the replica's 19 S population entries have 32-bit
 // offsets: the collide-stream kernel's row path (aligned rows, DPP x shift)
