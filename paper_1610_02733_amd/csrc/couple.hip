@@ -165,7 +165,7 @@ struct CoupleShape {
   }
 };
 
-template <typename T, bool Rec, int ST, int L, bool Bin>
+template <typename T, bool Rec, int ST, int L, bool Bin, bool One>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
   using Sh = CoupleShape<L>;
@@ -175,6 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   const uint32_t step_lo = (uint32_t)(t_md & 0xFFFFFFFFull), step_hi = (uint32_t)(t_md >> 32);
   const int64_t N = a.N;
   const int64_t lanes = N * Sh::kLanes;
+  // One (a single replica): the replica's constants are the same for every
+  // particle, read once before any store (uniform, scalar loads); otherwise
+  // each particle reads its replica's entry
+  RepMD m1;
+  if constexpr (One) m1 = a.md[0];
   // entries of this block's segment in the two lists, counted in LDS
   __shared__ int s_l, s_m;
   // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
@@ -201,14 +206,32 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     const int64_t p = t / Sh::kLanes;
     const int k0 = (int)(t & (Sh::kLanes - 1));
     double X[3], V[3];
+    // everything the step reads of the particle and its stencil entries,
+    // loaded together (J, which needs the stencil's sites, follows)
+    double fc[3];
+    int32_t im[3];
+    uint32_t lp = 0;
+    Vec4<T> cv_[kPer];
     bool live = t < lanes;
     if (live) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         X[d] = a.x[d * N + p];
         V[d] = a.v[d * N + p];
-        live = live && isfinite(X[d]) && isfinite(V[d]);
+        fc[d] = a.fcons[d * N + p];
+        im[d] = a.img[d * N + p];
       }
+      lp = (uint32_t)a.pid[p];
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj) {
+        const int k = k0 + jj * Sh::kLanes;
+        if (k < St::kSites) {
+          cv_[jj] = *cache_entry<ST>(a, p, k);
+          jv_[jj] = *own_entry<ST>(a, p, k);
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) live = live && isfinite(X[d]) && isfinite(V[d]);
       if (!live && k0 == 0) {
         a.flags[0] = 1;
         if (Rec) a.rec[p] = __builtin_nan("");
@@ -216,40 +239,50 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       }
     }
     if (live) {
-      const int rr = a.single ? 0 : a.part_rep[p];
-      const RepMD& m = a.md[rr];
+      RepMD mr;
+      if constexpr (!One) mr = a.md[a.part_rep[p]];
+      const RepMD& m = One ? m1 : mr;
       Cube q;
       St::locate(X, m.g, q);
-      double ux = 0.0, uy = 0.0, uz = 0.0;
+      // the sites' pending transfer: the particle's own one where it claimed
+      // the site alone, else J (all loads issued before use); after a refill
+      // the w word of J tells which (claim_site), and so it does for a site
+      // claimed after a stencil change (own w = 2)
 #pragma unroll
       for (int jj = 0; jj < kPer; ++jj) {
         const int k = k0 + jj * Sh::kLanes;
-        if (k >= St::kSites) break;
-        int cx, cy, cz, site;
-        double w;
-        St::site(q, m.g, k, cx, cy, cz, site, w);
-        const int gs = m.site_off + site;
-        gs_[jj] = gs;
-        w_[jj] = w;
-        // every live particle's cache covers its current stencil (the
-        // refill, or the previous step's after-step work if it moved)
-        const Vec4<T> cv = *cache_entry<ST>(a, p, k);
+        if (k < St::kSites) {
+          int cx, cy, cz, site;
+          double w;
+          St::site(q, m.g, k, cx, cy, cz, site, w);
+          gs_[jj] = m.site_off + site;
+          w_[jj] = w;
+        }
+      }
+      // (one load per site, from J or again from the own entry, which no
+      // other thread writes: no branch, so the loads issue back to back)
+      const bool retag = a.retag != 0;
+      const Vec4<T>* src_[kPer];
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj) {
+        const T ow = jv_[jj].w;
+        dec_[jj] = retag | (ow == T(2));
+        const bool use_j = (retag | (ow != T(0))) & (gs_[jj] >= 0);
+        // (a slot past the stencil's last site reads the first own entry)
+        src_[jj] = use_j ? a.J + gs_[jj]
+                         : own_entry<ST>(a, p, gs_[jj] >= 0 ? k0 + jj * Sh::kLanes : 0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj) jv_[jj] = *src_[jj];
+      double ux = 0.0, uy = 0.0, uz = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kPer; ++jj) {
+        if (gs_[jj] < 0) continue;
+        const int k = k0 + jj * Sh::kLanes;
+        const Vec4<T> cv = cv_[jj];
+        sh_[jj] = jv_[jj].w != T(0);
         // fluid velocity at the particle (Eq. 5)
         double jx = (double)cv.x, jy = (double)cv.y, jz = (double)cv.z;
-        // the site's pending transfer: the particle's own one where it
-        // claimed the site alone, else J; after a refill the w word of J
-        // tells which (claim_site)
-        bool decide = a.retag != 0;
-        if (!decide) {
-          jv_[jj] = *own_entry<ST>(a, p, k);
-          decide = jv_[jj].w == T(2);  // a site claimed after a stencil change
-          sh_[jj] = jv_[jj].w != T(0);
-        }
-        if (decide || sh_[jj]) {
-          jv_[jj] = a.J[gs];
-          sh_[jj] = jv_[jj].w != T(0);
-        }
-        dec_[jj] = decide;
         if (a.variant >= 2) {  // the fluid velocity includes the pending transfer
           jx += (double)jv_[jj].x;
           jy += (double)jv_[jj].y;
@@ -261,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
           a.rec[(8 + 3 * k) * N + p] = jz;
           a.rec[(30 + k) * N + p] = (double)cv.w;
         }
-        const double wi = w * (double)cv.w;
+        const double wi = w_[jj] * (double)cv.w;
         ux += wi * jx;
         uy += wi * jy;
         uz += wi * jz;
@@ -283,7 +316,6 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       // friction + noise (Eq. 4), momentum change over the MD step (Eq. 6)
       double xi[3] = {0.0, 0.0, 0.0};
       if (m.noise) {
-        const uint32_t lp = (uint32_t)a.pid[p];
         const Words4 o = philox10(Words4{lp, step_lo, m.tag, step_hi}, m.key0, m.key1);
         const uint32_t ws[3] = {o.w0, o.w1, o.w2};
 #pragma unroll
@@ -298,20 +330,18 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       for (int d = 0; d < 3; ++d) {
         const double Fc = -m.gamma * (V[d] - u[d]) + amp * xi[d];
         dp[d] = m.tau * Fc;
-        const double fc = a.fcons[d * N + p];
-        int32_t im = a.img[d * N + p];
-        double v1 = V[d] + m.h * (fc + Fc);
+        double v1 = V[d] + m.h * (fc[d] + Fc);
         double x1 = X[d] + m.tau * v1;
-        wrap_coord(x1, im, m.L[d]);
+        wrap_coord(x1, im[d], m.L[d]);
         Xn[d] = x1;
         if (k0 == 0) {
           if (m.split_kick)
             a.fc_held[d * N + p] = Fc;
           else
-            v1 += m.h * (fc + Fc);
+            v1 += m.h * (fc[d] + Fc);
           a.x[d * N + p] = x1;
           a.v[d * N + p] = v1;
-          a.img[d * N + p] = im;
+          a.img[d * N + p] = im[d];
         }
       }
       if (Bin && k0 == 0) {
@@ -422,10 +452,18 @@ int couple_lane_candidates(int stencil, int out[4]) {
 
 template <typename T, int ST, int L>
 static void launch_couple_lanes(Context* c, const CoupleArgs<T>& a, bool bin, dim3 grid) {
-  if (bin)
-    hipLaunchKernelGGL((k_couple<T, false, ST, L, true>), grid, dim3(kBlock), 0, c->stream, a);
+  if (bin && a.single)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, true, true>), grid, dim3(kBlock), 0, c->stream,
+                       a);
+  else if (bin)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, true, false>), grid, dim3(kBlock), 0, c->stream,
+                       a);
+  else if (a.single)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, false, true>), grid, dim3(kBlock), 0, c->stream,
+                       a);
   else
-    hipLaunchKernelGGL((k_couple<T, false, ST, L, false>), grid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, false, false>), grid, dim3(kBlock), 0, c->stream,
+                       a);
 }
 
 template <typename T, int ST>
@@ -454,7 +492,8 @@ static hipError_t couple_st(Context* c, int substep) {
   // with position-dependent forces (never recorded) the kernel also bins
   const bool bin = c->plan.any_forces2 && !a.rec;
   if (ST == 0 && a.rec) {
-    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false>), cgrid, dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL((k_couple<T, true, 0, 8, false, false>), cgrid, dim3(kBlock), 0, c->stream,
+                       a);
   } else if constexpr (ST == 0) {
     if (L == 2)
       launch_couple_lanes<T, 0, 2>(c, a, bin, cgrid);
