@@ -208,8 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     double X[3], V[3];
     // everything the step reads of the particle and its stencil entries,
     // loaded together (J, which needs the stencil's sites, follows)
-    double fc[3];
-    int32_t im[3];
+    double fc[3] = {0.0, 0.0, 0.0};
     uint32_t lp = 0;
     Vec4<T> cv_[kPer];
     bool live = t < lanes;
@@ -218,8 +217,12 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       for (int d = 0; d < 3; ++d) {
         X[d] = a.x[d * N + p];
         V[d] = a.v[d * N + p];
-        fc[d] = a.fcons[d * N + p];
-        im[d] = a.img[d * N + p];
+      }
+      // conservative forces: none in force model 0 (known here for a single
+      // replica; otherwise the zeros are read)
+      if (!One || m1.force_model != 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fc[d] = a.fcons[d * N + p];
       }
       lp = (uint32_t)a.pid[p];
 #pragma unroll
@@ -332,7 +335,8 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         dp[d] = m.tau * Fc;
         double v1 = V[d] + m.h * (fc[d] + Fc);
         double x1 = X[d] + m.tau * v1;
-        wrap_coord(x1, im[d], m.L[d]);
+        int32_t dim = 0;  // periodic images crossed in this step (rare)
+        wrap_coord(x1, dim, m.L[d]);
         Xn[d] = x1;
         if (k0 == 0) {
           if (m.split_kick)
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
             v1 += m.h * (fc[d] + Fc);
           a.x[d * N + p] = x1;
           a.v[d * N + p] = v1;
-          a.img[d * N + p] = im[d];
+          if (dim != 0) a.img[d * N + p] += dim;
         }
       }
       if (Bin && k0 == 0) {
