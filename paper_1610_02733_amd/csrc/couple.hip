@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
 // With Reduce, the shared-site transfers of each segment are summed per site
 // in LDS first (reduce_segment_transfers; dynamic shared memory of
 // kSiteTable * (4 + 3 sizeof(T)) bytes).
-template <typename T, int ST, bool Reduce>
+template <typename T, int ST, bool Reduce, bool One>
 __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t nseg, int per,
                                                       int L) {
   extern __shared__ int site_table_mem[];
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t 
     tab.val = reinterpret_cast<T*>(site_table_mem + kSiteTable);
   }
   for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x)
-    after_step_item<T, ST>(a, it, nseg, per, L, tab);
+    after_step_item<T, ST, One>(a, it, nseg, per, L, tab);
 }
 
 static int grid_for(int64_t work_blocks, int tuned) {
@@ -519,12 +519,15 @@ static hipError_t couple_st(Context* c, int substep) {
   const int64_t nseg = (N * L + kBlock - 1) / kBlock;
   const dim3 agrid(grid_for(2 * nseg, c->tune.part_blocks));
   const int per = (St::kSites + L - 1) / L;
-  if (ST == 1)  // 27-site stencils overlap densely: pre-reduce per segment
-    hipLaunchKernelGGL((k_after_step<T, ST, true>), agrid, dim3(kBlock),
-                       kSiteTable * (4 + 3 * sizeof(T)), c->stream, a, nseg, per, L);
+  // (27-site stencils overlap densely: pre-reduce per segment)
+  constexpr bool Reduce = ST == 1;
+  const size_t lds = Reduce ? kSiteTable * (4 + 3 * sizeof(T)) : 0;
+  if (a.single)
+    hipLaunchKernelGGL((k_after_step<T, ST, Reduce, true>), agrid, dim3(kBlock), lds, c->stream, a,
+                       nseg, per, L);
   else
-    hipLaunchKernelGGL((k_after_step<T, ST, false>), agrid, dim3(kBlock), 0, c->stream, a, nseg,
-                       per, L);
+    hipLaunchKernelGGL((k_after_step<T, ST, Reduce, false>), agrid, dim3(kBlock), lds, c->stream,
+                       a, nseg, per, L);
   return hipGetLastError();
 }
 

@@ -276,11 +276,15 @@ __device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a,
 // two parts: the particles of the segment whose stencil moved (the new
 // stencil's cache entries, claims and records) and the segment's transfers
 // to shared sites.
-template <typename T, int ST>
+template <typename T, int ST, bool One>
 __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_t seg, int nmv,
                                                   int L) {
   using St = Stencil<ST>;
   const T* __restrict__ pop = a.pop[a.clock->cur];
+  // One (a single replica): its constants read once, before any store
+  // (uniform, scalar loads)
+  RepMD m1;
+  if constexpr (One) m1 = a.md[0];
   const int nm = nmv * St::kLanes;
   const int4* __restrict__ ml = reinterpret_cast<const int4*>(a.mlist) + seg * (kBlock / L);
   for (int u = threadIdx.x; u < nm; u += kBlock) {
@@ -289,7 +293,7 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     // (particle, replica-local indices of its new and old stencil bases)
     const int4 ent = ml[u / St::kLanes];
     const int64_t p = ent.x;
-    const RepMD& m = a.md[a.single ? 0 : a.part_rep[p]];
+    const RepMD& m = One ? m1 : a.md[a.single ? 0 : a.part_rep[p]];
     Cube q;
     q.base[0] = ent.y % m.g.nx;
     q.base[1] = (ent.y / m.g.nx) % m.g.ny;
@@ -354,13 +358,13 @@ __device__ __forceinline__ void after_step_lists(const CoupleArgs<T>& a, int64_t
 // Items [0, nseg) are the segments' moved particles, [nseg, 2 nseg) their
 // shared-site transfers (one block each in k_after_step and in the force
 // kernel's extra blocks).
-template <typename T, int ST>
+template <typename T, int ST, bool One = false>
 __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t it, int64_t nseg,
                                                 int per, int L,
                                                 SiteTable<T> tab = SiteTable<T>{nullptr, nullptr}) {
   if (it < nseg) {
     const int nmv = a.mseg[it];
-    if (nmv > 0) after_step_movers<T, ST>(a, it, nmv, L);
+    if (nmv > 0) after_step_movers<T, ST, One>(a, it, nmv, L);
   } else {
     const int n = a.lseg[it - nseg];
     if (n > 0) after_step_lists<T>(a, it - nseg, n, per, tab);
