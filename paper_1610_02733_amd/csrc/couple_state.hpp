@@ -139,34 +139,75 @@ __device__ __forceinline__ void load_base_records(const CoupleArgs<T>& a, const 
                        m.g.nx * (r.by[(d / W) % W] + m.g.ny * r.bz[d / (W * W)])];
 }
 
+// Candidate q (the record of the stencil base (bx, by, bz), the site at
+// offset (ox, oy, oz) from it): if q's current stencil starts there and q
+// holds the site alone, its transfer so far goes to J and its entry turns
+// shared.
+template <typename T, int ST>
+__device__ __forceinline__ void notify_holder(const CoupleArgs<T>& a, const RepMD& m, int rep,
+                                              int gs, int64_t p, int64_t q, int ox, int oy,
+                                              int oz, int bx, int by, int bz, long long now) {
+  using St = Stencil<ST>;
+  constexpr int W = BaseRecords<ST>::W;
+  const int64_t N = a.N;
+  if (q == p || q < 0 || q >= N) return;
+  Vec4<T>* e = own_entry<ST>(a, q, ox + W * (oy + W * oz));
+  // everything that decides, in one round of loads
+  const int rq = a.single ? 0 : a.part_rep[q];
+  const long long mv = a.moved_at[q];
+  const double X[3] = {a.x[q], a.x[N + q], a.x[2 * N + q]};
+  const Vec4<T> ev = *e;
+  if (rq != rep || mv == now || ev.w != T(0)) return;  // (undecided: the flag is in J)
+  if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) return;
+  Cube c;
+  St::locate(X, m.g, c);
+  if (c.base[0] != bx || c.base[1] != by || c.base[2] != bz) return;
+  T* j = reinterpret_cast<T*>(a.J + gs);
+  j[0] = ev.x;
+  j[1] = ev.y;
+  j[2] = ev.z;
+  e->w = T(1);
+}
+
+// All W^3 records loaded beforehand (the cube: 8).
 template <typename T, int ST>
 __device__ __forceinline__ void owner_of_shared(const CoupleArgs<T>& a, const RepMD& m, int rep,
                                                 int gs, int64_t p, const BaseRecords<ST>& r) {
-  using St = Stencil<ST>;
   constexpr int W = BaseRecords<ST>::W;
   const long long now = (long long)(a.clock->t_md + a.substep);
-  const int64_t N = a.N;
 #pragma unroll
   for (int d = 0; d < W * W * W; ++d) {
-    const int64_t q = r.rec[d];
-    if (q == p || q < 0 || q >= N) continue;
     const int ox = d % W, oy = (d / W) % W, oz = d / (W * W);
-    Vec4<T>* e = own_entry<ST>(a, q, ox + W * (oy + W * oz));
-    // everything that decides, in one round of loads
-    const int rq = a.single ? 0 : a.part_rep[q];
-    const long long mv = a.moved_at[q];
-    const double X[3] = {a.x[q], a.x[N + q], a.x[2 * N + q]};
-    const Vec4<T> ev = *e;
-    if (rq != rep || mv == now || ev.w != T(0)) continue;  // (undecided: the flag is in J)
-    if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) continue;
-    Cube c;
-    St::locate(X, m.g, c);
-    if (c.base[0] != r.bx[ox] || c.base[1] != r.by[oy] || c.base[2] != r.bz[oz]) continue;
-    T* j = reinterpret_cast<T*>(a.J + gs);
-    j[0] = ev.x;
-    j[1] = ev.y;
-    j[2] = ev.z;
-    e->w = T(1);
+    notify_holder<T, ST>(a, m, rep, gs, p, r.rec[d], ox, oy, oz, r.bx[ox], r.by[oy], r.bz[oz],
+                         now);
+  }
+}
+
+// The same one plane of W^2 records at a time (the three-point stencil's 27
+// records would hold too many registers at once), for site (sx, sy, sz).
+template <typename T, int ST>
+__device__ __forceinline__ void owner_of_shared_planes(const CoupleArgs<T>& a, const RepMD& m,
+                                                       int rep, int gs, int64_t p, int sx, int sy,
+                                                       int sz) {
+  constexpr int W = BaseRecords<ST>::W;
+  const long long now = (long long)(a.clock->t_md + a.substep);
+  int bx[W], by[W];
+#pragma unroll
+  for (int o = 0; o < W; ++o) {
+    bx[o] = cell_of(sx - o, m.g.nx);
+    by[o] = cell_of(sy - o, m.g.ny);
+  }
+#pragma unroll 1
+  for (int oz = 0; oz < W; ++oz) {
+    const int bz = cell_of(sz - oz, m.g.nz);
+    int32_t rec[W * W];
+#pragma unroll
+    for (int d = 0; d < W * W; ++d)
+      rec[d] = a.owner[m.site_off + bx[d % W] + m.g.nx * (by[d / W] + m.g.ny * bz)];
+#pragma unroll
+    for (int d = 0; d < W * W; ++d)
+      notify_holder<T, ST>(a, m, rep, gs, p, rec[d], d % W, d / W, oz, bx[d % W], by[d / W], bz,
+                           now);
   }
 }
 
@@ -314,8 +355,9 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     const bool was_mine = ox < W && oy < W && oz < W;
     const int rec_site = m.site_off + ent.y;
     BaseRecords<ST> recs;
-    // (the 27 records of the three-point stencil wait for the claim: loaded
-    // with the gather they cost more registers than the round trip they save)
+    // (the 27 records of the three-point stencil wait for the claim and are
+    // read a plane at a time: loaded with the gather they cost more
+    // registers than the round trip they save)
     if (ST == 0 && !was_mine) load_base_records<ST>(a, m, cx, cy, cz, recs);
     *cache_entry<ST>(a, p, k) =
         gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
@@ -325,8 +367,11 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     // launch, after this claim
     *own_entry<ST>(a, p, k) = Vec4<T>{T(0), T(0), T(0), T(2)};
     if (claim_site(a, m.site_off + site) && !was_mine) {
-      if (ST != 0) load_base_records<ST>(a, m, cx, cy, cz, recs);
-      owner_of_shared<T, ST>(a, m, a.single ? 0 : a.part_rep[p], m.site_off + site, p, recs);
+      const int rep = a.single ? 0 : a.part_rep[p];
+      if (ST == 0)
+        owner_of_shared<T, ST>(a, m, rep, m.site_off + site, p, recs);
+      else
+        owner_of_shared_planes<T, ST>(a, m, rep, m.site_off + site, p, cx, cy, cz);
     }
     // the particle's record at its new base, after every lane of its wave
     // has read the records (one of them may be this very one): the lanes
