@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
     const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
     a.cc[(size_t)p * 32 + sl] = mine;
     if (c == 0) claim_site(a, m.site_off + site);
-    if (sl == 0) a.owner[m.site_off + site] = (int32_t)p;  // corner 0: the cube's base
+    if (sl == 0 && a.own_on) a.owner[m.site_off + site] = (int32_t)p;  // corner 0: the base
   }
 }
 
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
     claim_site(a, m.site_off + site);
-    if (k == 0) a.owner[m.site_off + site] = (int32_t)p;  // the stencil's base
+    if (k == 0 && a.own_on) a.owner[m.site_off + site] = (int32_t)p;  // the stencil's base
   }
 }
 
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       if (moved && k0 == 0) a.moved_at[p] = (long long)t_md;
       old_cell = q.base[0] + m.g.nx * (q.base[1] + m.g.ny * q.base[2]);
       // the record of the stencil it leaves (owner_of_shared)
-      if ((moved || !fin) && k0 == 0) a.owner[m.site_off + old_cell] = -1;
+      if ((moved || !fin) && k0 == 0 && a.own_on) a.owner[m.site_off + old_cell] = -1;
     }
     // transfer -w_k dP (Eq. 7-8): a site only this particle claimed in the
     // interval has no other reader or writer, so it takes the new value right
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_after_step(CoupleArgs<T> a, int64_t 
     tab.val = reinterpret_cast<T*>(site_table_mem + kSiteTable);
   }
   for (int64_t it = blockIdx.x; it < 2 * nseg; it += gridDim.x)
-    after_step_item<T, ST, One>(a, it, nseg, per, L, tab);
+    after_step_item<T, ST, One, true>(a, it, nseg, per, L, tab);
 }
 
 static int grid_for(int64_t work_blocks, int tuned) {
@@ -486,7 +486,7 @@ static hipError_t couple_st(Context* c, int substep) {
   }
   // the first coupling step after a refill takes the sharing of the sites
   // from J's w words and sets up the own-transfer entries
-  a.retag = c->retag ? 1 : 0;
+  a.retag = (c->retag || !a.own_on) ? 1 : 0;
   c->retag = false;
   // lanes per particle of the coupling kernel: eight while recording, else
   // the tuned count or the default
@@ -595,7 +595,7 @@ hipError_t launch_leave_transfers(Context* c) {
   // the entries are valid from the coupling step after a refill until the
   // cache is invalidated (which callers do after leaving the transfers)
   if (c->plan.Ntot == 0 || !c->bound || c->subs <= 0 || c->subs >= c->plan.n_sub ||
-      c->retag || c->cache_dirty)
+      c->retag || c->cache_dirty || c->plan.any_forces2)  // (no own transfers: J is complete)
     return hipSuccess;
   return c->plan.prec == 32 ? leave_t<float>(c) : leave_t<double>(c);
 }

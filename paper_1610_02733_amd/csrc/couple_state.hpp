@@ -52,6 +52,7 @@ struct CoupleArgs {
   int substep;  // MD step inside the LB interval
   int retag;    // the cache was refilled for this step: sharing comes from the w words of J
   int last;     // the interval's last MD step: every transfer is left in J
+  int own_on;   // own transfers in use (else every step reads J and leaves its transfers there)
   int variant;
   int single;   // one replica: its constants are uniform across the grid
 };
@@ -317,7 +318,10 @@ __device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a,
 // two parts: the particles of the segment whose stencil moved (the new
 // stencil's cache entries, claims and records) and the segment's transfers
 // to shared sites.
-template <typename T, int ST, bool One>
+// Own: own transfers in use (CoupleArgs::own_on; the standalone after-step
+// launch always, the force kernel's extra blocks never), so that the force
+// kernel carries none of the holder lookup's registers.
+template <typename T, int ST, bool One, bool Own>
 __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_t seg, int nmv,
                                                   int L) {
   using St = Stencil<ST>;
@@ -353,12 +357,13 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     oy += oy < 0 ? m.g.ny : 0;
     oz += oz < 0 ? m.g.nz : 0;
     const bool was_mine = ox < W && oy < W && oz < W;
+    constexpr bool own_on = Own;
     const int rec_site = m.site_off + ent.y;
     BaseRecords<ST> recs;
     // (the 27 records of the three-point stencil wait for the claim and are
     // read a plane at a time: loaded with the gather they cost more
     // registers than the round trip they save)
-    if (ST == 0 && !was_mine) load_base_records<ST>(a, m, cx, cy, cz, recs);
+    if (ST == 0 && own_on && !was_mine) load_base_records<ST>(a, m, cx, cy, cz, recs);
     *cache_entry<ST>(a, p, k) =
         gather_site_moments<T>(pop, m.site_off, m.g, cx, cy, cz, (T)m.rho0);
     // whether the particle holds the new site alone is read from J at its
@@ -366,7 +371,7 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     // stencils in the same step may claim the same site in this very
     // launch, after this claim
     *own_entry<ST>(a, p, k) = Vec4<T>{T(0), T(0), T(0), T(2)};
-    if (claim_site(a, m.site_off + site) && !was_mine) {
+    if (claim_site(a, m.site_off + site) && own_on && !was_mine) {
       const int rep = a.single ? 0 : a.part_rep[p];
       if (ST == 0)
         owner_of_shared<T, ST>(a, m, rep, m.site_off + site, p, recs);
@@ -378,7 +383,7 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     // of one wavefront share one in-order memory stream, so a compiler
     // barrier at wavefront scope suffices
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (k == 0) a.owner[rec_site] = (int32_t)p;
+    if (k == 0 && own_on) a.owner[rec_site] = (int32_t)p;
   }
 }
 
@@ -403,13 +408,13 @@ __device__ __forceinline__ void after_step_lists(const CoupleArgs<T>& a, int64_t
 // Items [0, nseg) are the segments' moved particles, [nseg, 2 nseg) their
 // shared-site transfers (one block each in k_after_step and in the force
 // kernel's extra blocks).
-template <typename T, int ST, bool One = false>
+template <typename T, int ST, bool One, bool Own>
 __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t it, int64_t nseg,
                                                 int per, int L,
                                                 SiteTable<T> tab = SiteTable<T>{nullptr, nullptr}) {
   if (it < nseg) {
     const int nmv = a.mseg[it];
-    if (nmv > 0) after_step_movers<T, ST, One>(a, it, nmv, L);
+    if (nmv > 0) after_step_movers<T, ST, One, Own>(a, it, nmv, L);
   } else {
     const int n = a.lseg[it - nseg];
     if (n > 0) after_step_lists<T>(a, it - nseg, n, per, tab);
@@ -449,8 +454,14 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.bin_rank = (int32_t*)at(c, L.bin_rank);
   a.N = c->plan.Ntot;
   a.substep = substep;
-  a.retag = 0;
-  a.last = substep == c->plan.n_sub - 1 ? 1 : 0;
+  // Own transfers pay where particles mostly keep their sites to themselves.
+  // Along bonded chains most particles that change cubes land on sites a
+  // neighbour holds, and finding the holders costs more than reading J:
+  // there every MD step reads the sharing and the transfer from J and
+  // leaves its transfers in J, as the first step of an interval does.
+  a.own_on = c->plan.any_forces2 ? 0 : 1;
+  a.retag = a.own_on ? 0 : 1;
+  a.last = (substep == c->plan.n_sub - 1 || !a.own_on) ? 1 : 0;
   a.variant = c->p[0].variant;
   a.single = c->plan.R == 1 ? 1 : 0;
   return a;

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
                                                    int per, int L, int64_t nfb) {
   if constexpr (AfterST >= 0) {
     if (blockIdx.x >= nfb) {
-      after_step_item<T, AfterST>(ca, (int64_t)blockIdx.x - nfb, nseg, per, L);
+      after_step_item<T, AfterST, false, false>(ca, (int64_t)blockIdx.x - nfb, nseg, per, L);
       return;
     }
   }
