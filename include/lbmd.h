@@ -138,7 +138,12 @@ int lb_destroy(lbmd *c);
  * rows).  d_x: double positions in [0, L) per axis; d_v: double velocities;
  * d_img: int32 periodic image counters (unwrapped position = x + L * img).  The library
  * updates them in place at every md_couple_substep().  Computes the
- * conservative forces at the bound positions.
+ * conservative forces at the bound positions.  Binding in the middle of an
+ * LB interval keeps the pending momentum transfer: before it switches to the
+ * new arrays the library reads the previously bound ones (positions) to
+ * store the transfer that particles keep to themselves into the transfer
+ * field, so those arrays must still hold the particles' state during the
+ * call.
  */
 int lbmd_bind_particles(lbmd *c, void *d_x, void *d_v, int32_t *d_img);
 

@@ -288,6 +288,9 @@ class Lattice(_System):
         library then advances in place (self.x, self.v, self.img)."""
         N = self.N
         f64 = torch.float64  # particle state is FP64 in both lattice precisions
+        # the arrays bound so far stay alive until the library is done with
+        # them: binding in mid-interval reads them (lbmd_bind_particles)
+        previous = (getattr(self, "x", None), getattr(self, "v", None), getattr(self, "img", None))
         self.x = torch.as_tensor(x, dtype=f64, device=self.device).reshape(3, N).clone()
         self.v = torch.as_tensor(v, dtype=f64, device=self.device).reshape(3, N).clone()
         if img is None:
@@ -296,6 +299,8 @@ class Lattice(_System):
             self.img = torch.as_tensor(img, dtype=torch.int32, device=self.device).reshape(3, N).clone()
         _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
                "lbmd_bind_particles")
+        self.stream.synchronize()
+        del previous
 
     def populations(self):
         out = torch.empty((19, self.nsites), dtype=self.dtype, device=self.device)
@@ -400,11 +405,14 @@ class Batch(_System):
         f64 = torch.float64
         x = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in xs], 1)
         v = np.concatenate([np.asarray(a, np.float64).reshape(3, -1) for a in vs], 1)
+        previous = (getattr(self, "x", None), getattr(self, "v", None), getattr(self, "img", None))
         self.x = torch.as_tensor(x, dtype=f64, device=self.device).clone()
         self.v = torch.as_tensor(v, dtype=f64, device=self.device).clone()
         self.img = torch.zeros((3, self.N), dtype=torch.int32, device=self.device)
         _check(lib().lbmd_bind_particles(self._h, _ptr(self.x), _ptr(self.v), _ptr(self.img)),
                "lbmd_bind_particles")
+        self.stream.synchronize()  # (the arrays bound so far: lbmd_bind_particles)
+        del previous
 
     def particles(self, rep):
         a, b = self.offsets[rep], self.offsets[rep + 1]

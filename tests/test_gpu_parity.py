@@ -198,6 +198,45 @@ def test_transfer_field_after_every_md_step(lb, orc, variant, stencil):
     check_particles(g, o, shape, 1e-12, 1e-4)
 
 
+@pytest.mark.parametrize("stencil", [0, 1])
+def test_counters_and_binding_renewed_mid_interval(lb, orc, stencil):
+    """Setting the step counters to their current values, and binding the
+    particles' current state again, in the middle of an interval: the
+    library first stores the transfers that particles keep to themselves
+    into J and forgets which particle holds which site, and the next MD step
+    refills every particle's cache and takes the sharing from J again.  Fast
+    particles at moderate density, so that sites change hands; the run must
+    still match the oracle, which does neither."""
+    shape = (12, 10, 8)
+    N = 60
+    rng = np.random.default_rng(53 + stencil)
+    x = rng.random((3, N)) * np.array(shape, float)[:, None]
+    v = rng.uniform(-3.0, 3.0, (3, N))
+    kw = dict(kT=1e-4, seed=11, n_particles=N, friction=0.05, n_sub=5, variant=2,
+              stencil=stencil)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=64, **kw)
+    o = orc.Oracle(*shape, **kw)
+    g.bind_particles(x, v)
+    o.set_particles(x, v)
+    for cyc in range(3):
+        for s in range(5):
+            g.md_couple_substep()
+            assert o.md_couple_substep() == 0
+            if cyc == 1 and s == 1:
+                cnt = g.counters()
+                g.set_counters(cnt["t_lb"], cnt["t_md"], cnt["subs"])
+            if cyc == 1 and s == 3:
+                g.bind_particles(g.x.clone(), g.v.clone(), g.img.clone())
+        g.lb_step()
+        o.lb_step()
+    Jo, Jg = o.J(), g.transfer().cpu().numpy()
+    assert np.abs(Jg - Jo).max() <= 1e-12 * max(np.abs(Jo).max(), 1e-30)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < 1e-12, err
+    check_particles(g, o, shape, 1e-12, 1e-4)
+
+
 @pytest.mark.parametrize("variant", [1, 2])
 def test_populations_replaced_mid_interval(lb, orc, variant):
     """Populations replaced from outside between two MD steps of an interval
