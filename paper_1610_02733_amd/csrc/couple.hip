@@ -80,8 +80,24 @@ __global__ __launch_bounds__(kBlock) void k_refill(CoupleArgs<T> a) {
     qz = quad_sum(qz);
     const T mine = c == 0 ? qx : (c == 1 ? qy : (c == 2 ? qz : T(1) / ((T)m.rho0 + drho)));
     a.cc[(size_t)p * 32 + sl] = mine;
-    if (c == 0) claim_site(a, m.site_off + site);
-    if (sl == 0 && a.own_on) a.owner[m.site_off + site] = (int32_t)p;  // corner 0: the base
+    // claims (claim_site): corners k and k ^ 1 (4 lanes apart) lie in one
+    // row, most often in one 64-bit mark word, and then one atomic sets both
+    // bits; each corner reads its own bit's old value (a corner that
+    // coincides with its partner, on an axis of one site, is claimed twice)
+    const int gs = m.site_off + site;
+    const int gs_pair = __shfl_xor(gs, 4, kRefillLanes);
+    const bool same_word = (gs >> 6) == (gs_pair >> 6);
+    const bool lead = (k & 1) == 0 || !same_word;
+    unsigned long long old = 0;
+    if (c == 0 && lead) {
+      unsigned long long bits = 1ull << (gs & 63);
+      if (same_word) bits |= 1ull << (gs_pair & 63);
+      old = atomicOr(a.mark + (gs >> 6), bits);
+    }
+    const unsigned long long old_pair = __shfl_xor(old, 4, kRefillLanes);
+    if (c == 0 && (((lead ? old : old_pair) >> (gs & 63)) & 1ull || gs == gs_pair))
+      reinterpret_cast<T*>(a.J + gs)[3] = T(1);
+    if (sl == 0 && a.own_on) a.owner[gs] = (int32_t)p;  // corner 0: the cube's base
   }
 }
 
@@ -120,8 +136,30 @@ __global__ __launch_bounds__(kBlock) void k_refill3(CoupleArgs<T> a) {
     T drho, jx, jy, jz;
     moments_deviation<T>(d, drho, jx, jy, jz);
     *cache_entry<1>(a, p, k) = Vec4<T>{jx, jy, jz, T(1) / ((T)m.rho0 + drho)};
-    claim_site(a, m.site_off + site);
-    if (k == 0 && a.own_on) a.owner[m.site_off + site] = (int32_t)p;  // the stencil's base
+    // claims (claim_site): the three sites of a row (lanes k - ox .. k - ox
+    // + 2) most often share a 64-bit mark word, and then the row's first
+    // lane sets their bits with one atomic; each site reads its own bit's
+    // old value (sites that coincide, on an axis shorter than the stencil,
+    // are claimed more than once)
+    const int gs = m.site_off + site;
+    const int ox = k % 3, lead = (int)(t & 31) - ox;
+    const int g0 = __shfl(gs, lead, 32), g1 = __shfl(gs, lead + 1, 32),
+              g2 = __shfl(gs, lead + 2, 32);
+    const bool covered = ox > 0 && (gs >> 6) == (g0 >> 6);
+    unsigned long long old = 0;
+    if (!covered) {
+      unsigned long long bits = 1ull << (gs & 63);
+      if (ox == 0) {
+        if ((g1 >> 6) == (gs >> 6)) bits |= 1ull << (g1 & 63);
+        if ((g2 >> 6) == (gs >> 6)) bits |= 1ull << (g2 & 63);
+      }
+      old = atomicOr(a.mark + (gs >> 6), bits);
+    }
+    const unsigned long long old_lead = __shfl(old, lead, 32);
+    const bool dup = (gs == g0) + (gs == g1) + (gs == g2) > 1;
+    if ((((covered ? old_lead : old) >> (gs & 63)) & 1ull) || dup)
+      reinterpret_cast<T*>(a.J + gs)[3] = T(1);
+    if (k == 0 && a.own_on) a.owner[gs] = (int32_t)p;  // the stencil's base
   }
 }
 
