@@ -426,17 +426,20 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
       if (gs >= 0 && !sh_[jj]) {
         const Vec4<T> nv{jv_[jj].x + ax, jv_[jj].y + ay, jv_[jj].z + az, T(0)};
-        *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = nv;
+        if (!a.final_step) *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = nv;
         if (leave) a.J[gs] = nv;
       }
       if (gs >= 0 && sh_[jj]) {
         const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
         a.lsite[e] = gs;
         a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
-        if (dec_[jj]) *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = Vec4<T>{T(0), T(0), T(0), T(1)};
+        if (dec_[jj] && !a.final_step)
+          *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = Vec4<T>{T(0), T(0), T(0), T(1)};
       }
     }
-    if (moved && k0 == 0)
+    // (after the interval's last MD step the next refill gathers and claims
+    // every particle's stencil: moved particles need no after-step work)
+    if (moved && k0 == 0 && !a.final_step)
       reinterpret_cast<int4*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
           make_int4((int)p, new_cell, old_cell, 0);
     __syncthreads();

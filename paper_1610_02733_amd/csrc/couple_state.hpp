@@ -53,6 +53,9 @@ struct CoupleArgs {
   int retag;    // the cache was refilled for this step: sharing comes from the w words of J
   int last;     // the interval's last MD step: every transfer is left in J
   int own_on;   // own transfers in use (else every step reads J and leaves its transfers there)
+  int final_step;  // the interval's last MD step: the own entries and the cache of a
+                   // particle that changes stencils are not needed after it (the next
+                   // interval starts with a refill)
   int variant;
   int single;   // one replica: its constants are uniform across the grid
 };
@@ -462,6 +465,7 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.own_on = c->plan.any_forces2 ? 0 : 1;
   a.retag = a.own_on ? 0 : 1;
   a.last = (substep == c->plan.n_sub - 1 || !a.own_on) ? 1 : 0;
+  a.final_step = substep == c->plan.n_sub - 1 ? 1 : 0;
   a.variant = c->p[0].variant;
   a.single = c->plan.R == 1 ? 1 : 0;
   return a;
