@@ -111,14 +111,16 @@ def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup, stencil=0, sort_
     for _ in range(warmup):
         cycle()
     torch.cuda.synchronize()
-    # HIP events bracket the collide-stream launch of every 4th cycle, and
-    # the MD steps (corner refill included) of every 4th cycle offset by 2
-    # (an event pair between kernels costs a few microseconds of idle time)
-    every = 4
+    # HIP events bracket the collide-stream launch of every 10th cycle, and
+    # the MD steps (corner refill included) of every 10th cycle offset by 5
+    # (an event between two kernels lets the queue drain before the next
+    # launch, which costs idle time, so they are kept sparse)
+    every = 10
+    half = every // 2
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, every)]
     ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, every)]
-    ev_p0 = [torch.cuda.Event(enable_timing=True) for _ in range(2, steps, every)]
-    ev_p1 = [torch.cuda.Event(enable_timing=True) for _ in range(2, steps, every)]
+    ev_p0 = [torch.cuda.Event(enable_timing=True) for _ in range(half, steps, every)]
+    ev_p1 = [torch.cuda.Event(enable_timing=True) for _ in range(half, steps, every)]
     t0 = time.perf_counter()
     for k in range(steps):
         # spatial reordering of the particles at LB-step boundaries, timed
@@ -126,7 +128,7 @@ def run_variant(lbmd, torch, cfg, variant, x, v, steps, warmup, stencil=0, sort_
             sim.sort_particles()
         if k % every == 0:
             cycle(ev_a[k // every], ev_b[k // every])
-        elif k % every == 2:
+        elif k % every == half:
             cycle(ev_p1[k // every], None, ev_p0[k // every])
         else:
             cycle()
