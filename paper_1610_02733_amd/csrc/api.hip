@@ -75,6 +75,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   pl.prec = p[0].precision;
   pl.n_sub = p[0].n_sub;
   pl.Stot = pl.Ntot = pl.Ctot = 0;
+  pl.cell_cap = 0;
   pl.nitems = 0;
   pl.any_forces2 = false;
   pl.row_replicas = 0;
@@ -88,6 +89,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
     pl.Stot += (S + 63) / 64 * 64;
     pl.Ntot += p[r].n_particles;
     pl.Ctot += force_cells(p + r);
+    pl.cell_cap = std::max(pl.cell_cap, force_cell_capacity(p + r));
     pl.nitems += (int)((S + kBlock - 1) / kBlock);
     pl.any_forces2 = pl.any_forces2 || (p[r].force_model >= 2 && p[r].n_particles > 0);
   }
@@ -129,12 +131,10 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.slist_delta = o; o = up(o + nent * 4 * t);
   L.mlist = o; o = up(o + nent * 8);  // kBlock / lanes int4 per segment, lanes >= 2
   L.seg_count = o; o = up(o + 2 * (size_t)pl.nseg * 4);
-  L.bin_count = o; o = up(o + C * 4);
-  L.bin_start = o; o = up(o + (C + 1) * 4);
-  L.bin_tiles = o; o = up(o + ((C + 1023) / 1024 + 1) * 4);
-  L.bin_of = o; o = up(o + N * 4);
-  L.bin_rank = o; o = up(o + N * 4);
-  L.bin_sorted = o; o = up(o + N * 4);
+  L.bin_count = o; o = up(o + (2 * C + 2) * 4);
+  L.bin_of = o; o = up(o + 2 * N * 4);
+  L.bin_slot = o; o = up(o + C * (size_t)pl.cell_cap * 4);
+  L.bin_ovf = o; o = up(o + N * 4);
   L.sort_keys = o; o = up(o + 2 * N * 8);
   L.sort_vals = o; o = up(o + 2 * N * 4);
   L.sort_temp = o; o = up(o + sort_temp_bytes((int64_t)N));
@@ -641,6 +641,9 @@ int lbmd_set_counters(lbmd* c, int64_t t_lb, int64_t t_md, int32_t subs) {
   c->subs = subs;
   int rc = fail(c, write_clock(c));
   if (!rc) rc = fail(c, reset_stencil_records(c));
+  // the force cells are kept in halves by MD-step parity: bin again under
+  // the new count
+  if (!rc && c->bound && c->plan.any_forces2) rc = fail(c, launch_forces(c));
   if (rc) return rc;
   return fail(c, invalidate_corner_cache(c));
 }

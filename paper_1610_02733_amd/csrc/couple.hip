@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       if (!live && k0 == 0) {
         a.flags[0] = 1;
         if (Rec) a.rec[p] = __builtin_nan("");
-        if (Bin) a.bin[p] = -1;
+        if (Bin) a.bin[((t_md + 1) & 1) * N + p] = -1;
       }
     }
     if (live) {
@@ -405,13 +405,16 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         }
       }
       if (Bin && k0 == 0) {
-        // force cell at the new position, for the force kernel that follows
+        // force cell at the new position (MD step t_md + 1), for the force
+        // kernel that follows
+        const int par = (int)((t_md + 1) & 1);
         if (m.force_model >= 2 && isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
           const int cb = m.cell_off + local_cell(Xn, m);
-          a.bin[p] = cb;
-          a.bin_rank[p] = atomicAdd(a.bin_count + cb, 1);
+          a.bin[par * N + p] = cb;
+          cell_insert(a.bin_count + par * a.ncells, a.bin_slot, a.bin_ovf,
+                      a.bin_count + 2 * a.ncells + par, a.cell_cap, cb, (int)p);
         } else {
-          a.bin[p] = -1;
+          a.bin[par * N + p] = -1;
         }
       }
       // the next MD step needs other sites if the stencil moved (a

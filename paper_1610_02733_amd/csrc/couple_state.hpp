@@ -44,10 +44,15 @@ struct CoupleArgs {
                                  //   stencil bases, -),
   int32_t* __restrict__ mseg;    //   their number in the segment
   // force cells (position-dependent forces): the coupling kernel bins the
-  // particles at their new positions for the force kernel
-  int32_t* __restrict__ bin_count;  // [cells] particles per cell (zero on entry)
-  int32_t* __restrict__ bin;        // [N] cell of each particle (-1: none)
-  int32_t* __restrict__ bin_rank;   // [N] slot inside the cell
+  // particles at their new positions for the force kernel (cell_insert)
+  int32_t* __restrict__ bin_count;  // [2][cells] particles per cell, then [2] overflow
+                                    //   lengths; the half of the step's parity is zero
+                                    //   on entry
+  int32_t* __restrict__ bin;        // [2][N] cell of each particle (-1: none)
+  int32_t* __restrict__ bin_slot;   // [cells][cell_cap] particles of each cell
+  int32_t* __restrict__ bin_ovf;    // [N] particles past their cell's capacity
+  int64_t ncells;
+  int cell_cap;
   int64_t N;    // particles over all replicas
   int substep;  // MD step inside the LB interval
   int retag;    // the cache was refilled for this step: sharing comes from the w words of J
@@ -61,6 +66,28 @@ struct CoupleArgs {
 };
 
 // Cache entry k of particle p: (jx, jy, jz, 1/rho) of stencil site k.
+// Force cells.  Positions at MD step t (global count) are binned into the
+// half t mod 2 of the double-buffered counts; the force kernel that reads
+// one half clears the other at the cells it was filled at (the particles'
+// cells one MD step earlier), so a half is zero again before the next
+// binning into it, with no pass over all cells.
+__device__ __forceinline__ int bin_parity(const Clock* clk, int pos_step) {
+  return (int)((clk->t_md + pos_step) & 1);
+}
+
+// Particle p into cell cb: the first cap particles of a cell take its slots,
+// later ones go to the overflow list (its length at ovf_n), which the force
+// kernel scans in full, so no capacity bounds the result.
+__device__ __forceinline__ void cell_insert(int32_t* __restrict__ cnt, int32_t* __restrict__ slot,
+                                            int32_t* __restrict__ ovf, int32_t* __restrict__ ovf_n,
+                                            int cap, int cb, int p) {
+  const int r = atomicAdd(cnt + cb, 1);
+  if (r < cap)
+    slot[(int64_t)cb * cap + r] = p;
+  else
+    ovf[atomicAdd(ovf_n, 1)] = p;
+}
+
 template <int ST = 0, typename T>
 __device__ __forceinline__ Vec4<T>* cache_entry(const CoupleArgs<T>& a, int64_t p, int k) {
   return reinterpret_cast<Vec4<T>*>(a.cc) + (size_t)p * Stencil<ST>::kSites + k;
@@ -454,7 +481,10 @@ inline CoupleArgs<T> couple_args(Context* c, int substep) {
   a.mseg = (int32_t*)at(c, L.seg_count) + c->plan.nseg;
   a.bin_count = (int32_t*)at(c, L.bin_count);
   a.bin = (int32_t*)at(c, L.bin_of);
-  a.bin_rank = (int32_t*)at(c, L.bin_rank);
+  a.bin_slot = (int32_t*)at(c, L.bin_slot);
+  a.bin_ovf = (int32_t*)at(c, L.bin_ovf);
+  a.ncells = c->plan.Ctot;
+  a.cell_cap = c->plan.cell_cap;
   a.N = c->plan.Ntot;
   a.substep = substep;
   // Own transfers pay where particles mostly keep their sites to themselves.

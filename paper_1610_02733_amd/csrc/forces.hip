@@ -3,8 +3,7 @@
 // model 2, harmonic bonds between consecutive beads of a chain and the purely
 // repulsive WCA potential between all pairs; model 3, the paper's
 // Kremer-Grest polymer (Sec. 3), FENE bonds and the Lennard-Jones potential
-// cut at 2^(7/6) sigma.  Also the counting-sort binning of particles
-// into cells (histogram, three-level exclusive scan, scatter).
+// cut at 2^(7/6) sigma.  Also the binning of particles into cells.
 #include <algorithm>
 #include <cmath>
 
@@ -17,105 +16,40 @@ namespace lbmd_impl {
 // nb[0] x nb[1] x nb[2] cells of edge L / nb >= the pair cut-off (local_cell);
 // cells of all replicas share one global index space (offset cell_off).
 // Non-finite particles go to no cell (they are left out of the force loop).
-// After an MD step the coupling kernel has already counted the particles
-// into their cells (it knows the new positions first), so only the scan and
-// the scatter follow; k_bin_count serves the binning at bound positions.
+// A cell holds up to cell_cap particles in slots of its own, taken in the
+// order of an atomic count; the rest go to an overflow list (cell_insert).
+// After an MD step the coupling kernel bins the particles (it knows the new
+// positions first), so the force kernel follows it directly, and it clears
+// the other half of the counts for the next MD step (bin_parity).  At bound
+// positions both halves are cleared and k_bin_count bins the particles.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bin_clear(int32_t* __restrict__ count, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) count[i] = 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__ x, int64_t N,
                                                       const RepMD* __restrict__ md,
                                                       const int32_t* __restrict__ part_rep,
+                                                      const Clock* __restrict__ clock,
+                                                      int pos_step, int64_t ncells, int cap,
                                                       int32_t* __restrict__ count,
                                                       int32_t* __restrict__ bin,
-                                                      int32_t* __restrict__ rank) {
+                                                      int32_t* __restrict__ slot,
+                                                      int32_t* __restrict__ ovf) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= N) return;
+  const int par = bin_parity(clock, pos_step);
+  bin[(1 - par) * N + p] = -1;  // nothing of the other half to clear
   const double X[3] = {x[p], x[N + p], x[2 * N + p]};
   const RepMD& m = md[part_rep[p]];
   if (m.force_model < 2 || !(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) {
-    bin[p] = -1;
+    bin[par * N + p] = -1;
     return;
   }
   const int c = m.cell_off + local_cell(X, m);
-  bin[p] = c;
-  rank[p] = atomicAdd(count + c, 1);
-}
-
-// Exclusive scan of the n cell counts in two launches: per-block scans
-// (kScanTile cells per block, which also reset the counts) and a single-block
-// scan of the tile totals.  The start of cell c is then the in-tile scan plus
-// its tile's offset (bin_begin); the total sits at index n.  (Folding the
-// second launch into the first with a last-block counter needs a device-wide
-// fence in every block, which on this multi-die part costs far more than the
-// launch.)
-constexpr int kScanTile = 1024;
-
-__device__ __forceinline__ int block_exclusive_scan(int v, int* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  return incl - v;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(int32_t* __restrict__ in, int64_t n,
-                                                       int32_t* __restrict__ out,
-                                                       int32_t* __restrict__ tile_sum) {
-  __shared__ int sh[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
-  int v[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    v[q] = base + q < n ? in[base + q] : 0;
-    if (base + q < n) in[base + q] = 0;  // counts start from zero at the next binning
-  }
-  const int tsum = v[0] + v[1] + v[2] + v[3];
-  int run = block_exclusive_scan(tsum, sh);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (base + q < n) out[base + q] = run;
-    run += v[q];
-  }
-  if (threadIdx.x == kBlock - 1) tile_sum[blockIdx.x] = run;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t* __restrict__ tile_sum, int ntiles,
-                                                     int32_t* __restrict__ total) {
-  __shared__ int sh[kBlock];
-  // each thread scans a contiguous chunk, then the chunk sums are scanned
-  const int per = (ntiles + kBlock - 1) / kBlock;
-  const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += tile_sum[i];
-  int run = block_exclusive_scan(s, sh);
-  for (int i = lo; i < hi; ++i) {
-    const int v = tile_sum[i];
-    tile_sum[i] = run;
-    run += v;
-  }
-  if (threadIdx.x == kBlock - 1) *total = run;
-}
-
-__device__ __forceinline__ int bin_begin(const int32_t* __restrict__ start,
-                                         const int32_t* __restrict__ tiles, int64_t n, int c) {
-  return c == n ? start[n] : start[c] + tiles[c / kScanTile];
-}
-
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restrict__ bin,
-                                                        const int32_t* __restrict__ rank,
-                                                        const int32_t* __restrict__ start,
-                                                        const int32_t* __restrict__ tiles,
-                                                        int64_t n, int64_t N,
-                                                        int32_t* __restrict__ sorted) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= N) return;
-  const int c = bin[p];
-  if (c >= 0) sorted[bin_begin(start, tiles, n, c) + rank[p]] = (int32_t)p;
+  bin[par * N + p] = c;
+  cell_insert(count + par * ncells, slot, ovf, count + 2 * ncells + par, cap, c, (int)p);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,15 +58,19 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 // rounding), with minimum-image separations.  Force models 0 and 1 give zero
 // or the constant f_ext.
 //
-// 32 lanes per particle: lanes 0-26 scan one neighbouring cell each (offsets
-// -1, 0, +1 per axis; on an axis with fewer than 3 cells, cells 0, 1, 2 of
-// that axis instead, so every distinct cell is scanned once), lane 27 adds
-// the two chain bonds; the lane sums are a butterfly reduction.  Lane 0
-// stores the force and, after an MD step, applies the second half-kick of
-// velocity Verlet (new conservative force + the coupling force held over the
-// step).  After an MD step the launch also carries the step's after-step
-// work in extra blocks: this kernel runs after every particle of the step
-// has read the transfer field.
+// 32 lanes per particle: lanes 0-26 scan the slots of one neighbouring cell
+// each (offsets -1, 0, +1 per axis; on an axis with fewer than 3 cells,
+// cells 0, 1, 2 of that axis instead, so every distinct cell is scanned
+// once), lane 27 adds the two chain bonds, lane 28 scans the overflow list
+// (empty unless a cell holds more than cell_cap particles; a pair closer
+// than the cut-off lies in neighbouring cells, so the list's particles need
+// only the distance test), and lane 29 clears the other half of the counts
+// at the particle's cell of one MD step earlier; the lane sums are a
+// butterfly reduction.  Lane 0 stores the force and, after an MD step,
+// applies the second half-kick of velocity Verlet (new conservative force +
+// the coupling force held over the step).  After an MD step the launch also
+// carries the step's after-step work in extra blocks: this kernel runs after
+// every particle of the step has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -155,13 +93,35 @@ struct ForceArgs {
   const double* __restrict__ fc_held;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
-  const int32_t* __restrict__ bin;
-  const int32_t* __restrict__ start;
-  const int32_t* __restrict__ tiles;
-  const int32_t* __restrict__ sorted;
+  const Clock* __restrict__ clock;
+  int32_t* __restrict__ count;  // [2][ncells] + [2] overflow lengths (CoupleArgs::bin_count)
+  int32_t* __restrict__ bin;    // [2][N]
+  const int32_t* __restrict__ slot;
+  const int32_t* __restrict__ ovf;
   int64_t N;
   int64_t ncells;
+  int cap;
+  int pos_step;  // the positions are those of MD step clock->t_md + pos_step
 };
+
+// Pair force of the WCA or cut Lennard-Jones potential on the particle at X
+// from particle q, added to F when q lies within the cut-off.
+__device__ __forceinline__ void add_pair_force(const double* __restrict__ x, int64_t N,
+                                               const double X[3], int q, const RepMD& m,
+                                               double rc2, double sig2, double F[3]) {
+  double dx[3], r2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    dx[d] = min_image(X[d] - x[d * N + q], m.L[d]);
+    r2 += dx[d] * dx[d];
+  }
+  if (r2 >= rc2) return;
+  const double sr2 = sig2 / r2;
+  const double sr6 = sr2 * sr2 * sr2;
+  const double fm = 24.0 * m.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
+}
 
 // Blocks [0, nfb) compute the forces; with AfterST >= 0 (after an MD step,
 // not recording) blocks [nfb, nfb + 2 nseg) do the after-step work
@@ -177,6 +137,10 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
     }
   }
   const int64_t N = a.N;
+  const int par = bin_parity(a.clock, a.pos_step);
+  const int32_t* __restrict__ cnt = a.count + par * a.ncells;
+  // the overflow length of the other half, for the binning of the next MD step
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.count[2 * a.ncells + (1 - par)] = 0;
   // lanes come in whole particles (32 | kBlock), as the shuffles require
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kForceLanes;
        t += nfb * kBlock) {
@@ -184,7 +148,12 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
     const int lane = (int)(t & (kForceLanes - 1));
     const RepMD& m = a.md[a.part_rep[p]];
     double F[3] = {0.0, 0.0, 0.0};
-    const int c = m.force_model >= 2 ? a.bin[p] : -1;
+    const bool cells = m.force_model >= 2;
+    if (cells && lane == 29) {
+      const int old = a.bin[(1 - par) * N + p];
+      if (old >= 0) a.count[(1 - par) * a.ncells + old] = 0;
+    }
+    const int c = cells ? a.bin[par * N + p] : -1;
     if (c >= 0) {
       const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
       // pair cut-off squared: (2^(1/6) sigma)^2 (WCA) or (2^(7/6) sigma)^2
@@ -209,22 +178,11 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
         }
         if (use) {
           const int cell = m.cell_off + q3[0] + m.nb[0] * (q3[1] + m.nb[1] * q3[2]);
-          const int s1 = bin_begin(a.start, a.tiles, a.ncells, cell + 1);
-          for (int s = bin_begin(a.start, a.tiles, a.ncells, cell); s < s1; ++s) {
-            const int q = a.sorted[s];
-            if (q == p) continue;
-            double dx[3], r2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              dx[d] = min_image(X[d] - a.x[d * N + q], m.L[d]);
-              r2 += dx[d] * dx[d];
-            }
-            if (r2 >= rc2) continue;
-            const double sr2 = sig2 / r2;
-            const double sr6 = sr2 * sr2 * sr2;
-            const double fm = 24.0 * m.wca_eps * (2.0 * sr6 * sr6 - sr6) / r2;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
+          const int n = min(cnt[cell], a.cap);
+          const int32_t* __restrict__ sl = a.slot + (int64_t)cell * a.cap;
+          for (int s = 0; s < n; ++s) {
+            const int q = sl[s];
+            if (q != p) add_pair_force(a.x, N, X, q, m, rc2, sig2, F);
           }
         }
       } else if (lane == 27) {
@@ -251,6 +209,13 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
           }
 #pragma unroll
           for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
+        }
+      } else if (lane == 28) {
+        const int no = a.count[2 * a.ncells + par];
+        const int rep = a.part_rep[p];
+        for (int e = 0; e < no; ++e) {
+          const int q = a.ovf[e];
+          if (q != p && a.part_rep[q] == rep) add_pair_force(a.x, N, X, q, m, rc2, sig2, F);
         }
       }
     }
@@ -289,8 +254,17 @@ int64_t force_cells(const lbmd_params* p) {
   return n;
 }
 
+// Particle slots per force cell.  A WCA cell (edge ~1.12 sigma, ~1.4
+// sigma^3) holds about one bead even at melt density; a Kremer-Grest cell
+// (edge ~2.24 sigma, ~11 sigma^3) holds about ten there.  Particles past the
+// capacity are still found, through the overflow list, at a cost per pair.
+int force_cell_capacity(const lbmd_params* p) {
+  if (p->force_model < 2) return 0;
+  return p->force_model == 3 ? 32 : 8;
+}
+
 template <typename T>
-static ForceArgs<T> force_args(Context* c) {
+static ForceArgs<T> force_args(Context* c, int pos_step) {
   const Layout& L = c->plan.lay;
   ForceArgs<T> a;
   a.x = (const double*)c->x;
@@ -299,44 +273,40 @@ static ForceArgs<T> force_args(Context* c) {
   a.fc_held = (const double*)at(c, L.fc_held);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
-  a.bin = (const int32_t*)at(c, L.bin_of);
-  a.start = (const int32_t*)at(c, L.bin_start);
-  a.tiles = (const int32_t*)at(c, L.bin_tiles);
-  a.sorted = (const int32_t*)at(c, L.bin_sorted);
+  a.clock = (const Clock*)at(c, L.clock);
+  a.count = (int32_t*)at(c, L.bin_count);
+  a.bin = (int32_t*)at(c, L.bin_of);
+  a.slot = (const int32_t*)at(c, L.bin_slot);
+  a.ovf = (const int32_t*)at(c, L.bin_ovf);
   a.N = c->plan.Ntot;
   a.ncells = c->plan.Ctot;
+  a.cap = c->plan.cell_cap;
+  a.pos_step = pos_step;
   return a;
 }
 
-// Bin the particles of bead-spring replicas (models 2, 3) into their cells.
-// counted: the coupling kernel of the MD step already filled count, bin
-// and rank.
-static hipError_t launch_binning(Context* c, bool counted) {
-  const int64_t N = c->plan.Ntot;
+// Bin the particles of bead-spring replicas (models 2, 3) at the current
+// positions, those of MD step clock->t_md + pos_step, from scratch: both
+// halves of the counts are cleared first (a fill kernel, so the sequence
+// may be captured in a graph).
+static hipError_t launch_binning(Context* c, int pos_step) {
+  const int64_t N = c->plan.Ntot, C = c->plan.Ctot;
   const Layout& L = c->plan.lay;
-  const int pb = (int)((N + kBlock - 1) / kBlock);
   int32_t* count = (int32_t*)at(c, L.bin_count);
-  int32_t* tiles = (int32_t*)at(c, L.bin_tiles);
-  int32_t* rank = (int32_t*)at(c, L.bin_rank);
-  int32_t* bin = (int32_t*)at(c, L.bin_of);
-  int32_t* start = (int32_t*)at(c, L.bin_start);
-  const int64_t n = c->plan.Ctot;
-  if (!counted)
-    hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(kBlock), 0, c->stream, (const double*)c->x,
-                       N, (const RepMD*)at(c, L.rep_md), (const int32_t*)at(c, L.part_rep), count,
-                       bin, rank);
-  const int ntiles = (int)((n + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, c->stream, count, n, start,
-                     tiles);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, c->stream, tiles, ntiles, start + n);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(kBlock), 0, c->stream, bin, rank, start, tiles,
-                     n, N, (int32_t*)at(c, L.bin_sorted));
+  const int64_t nc = 2 * C + 2;
+  hipLaunchKernelGGL(k_bin_clear, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, count, nc);
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, (const double*)c->x, N, (const RepMD*)at(c, L.rep_md),
+                     (const int32_t*)at(c, L.part_rep), (const Clock*)at(c, L.clock), pos_step,
+                     C, c->plan.cell_cap, count, (int32_t*)at(c, L.bin_of),
+                     (int32_t*)at(c, L.bin_slot), (int32_t*)at(c, L.bin_ovf));
   return hipGetLastError();
 }
 
 template <typename T, bool Kick, int AfterST>
-static hipError_t forces_t(Context* c, int substep = 0) {
-  const ForceArgs<T> a = force_args<T>(c);
+static hipError_t forces_t(Context* c, int pos_step, int substep = 0) {
+  const ForceArgs<T> a = force_args<T>(c, pos_step);
   const int64_t nfb = (a.N * kForceLanes + kBlock - 1) / kBlock;
   CoupleArgs<T> ca{};
   int64_t nseg = 0;
@@ -359,8 +329,9 @@ static hipError_t forces_t(Context* c, int substep = 0) {
 hipError_t launch_forces(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e;
-  if (c->plan.any_forces2 && (e = launch_binning(c, false)) != hipSuccess) return e;
-  return c->plan.prec == 32 ? forces_t<float, false, -1>(c) : forces_t<double, false, -1>(c);
+  if (c->plan.any_forces2 && (e = launch_binning(c, c->subs)) != hipSuccess) return e;
+  return c->plan.prec == 32 ? forces_t<float, false, -1>(c, c->subs)
+                            : forces_t<double, false, -1>(c, c->subs);
 }
 
 // Forces at the bound positions; the corner cache is stale from here on.
@@ -370,21 +341,24 @@ hipError_t launch_init_forces(Context* c) {
   return invalidate_corner_cache(c);
 }
 
-// After an MD step of replicas with position-dependent forces: binning,
-// forces at the new positions, the second half-kick and the step's
-// after-step work in the same launch (so the coupling step launches no
-// after-step kernel of its own).
+// After an MD step of replicas with position-dependent forces: forces at
+// the new positions (binned by the coupling kernel, or here while
+// recording), the second half-kick and the step's after-step work in the
+// same launch (so the coupling step launches no after-step kernel of its
+// own).
 template <typename T>
 static hipError_t forces_and_kick_t(Context* c, int substep) {
-  if (c->rec_part) return forces_t<T, true, -1>(c, substep);
-  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c, substep)
-                              : forces_t<T, true, 0>(c, substep);
+  if (c->rec_part) return forces_t<T, true, -1>(c, substep + 1, substep);
+  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c, substep + 1, substep)
+                              : forces_t<T, true, 0>(c, substep + 1, substep);
 }
 
 hipError_t launch_forces_and_kick(Context* c, int substep) {
   if (c->plan.Ntot == 0) return hipSuccess;
-  hipError_t e = launch_binning(c, !c->rec_part);
-  if (e != hipSuccess) return e;
+  if (c->rec_part) {
+    const hipError_t e = launch_binning(c, substep + 1);
+    if (e != hipSuccess) return e;
+  }
   return c->plan.prec == 32 ? forces_and_kick_t<float>(c, substep)
                             : forces_and_kick_t<double>(c, substep);
 }

@@ -97,12 +97,11 @@ struct Layout {
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
   size_t mlist;      // [segments * kBlock / lanes] int4: particles whose stencil moved, new and old base
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
-  size_t bin_count;  // [Ctot] int32: particles per force cell
-  size_t bin_start;  // [Ctot + 1] int32: exclusive scan of bin_count
-  size_t bin_tiles;  // [ceil(Ctot / 1024) + 1] int32: scan tile totals
-  size_t bin_of;     // [Ntot] int32: global force cell of each particle (-1: none)
-  size_t bin_rank;   // [Ntot] int32: slot inside the cell
-  size_t bin_sorted; // [Ntot] int32: particles ordered by cell
+  size_t bin_count;  // [2 Ctot + 2] int32: particles per force cell, two halves by MD-step
+                     // parity, then the two overflow-list lengths (cell_insert)
+  size_t bin_of;     // [2][Ntot] int32: global force cell of each particle (-1: none)
+  size_t bin_slot;   // [Ctot][cell_cap] int32: particles of each cell
+  size_t bin_ovf;    // [Ntot] int32: particles past their cell's capacity
   size_t sort_keys;  // [2][Ntot] uint64: spatial sort keys (in, out)
   size_t sort_vals;  // [2][Ntot] int32: particle indices (in, out = the permutation)
   size_t sort_temp;  // radix-sort temporary storage
@@ -129,6 +128,7 @@ struct Plan {
   int64_t P;     // sites per population buffer (= Stot; a buffer holds 19 * P values)
   int64_t Ntot;  // particles
   int64_t Ctot;  // force cells
+  int cell_cap;  // particle slots per force cell
   int nitems;    // 256-site work items of the LB kernels
   int64_t nseg;  // segments (block-sized stretches) of the widest coupling launch
   int row_replicas;  // replicas on the collide-stream row path (see row_path)
@@ -251,6 +251,7 @@ int couple_lane_candidates(int stencil, int out[4]);
 hipError_t launch_forces(Context* c);
 hipError_t launch_forces_and_kick(Context* c, int substep);
 int64_t force_cells(const lbmd_params* p);
+int force_cell_capacity(const lbmd_params* p);
 // nx is 64, 128 or 256 and the replica's 19 S population entries have 32-bit
 // offsets: the collide-stream kernel's row path (aligned rows, DPP x shift)
 inline bool row_path(const lbmd_params& p) {

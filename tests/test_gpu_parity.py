@@ -417,6 +417,35 @@ def test_polymer_small_box_cell_grid(lb, orc):
     check_particles(g, o, shape, 1e-12, 1e-3)
 
 
+def _packed_beads(n, region, min_dist, seed):
+    """n positions in [0.05, region)^3, pairwise at least min_dist apart."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        q = 0.05 + rng.random(3) * (region - 0.05)
+        if all(np.linalg.norm(q - r) >= min_dist for r in pts):
+            pts.append(q)
+    return np.ascontiguousarray(np.array(pts).T)
+
+
+@pytest.mark.parametrize("model,n,box,region,min_dist", [(2, 24, 6, 1.15, 0.3),
+                                                         (3, 48, 9, 2.2, 0.4)])
+def test_crowded_force_cell_overflow(lb, orc, model, n, box, region, min_dist):
+    """More beads in one force cell than it has slots (8 for WCA cells, 32
+    for Kremer-Grest cells): the rest are found through the overflow list,
+    over several MD steps (the list is rebuilt at every step), FP64.  The
+    potentials are scaled down so that the close pairs stay gentle."""
+    shape = (box, box, box)
+    x = _packed_beads(n, region, min_dist, seed=40 + model)
+    v = np.zeros_like(x)
+    kw = dict(kT=0.0, seed=3, n_particles=n, friction=0.5, n_sub=3, variant=2,
+              force_model=model, chain_len=8, k_bond=1e-3, r0_bond=1.0 if model == 2 else 4.0,
+              wca_eps=1e-12, wca_sigma=1.0)
+    g, o, w, rho0 = run_pair(lb, orc, shape, 3, x=x, v=v, precision=64, **kw)
+    assert np.abs(o.particles()[1]).max() > 1e-6  # the pair forces moved the beads
+    check_particles(g, o, shape, 1e-12, 0.0)
+
+
 def test_fast_particles_wrap(lb, orc):
     """Displacements of several box lengths per MD step: positions stay in
     [0, L), image counters agree with the oracle (FP64)."""
