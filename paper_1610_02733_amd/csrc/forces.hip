@@ -127,7 +127,12 @@ __device__ __forceinline__ void add_pair_force(const double* __restrict__ x, int
 // not recording) blocks [nfb, nfb + 2 nseg) do the after-step work
 // of the MD step just taken (after_step_item), which is independent of the
 // forces: it touches J, the claims and the corner cache only.
-template <typename T, bool Kick, int AfterST>
+// One (a single replica): its constants are read once, before the loop
+// (uniform, scalar loads), so the particle's loads need not wait for them.
+// The loads of a particle are issued together where they do not depend on
+// each other: its cell, position and (lane 0) velocity and held coupling
+// force; a cell's count with its first two slots; the two bond partners.
+template <typename T, bool Kick, int AfterST, bool One>
 __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T> ca, int64_t nseg,
                                                    int per, int L, int64_t nfb) {
   if constexpr (AfterST >= 0) {
@@ -137,6 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
     }
   }
   const int64_t N = a.N;
+  RepMD m1;
+  if constexpr (One) m1 = a.md[0];
   const int par = bin_parity(a.clock, a.pos_step);
   const int32_t* __restrict__ cnt = a.count + par * a.ncells;
   // the overflow length of the other half, for the binning of the next MD step
@@ -146,16 +153,26 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
        t += nfb * kBlock) {
     const int64_t p = t / kForceLanes;
     const int lane = (int)(t & (kForceLanes - 1));
-    const RepMD& m = a.md[a.part_rep[p]];
+    RepMD mr;
+    if constexpr (!One) mr = a.md[a.part_rep[p]];
+    const RepMD& m = One ? m1 : mr;
     double F[3] = {0.0, 0.0, 0.0};
+    // (the cells are written for every particle when a replica has them)
     const bool cells = m.force_model >= 2;
-    if (cells && lane == 29) {
-      const int old = a.bin[(1 - par) * N + p];
-      if (old >= 0) a.count[(1 - par) * a.ncells + old] = 0;
-    }
     const int c = cells ? a.bin[par * N + p] : -1;
+    const int old = cells && lane == 29 ? a.bin[(1 - par) * N + p] : -1;
+    const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
+    const bool kick = Kick && lane == 0 && m.split_kick;
+    double vv[3] = {0.0, 0.0, 0.0}, fh[3] = {0.0, 0.0, 0.0};
+    if (kick) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        vv[d] = a.v[d * N + p];
+        fh[d] = a.fc_held[d * N + p];
+      }
+    }
+    if (old >= 0) a.count[(1 - par) * a.ncells + old] = 0;
     if (c >= 0) {
-      const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
       // pair cut-off squared: (2^(1/6) sigma)^2 (WCA) or (2^(7/6) sigma)^2
       const double rc2 = (m.force_model == 2 ? 1.2599210498948732 : 5.0396841995794928) *
                          m.wca_sigma * m.wca_sigma;
@@ -178,37 +195,52 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
         }
         if (use) {
           const int cell = m.cell_off + q3[0] + m.nb[0] * (q3[1] + m.nb[1] * q3[2]);
-          const int n = min(cnt[cell], a.cap);
           const int32_t* __restrict__ sl = a.slot + (int64_t)cell * a.cap;
-          for (int s = 0; s < n; ++s) {
+          // the count and the first two slots at once (cap >= 2; a slot past
+          // the count holds a stale index, replaced by p and not used)
+          const int n = min(cnt[cell], a.cap);
+          const int s0 = sl[0], s1 = sl[1];
+          const int q0 = n > 0 ? s0 : (int)p, q1 = n > 1 ? s1 : (int)p;
+          double F0[3] = {0.0, 0.0, 0.0}, F1[3] = {0.0, 0.0, 0.0};
+          add_pair_force(a.x, N, X, q0, m, rc2, sig2, F0);
+          add_pair_force(a.x, N, X, q1, m, rc2, sig2, F1);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (q0 != p) F[d] += F0[d];
+            if (q1 != p) F[d] += F1[d];
+          }
+          for (int s = 2; s < n; ++s) {
             const int q = sl[s];
             if (q != p) add_pair_force(a.x, N, X, q, m, rc2, sig2, F);
           }
         }
       } else if (lane == 27) {
         // bonds to the chain neighbours: harmonic (model 2) or FENE (model 3,
-        // no finite force at r >= R0)
+        // no finite force at r >= R0); both partners' positions at once
         const int pos = (int)((p - m.part_off) % m.chain_len);
+        const bool has[2] = {pos > 0, pos < m.chain_len - 1};
+        const int64_t qs[2] = {has[0] ? p - 1 : p, has[1] ? p + 1 : p};
+        double dx[2][3], r2[2] = {0.0, 0.0};
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          if ((side == 0 && pos == 0) || (side == 1 && pos == m.chain_len - 1)) continue;
-          const int64_t q = side == 0 ? p - 1 : p + 1;
-          double dx[3], r2 = 0.0;
+        for (int side = 0; side < 2; ++side)
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            dx[d] = min_image(X[d] - a.x[d * N + q], m.L[d]);
-            r2 += dx[d] * dx[d];
+            dx[side][d] = min_image(X[d] - a.x[d * N + qs[side]], m.L[d]);
+            r2[side] += dx[side][d] * dx[side][d];
           }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (!has[side]) continue;
           double fm;
           if (m.force_model == 2) {
-            const double r = sqrt(r2);
+            const double r = sqrt(r2[side]);
             fm = -m.k_bond * (r - m.r0_bond) / r;
           } else {
-            const double x2 = r2 / (m.r0_bond * m.r0_bond);
+            const double x2 = r2[side] / (m.r0_bond * m.r0_bond);
             fm = x2 < 1.0 ? -m.k_bond / (1.0 - x2) : __builtin_nan("");
           }
 #pragma unroll
-          for (int d = 0; d < 3; ++d) F[d] += fm * dx[d];
+          for (int d = 0; d < 3; ++d) F[d] += fm * dx[side][d];
         }
       } else if (lane == 28) {
         const int no = a.count[2 * a.ncells + par];
@@ -226,10 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
       for (int d = 0; d < 3; ++d) {
         if (m.force_model == 1) F[d] = m.f_ext[d];
         a.f[d * N + p] = F[d];
-        if (Kick && m.split_kick) {
-          const double vv = a.v[d * N + p];
-          if (isfinite(vv)) a.v[d * N + p] = vv + m.h * (F[d] + a.fc_held[d * N + p]);
-        }
+        if (kick && isfinite(vv[d])) a.v[d * N + p] = vv[d] + m.h * (F[d] + fh[d]);
       }
     }
   }
@@ -320,8 +349,12 @@ static hipError_t forces_t(Context* c, int pos_step, int substep = 0) {
     nseg = (a.N * L + kBlock - 1) / kBlock;
   }
   const dim3 grid((unsigned)(nfb + 2 * nseg));
-  hipLaunchKernelGGL((k_forces<T, Kick, AfterST>), grid, dim3(kBlock), 0, c->stream, a, ca, nseg,
-                     per, L, nfb);
+  if (c->plan.R == 1)
+    hipLaunchKernelGGL((k_forces<T, Kick, AfterST, true>), grid, dim3(kBlock), 0, c->stream, a,
+                       ca, nseg, per, L, nfb);
+  else
+    hipLaunchKernelGGL((k_forces<T, Kick, AfterST, false>), grid, dim3(kBlock), 0, c->stream, a,
+                       ca, nseg, per, L, nfb);
   return hipGetLastError();
 }
 
