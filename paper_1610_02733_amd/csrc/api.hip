@@ -66,7 +66,7 @@ bool valid_set(const lbmd_params* p, int32_t R) {
     C += force_cells(p + r);
   }
   return S < (int64_t)0x7FFFFFFF - 256 && N < (int64_t)0x7FFFFFFF / 32 &&
-         C < (int64_t)0x7FFFFFFF - 1;
+         C < ((int64_t)1 << 30) - 1;  // two halves of counts: 32-bit entries
 }
 
 Plan make_plan(const lbmd_params* p, int32_t R) {
@@ -132,7 +132,7 @@ Plan make_plan(const lbmd_params* p, int32_t R) {
   L.mlist = o; o = up(o + nent * 8);  // kBlock / lanes int4 per segment, lanes >= 2
   L.seg_count = o; o = up(o + 2 * (size_t)pl.nseg * 4);
   L.bin_count = o; o = up(o + (2 * C + 2) * 4);
-  L.bin_of = o; o = up(o + 2 * N * 4);
+  L.bin_of = o; o = up(o + N * 4);
   L.bin_slot = o; o = up(o + C * (size_t)pl.cell_cap * 4);
   L.bin_ovf = o; o = up(o + N * 4);
   L.sort_keys = o; o = up(o + 2 * N * 8);

@@ -238,6 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   if constexpr (One) m1 = a.md[0];
   // entries of this block's segment in the two lists, counted in LDS
   __shared__ int s_l, s_m;
+  // Bin: the overflow length of the other half, for the binning after this one
+  if (Bin && blockIdx.x == 0 && threadIdx.x == 0) a.bin_count[2 * a.ncells + (int)(t_md & 1)] = 0;
   // lanes come in whole particles (kLanes | kBlock): the lanes of a particle
   // are always active together, as the shuffles require; every thread of a
   // block runs the loop the same number of times (block barriers)
@@ -267,8 +269,10 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     double fc[3] = {0.0, 0.0, 0.0};
     uint32_t lp = 0;
     Vec4<T> cv_[kPer];
+    int old_bin = -1;  // Bin: the particle's count entry of the previous binning
     bool live = t < lanes;
     if (live) {
+      if (Bin && k0 == 0) old_bin = a.bin[p];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         X[d] = a.x[d * N + p];
@@ -294,7 +298,10 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       if (!live && k0 == 0) {
         a.flags[0] = 1;
         if (Rec) a.rec[p] = __builtin_nan("");
-        if (Bin) a.bin[((t_md + 1) & 1) * N + p] = -1;
+        if (Bin) {
+          if (old_bin >= 0) a.bin_count[old_bin] = 0;
+          a.bin[p] = -1;
+        }
       }
     }
     if (live) {
@@ -406,15 +413,17 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       }
       if (Bin && k0 == 0) {
         // force cell at the new position (MD step t_md + 1), for the force
-        // kernel that follows
-        const int par = (int)((t_md + 1) & 1);
+        // kernel that follows; the count entry of the previous binning (the
+        // other half) is cleared for the binning after this one
+        if (old_bin >= 0) a.bin_count[old_bin] = 0;
+        const int half = (int)((t_md + 1) & 1);
         if (m.force_model >= 2 && isfinite(Xn[0]) && isfinite(Xn[1]) && isfinite(Xn[2])) {
           const int cb = m.cell_off + local_cell(Xn, m);
-          a.bin[par * N + p] = cb;
-          cell_insert(a.bin_count + par * a.ncells, a.bin_slot, a.bin_ovf,
-                      a.bin_count + 2 * a.ncells + par, a.cell_cap, cb, (int)p);
+          a.bin[p] = (int32_t)(half * a.ncells + cb);
+          cell_insert(a.bin_count + half * a.ncells, a.bin_slot, a.bin_ovf,
+                      a.bin_count + 2 * a.ncells + half, a.cell_cap, cb, (int)p);
         } else {
-          a.bin[par * N + p] = -1;
+          a.bin[p] = -1;
         }
       }
       // the next MD step needs other sites if the stencil moved (a

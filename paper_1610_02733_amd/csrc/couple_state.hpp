@@ -48,7 +48,8 @@ struct CoupleArgs {
   int32_t* __restrict__ bin_count;  // [2][cells] particles per cell, then [2] overflow
                                     //   lengths; the half of the step's parity is zero
                                     //   on entry
-  int32_t* __restrict__ bin;        // [2][N] cell of each particle (-1: none)
+  int32_t* __restrict__ bin;        // [N] count entry of each particle: half * cells + cell
+                                    //   (-1: none)
   int32_t* __restrict__ bin_slot;   // [cells][cell_cap] particles of each cell
   int32_t* __restrict__ bin_ovf;    // [N] particles past their cell's capacity
   int64_t ncells;
@@ -67,10 +68,12 @@ struct CoupleArgs {
 
 // Cache entry k of particle p: (jx, jy, jz, 1/rho) of stencil site k.
 // Force cells.  Positions at MD step t (global count) are binned into the
-// half t mod 2 of the double-buffered counts; the force kernel that reads
-// one half clears the other at the cells it was filled at (the particles'
-// cells one MD step earlier), so a half is zero again before the next
-// binning into it, with no pass over all cells.
+// half t mod 2 of the double-buffered counts, and each particle's bin entry
+// is its index in the counts (half * cells + cell), so the force kernel
+// needs no step count.  The coupling kernel of MD step t, which bins into
+// one half, clears the other at each particle's previous entry (the half
+// the force kernel of the step before has read), so a half is zero again
+// before the next binning into it, with no pass over all cells.
 __device__ __forceinline__ int bin_parity(const Clock* clk, int pos_step) {
   return (int)((clk->t_md + pos_step) & 1);
 }

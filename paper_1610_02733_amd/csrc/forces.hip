@@ -19,9 +19,9 @@ namespace lbmd_impl {
 // A cell holds up to cell_cap particles in slots of its own, taken in the
 // order of an atomic count; the rest go to an overflow list (cell_insert).
 // After an MD step the coupling kernel bins the particles (it knows the new
-// positions first), so the force kernel follows it directly, and it clears
-// the other half of the counts for the next MD step (bin_parity).  At bound
-// positions both halves are cleared and k_bin_count bins the particles.
+// positions first) and clears the other half of the counts (bin_parity), so
+// the force kernel follows it directly.  At bound positions both halves are
+// cleared and k_bin_count bins the particles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_bin_clear(int32_t* __restrict__ count, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -40,15 +40,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= N) return;
   const int par = bin_parity(clock, pos_step);
-  bin[(1 - par) * N + p] = -1;  // nothing of the other half to clear
   const double X[3] = {x[p], x[N + p], x[2 * N + p]};
   const RepMD& m = md[part_rep[p]];
   if (m.force_model < 2 || !(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) {
-    bin[par * N + p] = -1;
+    bin[p] = -1;
     return;
   }
   const int c = m.cell_off + local_cell(X, m);
-  bin[par * N + p] = c;
+  bin[p] = (int32_t)(par * ncells + c);
   cell_insert(count + par * ncells, slot, ovf, count + 2 * ncells + par, cap, c, (int)p);
 }
 
@@ -64,13 +63,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const double* __restrict__
 // once), lane 27 adds the two chain bonds, lane 28 scans the overflow list
 // (empty unless a cell holds more than cell_cap particles; a pair closer
 // than the cut-off lies in neighbouring cells, so the list's particles need
-// only the distance test), and lane 29 clears the other half of the counts
-// at the particle's cell of one MD step earlier; the lane sums are a
-// butterfly reduction.  Lane 0 stores the force and, after an MD step,
-// applies the second half-kick of velocity Verlet (new conservative force +
-// the coupling force held over the step).  After an MD step the launch also
-// carries the step's after-step work in extra blocks: this kernel runs after
-// every particle of the step has read the transfer field.
+// only the distance test); the lane sums are a butterfly reduction.  The
+// half of the counts comes with the particle's own count entry.  Lane 0
+// stores the force and, after an MD step, applies the second half-kick of
+// velocity Verlet (new conservative force + the coupling force held over the
+// step).  After an MD step the launch also carries the step's after-step
+// work in extra blocks: this kernel runs after every particle of the step
+// has read the transfer field.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
 
@@ -93,15 +92,13 @@ struct ForceArgs {
   const double* __restrict__ fc_held;
   const RepMD* __restrict__ md;
   const int32_t* __restrict__ part_rep;
-  const Clock* __restrict__ clock;
-  int32_t* __restrict__ count;  // [2][ncells] + [2] overflow lengths (CoupleArgs::bin_count)
-  int32_t* __restrict__ bin;    // [2][N]
+  const int32_t* __restrict__ count;  // [2][ncells] + [2] overflow lengths (CoupleArgs::bin_count)
+  const int32_t* __restrict__ bin;    // [N] count entries (CoupleArgs::bin)
   const int32_t* __restrict__ slot;
   const int32_t* __restrict__ ovf;
   int64_t N;
   int64_t ncells;
   int cap;
-  int pos_step;  // the positions are those of MD step clock->t_md + pos_step
 };
 
 // Pair force of the WCA or cut Lennard-Jones potential on the particle at X
@@ -144,10 +141,6 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
   const int64_t N = a.N;
   RepMD m1;
   if constexpr (One) m1 = a.md[0];
-  const int par = bin_parity(a.clock, a.pos_step);
-  const int32_t* __restrict__ cnt = a.count + par * a.ncells;
-  // the overflow length of the other half, for the binning of the next MD step
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.count[2 * a.ncells + (1 - par)] = 0;
   // lanes come in whole particles (32 | kBlock), as the shuffles require
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N * kForceLanes;
        t += nfb * kBlock) {
@@ -158,9 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
     const RepMD& m = One ? m1 : mr;
     double F[3] = {0.0, 0.0, 0.0};
     // (the cells are written for every particle when a replica has them)
-    const bool cells = m.force_model >= 2;
-    const int c = cells ? a.bin[par * N + p] : -1;
-    const int old = cells && lane == 29 ? a.bin[(1 - par) * N + p] : -1;
+    const int g = m.force_model >= 2 ? a.bin[p] : -1;
     const double X[3] = {a.x[p], a.x[N + p], a.x[2 * N + p]};
     const bool kick = Kick && lane == 0 && m.split_kick;
     double vv[3] = {0.0, 0.0, 0.0}, fh[3] = {0.0, 0.0, 0.0};
@@ -171,8 +162,10 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
         fh[d] = a.fc_held[d * N + p];
       }
     }
-    if (old >= 0) a.count[(1 - par) * a.ncells + old] = 0;
-    if (c >= 0) {
+    if (g >= 0) {
+      const int half = g >= a.ncells ? 1 : 0;
+      const int c = g - (half ? (int)a.ncells : 0);
+      const int32_t* __restrict__ cnt = a.count + half * a.ncells;
       // pair cut-off squared: (2^(1/6) sigma)^2 (WCA) or (2^(7/6) sigma)^2
       const double rc2 = (m.force_model == 2 ? 1.2599210498948732 : 5.0396841995794928) *
                          m.wca_sigma * m.wca_sigma;
@@ -243,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs<T> a, CoupleArgs<T>
           for (int d = 0; d < 3; ++d) F[d] += fm * dx[side][d];
         }
       } else if (lane == 28) {
-        const int no = a.count[2 * a.ncells + par];
+        const int no = a.count[2 * a.ncells + half];
         const int rep = a.part_rep[p];
         for (int e = 0; e < no; ++e) {
           const int q = a.ovf[e];
@@ -293,7 +286,7 @@ int force_cell_capacity(const lbmd_params* p) {
 }
 
 template <typename T>
-static ForceArgs<T> force_args(Context* c, int pos_step) {
+static ForceArgs<T> force_args(Context* c) {
   const Layout& L = c->plan.lay;
   ForceArgs<T> a;
   a.x = (const double*)c->x;
@@ -302,15 +295,13 @@ static ForceArgs<T> force_args(Context* c, int pos_step) {
   a.fc_held = (const double*)at(c, L.fc_held);
   a.md = (const RepMD*)at(c, L.rep_md);
   a.part_rep = (const int32_t*)at(c, L.part_rep);
-  a.clock = (const Clock*)at(c, L.clock);
-  a.count = (int32_t*)at(c, L.bin_count);
-  a.bin = (int32_t*)at(c, L.bin_of);
+  a.count = (const int32_t*)at(c, L.bin_count);
+  a.bin = (const int32_t*)at(c, L.bin_of);
   a.slot = (const int32_t*)at(c, L.bin_slot);
   a.ovf = (const int32_t*)at(c, L.bin_ovf);
   a.N = c->plan.Ntot;
   a.ncells = c->plan.Ctot;
   a.cap = c->plan.cell_cap;
-  a.pos_step = pos_step;
   return a;
 }
 
@@ -334,8 +325,8 @@ static hipError_t launch_binning(Context* c, int pos_step) {
 }
 
 template <typename T, bool Kick, int AfterST>
-static hipError_t forces_t(Context* c, int pos_step, int substep = 0) {
-  const ForceArgs<T> a = force_args<T>(c, pos_step);
+static hipError_t forces_t(Context* c, int substep = 0) {
+  const ForceArgs<T> a = force_args<T>(c);
   const int64_t nfb = (a.N * kForceLanes + kBlock - 1) / kBlock;
   CoupleArgs<T> ca{};
   int64_t nseg = 0;
@@ -363,8 +354,7 @@ hipError_t launch_forces(Context* c) {
   if (c->plan.Ntot == 0) return hipSuccess;
   hipError_t e;
   if (c->plan.any_forces2 && (e = launch_binning(c, c->subs)) != hipSuccess) return e;
-  return c->plan.prec == 32 ? forces_t<float, false, -1>(c, c->subs)
-                            : forces_t<double, false, -1>(c, c->subs);
+  return c->plan.prec == 32 ? forces_t<float, false, -1>(c) : forces_t<double, false, -1>(c);
 }
 
 // Forces at the bound positions; the corner cache is stale from here on.
@@ -381,9 +371,9 @@ hipError_t launch_init_forces(Context* c) {
 // own).
 template <typename T>
 static hipError_t forces_and_kick_t(Context* c, int substep) {
-  if (c->rec_part) return forces_t<T, true, -1>(c, substep + 1, substep);
-  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c, substep + 1, substep)
-                              : forces_t<T, true, 0>(c, substep + 1, substep);
+  if (c->rec_part) return forces_t<T, true, -1>(c, substep);
+  return c->p[0].stencil == 1 ? forces_t<T, true, 1>(c, substep)
+                              : forces_t<T, true, 0>(c, substep);
 }
 
 hipError_t launch_forces_and_kick(Context* c, int substep) {

@@ -99,7 +99,8 @@ struct Layout {
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
   size_t bin_count;  // [2 Ctot + 2] int32: particles per force cell, two halves by MD-step
                      // parity, then the two overflow-list lengths (cell_insert)
-  size_t bin_of;     // [2][Ntot] int32: global force cell of each particle (-1: none)
+  size_t bin_of;     // [Ntot] int32: count entry of each particle's force cell,
+                     // half * Ctot + global cell (-1: none)
   size_t bin_slot;   // [Ctot][cell_cap] int32: particles of each cell
   size_t bin_ovf;    // [Ntot] int32: particles past their cell's capacity
   size_t sort_keys;  // [2][Ntot] uint64: spatial sort keys (in, out)
