@@ -380,6 +380,44 @@ def test_kremer_grest_coupled(lb, orc, prec, variant):
     check_particles(g, o, shape, TOL[prec] * 10, 0.01)
 
 
+@pytest.mark.parametrize("model", [2, 3])
+def test_polymer_counters_shifted(lb, orc, model):
+    """Step counters moved by an odd number of MD steps, in the middle of an
+    interval and at an LB step: the force cells, kept in two halves by the
+    parity of the MD step, are binned again, and the run matches the
+    oracle's with the same counters (which also move the noise; FP64)."""
+    shape = (20, 20, 20)
+    x, v = wl.chains(shape, 12, 10, 0.01, 1.0, seed=35, bond=0.97, min_dist=0.95)
+    kw = dict(kT=0.01, nu=0.3, seed=9, n_particles=120, friction=2.0, n_sub=5, variant=2,
+              force_model=model, chain_len=10, k_bond=0.3, r0_bond=1.0 if model == 2 else 1.5,
+              wca_eps=0.01, wca_sigma=1.0)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=64, **kw)
+    o = orc.Oracle(*shape, **kw)
+    g.bind_particles(x, v)
+    o.set_particles(x, v)
+
+    def shift(dlb, dmd):
+        cnt = g.counters()
+        args = (cnt["t_lb"] + dlb, cnt["t_md"] + dmd, cnt["subs"])
+        g.set_counters(*args)
+        o.set_counters(*args)
+
+    for cyc in range(3):
+        for s in range(5):
+            g.md_couple_substep()
+            assert o.md_couple_substep() == 0
+            if cyc == 1 and s == 1:
+                shift(3, 7)
+        g.lb_step()
+        o.lb_step()
+        if cyc == 0:
+            shift(1, 5)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < 1e-12, err
+    check_particles(g, o, shape, 1e-11, 0.01)
+
+
 def test_fene_overstretch_is_flagged(lb, orc):
     """A FENE bond stretched to R0 has no finite force: its beads become
     non-finite and the context reports ENONFINITE; the other chain stays
