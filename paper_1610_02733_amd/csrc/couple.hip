@@ -290,7 +290,12 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         const int k = k0 + jj * Sh::kLanes;
         if (k < St::kSites) {
           cv_[jj] = *cache_entry<ST>(a, p, k);
-          jv_[jj] = *own_entry<ST>(a, p, k);
+          // (Bin: position-dependent forces, so no own transfers are kept;
+          // every MD step takes the sharing and the transfer from J)
+          if constexpr (Bin)
+            jv_[jj] = Vec4<T>{T(0), T(0), T(0), T(0)};
+          else
+            jv_[jj] = *own_entry<ST>(a, p, k);
         }
       }
 #pragma unroll
@@ -456,14 +461,14 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       const T ax = (T)(-ww * dp[0]), ay = (T)(-ww * dp[1]), az = (T)(-ww * dp[2]);
       if (gs >= 0 && !sh_[jj]) {
         const Vec4<T> nv{jv_[jj].x + ax, jv_[jj].y + ay, jv_[jj].z + az, T(0)};
-        if (!a.final_step) *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = nv;
+        if (!Bin && !a.final_step) *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = nv;
         if (leave) a.J[gs] = nv;
       }
       if (gs >= 0 && sh_[jj]) {
         const int64_t e = seg * (kBlock * kPer) + atomicAdd(&s_l, 1);
         a.lsite[e] = gs;
         a.ldelta[e] = Vec4<T>{ax, ay, az, T(0)};
-        if (dec_[jj] && !a.final_step)
+        if (!Bin && dec_[jj] && !a.final_step)
           *own_entry<ST>(a, p, k0 + jj * Sh::kLanes) = Vec4<T>{T(0), T(0), T(0), T(1)};
       }
     }
