@@ -125,6 +125,8 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
     site_coords(q.g, act ? local : 0, x, y, z);
     T d[19];
     const bool rows = Mode == 2 ? q.rows != 0 : Mode == 1;
+    // general path: 32-bit offsets where the replica's entries allow (uniform)
+    const bool off32 = !rows && 19ull * (unsigned long long)q.g.S < (1ull << 32);
     if (rows) {
       // aligned loads at this lane's own x.  Offsets are 32-bit here (the
       // row path is taken only for replicas of fewer than 2^32 / 19 sites):
@@ -171,6 +173,27 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
         d[kFromRight[j]] = lane == 63 ? edge[par][1][wright][j] : r;
       }
       par ^= 1;
+    } else if (act && off32) {
+      // 32-bit offsets inside population i's slab, i A folded into the
+      // scalar base (the replica's 19 S entries fit 32 bits)
+      const uint32_t A = (uint32_t)q.g.A;
+      const int xm = x == 0 ? q.g.nx - 1 : x - 1, xp = x == q.g.nx - 1 ? 0 : x + 1;
+      const int ym = y == 0 ? q.g.ny - 1 : y - 1, yp = y == q.g.ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? q.g.nz - 1 : z - 1, zp = z == q.g.nz - 1 ? 0 : z + 1;
+      const uint32_t z0 = (uint32_t)z * 19u * A, zl = (uint32_t)zm * 19u * A,
+                     zh = (uint32_t)zp * 19u * A;
+      const uint32_t r0 = (uint32_t)(y * q.g.nx), rl = (uint32_t)(ym * q.g.nx),
+                     rh = (uint32_t)(yp * q.g.nx);
+      const uint32_t X0 = (uint32_t)x, Xl = (uint32_t)xm, Xh = (uint32_t)xp;
+      // source (plane, row, column) of each population: z - c_z, y - c_y, x - c_x
+      const uint32_t off[19] = {z0 + r0 + X0, z0 + r0 + Xl, z0 + r0 + Xh, z0 + rl + X0,
+                                z0 + rh + X0, zl + r0 + X0, zh + r0 + X0, z0 + rl + Xl,
+                                z0 + rh + Xh, z0 + rh + Xl, z0 + rl + Xh, zl + r0 + Xl,
+                                zh + r0 + Xh, zh + r0 + Xl, zl + r0 + Xh, zl + rl + X0,
+                                zh + rh + X0, zh + rl + X0, zl + rh + X0};
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        d[i] = __builtin_nontemporal_load(sbase + (size_t)i * A + off[i]);
     } else if (act) {
       size_t off[19];
       pull_offsets(q.g, x, y, z, off);
@@ -208,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_stream(StreamArgs<T> a) {
       // every population is written once per step: stream the stores past the
       // caches (non-temporal hint)
       T* __restrict__ o = dst + 19 * (size_t)q.site_off;
-      if (rows) {
+      if (rows || off32) {
         const uint32_t own = ((uint32_t)z * 19u) * (uint32_t)q.g.A + (uint32_t)(y * q.g.nx + x);
 #pragma unroll
         for (int i = 0; i < 19; ++i)
