@@ -270,9 +270,12 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     uint32_t lp = 0;
     Vec4<T> cv_[kPer];
     int old_bin = -1;  // Bin: the particle's count entry of the previous binning
+    int rep_p = 0;     // the particle's replica (several replicas)
+    RepMD mr;
     bool live = t < lanes;
     if (live) {
       if (Bin && k0 == 0) old_bin = a.bin[p];
+      if constexpr (!One) rep_p = a.part_rep[p];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         X[d] = a.x[d * N + p];
@@ -298,6 +301,8 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
             jv_[jj] = *own_entry<ST>(a, p, k);
         }
       }
+      // the replica's constants as soon as its index is in (several replicas)
+      if constexpr (!One) mr = a.md[rep_p];
 #pragma unroll
       for (int d = 0; d < 3; ++d) live = live && isfinite(X[d]) && isfinite(V[d]);
       if (!live && k0 == 0) {
@@ -310,8 +315,6 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
       }
     }
     if (live) {
-      RepMD mr;
-      if constexpr (!One) mr = a.md[a.part_rep[p]];
       const RepMD& m = One ? m1 : mr;
       Cube q;
       St::locate(X, m.g, q);
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
     // every particle's stencil: moved particles need no after-step work)
     if (moved && k0 == 0 && !a.final_step)
       reinterpret_cast<int4*>(a.mlist)[seg * (kBlock / L) + atomicAdd(&s_m, 1)] =
-          make_int4((int)p, new_cell, old_cell, 0);
+          make_int4((int)p, new_cell, old_cell, rep_p);
     __syncthreads();
     if (threadIdx.x == 0) {
       a.lseg[seg] = s_l;

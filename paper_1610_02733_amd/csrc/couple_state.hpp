@@ -41,7 +41,7 @@ struct CoupleArgs {
   int32_t* __restrict__ lseg;    //   entries in the segment
   int32_t* __restrict__ mlist;   // particles whose stencil moved in the MD step (int4:
                                  //   slot, replica-local indices of the new and old
-                                 //   stencil bases, -),
+                                 //   stencil bases, replica),
   int32_t* __restrict__ mseg;    //   their number in the segment
   // force cells (position-dependent forces): the coupling kernel bins the
   // particles at their new positions for the force kernel (cell_insert)
@@ -368,10 +368,11 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
   for (int u = threadIdx.x; u < nm; u += kBlock) {
     const int k = u % St::kLanes;
     if (k >= St::kSites) continue;
-    // (particle, replica-local indices of its new and old stencil bases)
+    // (particle, replica-local indices of its new and old stencil bases,
+    // replica)
     const int4 ent = ml[u / St::kLanes];
     const int64_t p = ent.x;
-    const RepMD& m = One ? m1 : a.md[a.single ? 0 : a.part_rep[p]];
+    const RepMD& m = One ? m1 : a.md[a.single ? 0 : ent.w];
     Cube q;
     q.base[0] = ent.y % m.g.nx;
     q.base[1] = (ent.y / m.g.nx) % m.g.ny;
@@ -405,7 +406,7 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     // launch, after this claim
     *own_entry<ST>(a, p, k) = Vec4<T>{T(0), T(0), T(0), T(2)};
     if (claim_site(a, m.site_off + site) && own_on && !was_mine) {
-      const int rep = a.single ? 0 : a.part_rep[p];
+      const int rep = a.single ? 0 : ent.w;
       if (ST == 0)
         owner_of_shared<T, ST>(a, m, rep, m.site_off + site, p, recs);
       else

@@ -95,7 +95,7 @@ struct Layout {
   size_t moved_at;   // [Ntot] int64: MD step of each particle's last stencil change
   size_t slist_site;  // [sites per stencil * Ntot] int32: shared-site transfers of an MD step
   size_t slist_delta; // [sites per stencil * Ntot] Vec4<T>: their momenta
-  size_t mlist;      // [segments * kBlock / lanes] int4: particles whose stencil moved, new and old base
+  size_t mlist;      // [segments * kBlock / lanes] int4: particles whose stencil moved, new and old base, replica
   size_t seg_count;  // [2][segments] int32: entries per segment of the two lists
   size_t bin_count;  // [2 Ctot + 2] int32: particles per force cell, two halves by MD-step
                      // parity, then the two overflow-list lengths (cell_insert)
