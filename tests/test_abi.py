@@ -74,3 +74,26 @@ def test_host_side_validation_of_models_and_batches():
         arr[1] = lbmd.make_params((12, 10, 8), **dict(dict(n_sub=2), **{key: val}))
         assert L.lbmd_batch_workspace_bytes(arr, 2) == 0, key
     assert L.lbmd_batch_workspace_bytes(arr, 0) == 0
+
+
+def test_force_cell_workspace():
+    """Force cells on the host: floor(L / cut-off) cells per axis (cut-off
+    2^(1/6) sigma for WCA, 2^(7/6) sigma for the Kremer-Grest model), each with
+    two count halves and 8 (WCA) or 32 (Kremer-Grest) particle slots of 4
+    bytes: the workspace grows by exactly that over force model 0."""
+    import math
+    from paper_1610_02733_amd import lbmd
+    L = lbmd.lib()
+
+    def ws(model):
+        p = lbmd.make_params((64, 64, 64), n_particles=100, chain_len=10, force_model=model,
+                             k_bond=0.3, r0_bond=1.5, wca_eps=0.01, wca_sigma=1.0)
+        return L.lbmd_workspace_bytes(ctypes.byref(p))
+
+    def up(a):  # 256-byte alignment of each workspace region
+        return (a + 255) // 256 * 256
+
+    base = ws(0)
+    for model, rc, cap in ((2, 2.0 ** (1 / 6), 8), (3, 2.0 ** (7 / 6), 32)):
+        C = math.floor(64 / rc) ** 3
+        assert ws(model) - base == up((2 * C + 2) * 4) - up(4 * 4) + up(C * cap * 4), model
