@@ -240,7 +240,14 @@ int lbmd_set_populations(lbmd *c, const void *d_src);
  * [3][nsites] in the context precision. */
 int lbmd_get_transfer(lbmd *c, void *d_dst);
 
-/* Step counters: LB steps, MD steps, MD steps since the last LB step. */
+/* Step counters: LB steps, MD steps, MD steps since the last LB step.
+ * Set: the noise streams and the step clock of captured cycles follow the
+ * new counts; the particles' transfers kept to themselves go to J first, the
+ * corner cache is rebuilt at the next MD step, and with position-dependent
+ * forces (models 2, 3) the bound particles are binned into their force
+ * cells again and F_cons is recomputed at the current positions (the cells
+ * are kept by MD-step parity).  EINVAL for t_lb < 0, subs outside
+ * [0, n_sub] or t_md < subs. */
 int lbmd_get_counters(lbmd *c, int64_t *t_lb, int64_t *t_md, int32_t *subs);
 int lbmd_set_counters(lbmd *c, int64_t t_lb, int64_t t_md, int32_t subs);
 
