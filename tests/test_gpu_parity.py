@@ -814,6 +814,31 @@ def test_launch_shapes_match_oracle(lb, orc, prec, stencil, lanes, blocks):
     check_particles(g, o, shape, TOL[prec], 1e-3)
 
 
+@pytest.mark.parametrize("stencil,blocks", [(0, 0), (0, 13), (1, 13)])
+def test_general_path_item_order(lb, orc, stencil, blocks):
+    """A lattice off the collide-stream row path (40 x 30 x 20: 94 work items)
+    takes its items in XCD-contiguous ranges, and the three-point refill its
+    particle blocks likewise: one block per item, and persistent grids whose
+    size is not a multiple of the 8 XCDs (13 blocks), match the oracle (FP64)."""
+    shape = (40, 30, 20)
+    N = 200
+    x, v = wl.free_particles(shape, N, 1e-3, 1.0, 81)
+    kw = dict(kT=1e-3, seed=82, n_particles=N, friction=0.8, n_sub=3, variant=2,
+              stencil=stencil)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=64, **kw)
+    g.set_launch_shape(lb_blocks=blocks, part_blocks=blocks)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    g.cycle(2)
+    g.run_cycles(2)
+    o.cycle(4)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < TOL[64], err
+    check_particles(g, o, shape, TOL[64], 1e-3)
+
+
 def test_launch_shape_rejects_bad_lanes(lb):
     g = lb.Lattice((8, 8, 8), precision=32, n_particles=4)
     for bad in (3, 16, 32):
