@@ -418,6 +418,28 @@ def test_polymer_counters_shifted(lb, orc, model):
     check_particles(g, o, shape, 1e-11, 0.01)
 
 
+def test_polymer_graph_replay_odd_steps(lb, orc):
+    """Kremer-Grest chains run as replays of one captured cycle of an odd
+    number of MD steps (n = 5): the half of the force-cell counts that an MD
+    step bins into alternates from one replay to the next, taken from the
+    device step clock; the run matches the oracle's (FP64)."""
+    shape = (20, 20, 20)
+    x, v = wl.chains(shape, 12, 10, 0.01, 1.0, seed=37, bond=0.97, min_dist=0.95)
+    kw = dict(kT=0.01, nu=0.3, seed=9, n_particles=120, friction=2.0, n_sub=5, variant=2,
+              force_model=3, chain_len=10, k_bond=0.3, r0_bond=1.5, wca_eps=0.01,
+              wca_sigma=1.0)
+    c, w, e, b = orc.tables()
+    g = lb.Lattice(shape, precision=64, **kw)
+    g.bind_particles(x, v)
+    o = orc.Oracle(*shape, **kw)
+    o.set_particles(x, v)
+    g.run_cycles(5)
+    o.cycle(5)
+    err = pop_err(g.populations().cpu().numpy(), o.populations(), w, 1.0)
+    assert err < 1e-12, err
+    check_particles(g, o, shape, 1e-11, 0.01)
+
+
 def test_fene_overstretch_is_flagged(lb, orc):
     """A FENE bond stretched to R0 has no finite force: its beads become
     non-finite and the context reports ENONFINITE; the other chain stays
