@@ -354,8 +354,13 @@ __device__ __forceinline__ void reduce_segment_transfers(const CoupleArgs<T>& a,
 // Own: own transfers in use (CoupleArgs::own_on; the standalone after-step
 // launch always, the force kernel's extra blocks never), so that the force
 // kernel carries none of the holder lookup's registers.
-// ent0: this thread's entry of its first pass, loaded with the count (the
-// cube only, see after_step_item).
+// Whether an after-step item loads its count together with the thread's
+// first entry (after_step_item): the cube's standalone launch only.
+template <int ST, bool Own>
+constexpr bool kAfterStepPrefetch = ST == 0 && Own;
+
+// ent0: this thread's entry of its first pass, loaded with the count when
+// kAfterStepPrefetch (see after_step_item).
 template <typename T, int ST, bool One, bool Own>
 __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_t seg, int nmv,
                                                   int L, const int4& ent0) {
@@ -372,7 +377,7 @@ __device__ __forceinline__ void after_step_movers(const CoupleArgs<T>& a, int64_
     if (k >= St::kSites) continue;
     // (particle, replica-local indices of its new and old stencil bases,
     // replica)
-    const int4 ent = ST == 0 && u < kBlock ? ent0 : ml[u / St::kLanes];
+    const int4 ent = kAfterStepPrefetch<ST, Own> && u < kBlock ? ent0 : ml[u / St::kLanes];
     const int64_t p = ent.x;
     const RepMD& m = One ? m1 : a.md[a.single ? 0 : ent.w];
     Cube q;
@@ -459,8 +464,10 @@ __device__ __forceinline__ void after_step_item(const CoupleArgs<T>& a, int64_t 
   // whatever the count (a mover region holds kBlock / L entries with L at
   // most the cube's 8 lanes, a transfer region kBlock * per), and one past
   // the count is stale and left unused.  The three-point stencil's items do
-  // without: the registers held across its table's set-up cost more.
-  constexpr bool kPre = ST == 0;
+  // without: the registers held across its table's set-up cost more; so do
+  // the force kernel's extra blocks (Own false), whose registers the force
+  // lanes share (14.2 against 16.8 us per MD step on the 128^3 polymer).
+  constexpr bool kPre = kAfterStepPrefetch<ST, Own>;
   if (it < nseg) {
     int4 ent0 = make_int4(0, 0, 0, 0);
     if constexpr (kPre)
