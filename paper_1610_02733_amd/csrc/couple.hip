@@ -221,7 +221,9 @@ struct CoupleShape {
   }
 };
 
-template <typename T, bool Rec, int ST, int L, bool Bin, bool One>
+// Retag: the launch takes every site's sharing from J (the first MD step
+// after a refill), so the own-transfer entries are written but not read.
+template <typename T, bool Rec, int ST, int L, bool Bin, bool One, bool Retag = false>
 __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
   using St = Stencil<ST>;
   using Sh = CoupleShape<L>;
@@ -294,8 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_couple(CoupleArgs<T> a) {
         if (k < St::kSites) {
           cv_[jj] = *cache_entry<ST>(a, p, k);
           // (Bin: position-dependent forces, so no own transfers are kept;
-          // every MD step takes the sharing and the transfer from J)
-          if constexpr (Bin)
+          // every MD step takes the sharing and the transfer from J; Retag:
+          // this step does)
+          if constexpr (Bin || Retag)
             jv_[jj] = Vec4<T>{T(0), T(0), T(0), T(0)};
           else
             jv_[jj] = *own_entry<ST>(a, p, k);
@@ -541,9 +544,15 @@ static void launch_couple_lanes(Context* c, const CoupleArgs<T>& a, bool bin, di
   else if (bin)
     hipLaunchKernelGGL((k_couple<T, false, ST, L, true, false>), grid, dim3(kBlock), 0, c->stream,
                        a);
+  else if (a.single && a.retag)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, false, true, true>), grid, dim3(kBlock), 0,
+                       c->stream, a);
   else if (a.single)
     hipLaunchKernelGGL((k_couple<T, false, ST, L, false, true>), grid, dim3(kBlock), 0, c->stream,
                        a);
+  else if (a.retag)
+    hipLaunchKernelGGL((k_couple<T, false, ST, L, false, false, true>), grid, dim3(kBlock), 0,
+                       c->stream, a);
   else
     hipLaunchKernelGGL((k_couple<T, false, ST, L, false, false>), grid, dim3(kBlock), 0, c->stream,
                        a);
